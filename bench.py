@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X MRRR tridiagonal eigensolver (FP64, one GPU).
+
+Step = one pass of the whole solver over one batch of synthetic input: the full
+spectrum (all eigenvalues and eigenvectors) of three order-20000 tridiagonals --
+random U(-1,1) entries (seed 2001), the "1-2-1" Toeplitz matrix, and a spectrum
+geometrically spaced in [1e-8, 1] (seed 2003).  Metric: FP64 eigenpairs per
+second (60000 eigenpairs per step), inputs resident in HBM, outputs
+preallocated by the caching allocator, stream synchronized around the timed
+region.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's achieved rate from HIP events recorded by
+                the library on the launch stream over the timed region
+                (algorithmic work / event time) against the MI355X peak
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the workload
+  batched       solves/s of the batched entry point on 4096 mixed problems (sizes
+                log-uniform in [32, 2048]) and of a loop of single-problem calls
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+PEAK_FP64_MATRIX_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(n):
+    from paper_1205_2107_amd import workloads as W
+    return [("random", *W.random_uniform(n, W.SEEDS["c2_random"])),
+            ("toeplitz_121", *W.toeplitz(n)),
+            ("geometric_1e-8", *W.geometric(n, W.SEEDS["c2_geometric"]))]
+
+
+def cpu_baseline(n):
+    """Oracle (single-threaded C, as it stands) on a bounded sample: the 600
+    smallest eigenpairs of the random n = 20000 matrix."""
+    import oracle
+    from paper_1205_2107_amd import workloads as W
+    d, e = W.random_uniform(n, W.SEEDS["c2_random"])
+    k = 600
+    t0 = time.perf_counter()
+    w, Z, st = oracle.mrrr(d, e, kind=oracle.RANGE_INDEX, il=1, iu=k)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"random n={n} (seed 2001), eigenpairs 1..{k} (il..iu), {dt:.1f} s on 1 host thread"}
+
+
+def roofline(prof):
+    """dominant kernel by event time; ALU-bound kernels against the FP64 vector
+    peak, the eigenvector kernel against HBM bandwidth"""
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    p = prof[name]
+    out = {"kernel": name, "launches": p["launches"], "avg_ms": p["ms"] / max(p["launches"], 1), "traffic": None}
+    if name == "vectors":
+        ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS})
+    else:
+        ach = p["work"] / (p["ms"] * 1e-3) / 1e12
+        out.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / PEAK_FP64_VECTOR_TFLOPS})
+    return out
+
+
+def batched_leg(torch, M, count, loop_count):
+    from paper_1205_2107_amd import workloads as W
+    probs = W.batched_mix(count, W.SEEDS["c4"])
+    d, e, ns, off = W.pack(probs)
+    dt = torch.tensor(d, device="cuda")
+    et = torch.tensor(e, device="cuda")
+    M.eigh_tridiagonal_batched(dt, et, ns)  # warm-up (workspace growth)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        M.eigh_tridiagonal_batched(dt, et, ns)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    # loop of single-problem calls over the first loop_count problems of the same mix
+    singles = [(torch.tensor(p[0], device="cuda"), torch.tensor(p[1], device="cuda")) for p in probs[:loop_count]]
+    for a, b in singles[:8]:
+        M.eigh_tridiagonal(a, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in singles:
+        M.eigh_tridiagonal(a, b)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    return {"problems": count, "sum_n": int(ns.sum()), "seconds": tb, "solves_per_s": count / tb,
+            "looped_problems": loop_count, "looped_solves_per_s": loop_count / tl,
+            "speedup_vs_looped": (count / tb) / (loop_count / tl)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=4096)
+    ap.add_argument("--looped-count", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1205_2107_amd as M
+    if not torch.cuda.is_available():
+        print("bench.py: no ROCm GPU visible", file=sys.stderr)
+        sys.exit(1)
+    n = args.n
+    log(f"[bench] generating inputs n={n}")
+    inputs = make_inputs(n)
+    dev = [(name, torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda")) for name, d, e in inputs]
+    torch.cuda.synchronize()
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        for name, d, e in dev:
+            M.eigh_tridiagonal(d, e)
+    torch.cuda.synchronize()
+    M.profile(True)
+    per_type = {name: 0.0 for name, _, _ in dev}
+    infos = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for name, d, e in dev:
+            ts = time.perf_counter()
+            w, Z, info = M.eigh_tridiagonal(d, e, return_info=True)
+            per_type[name] += time.perf_counter() - ts
+            infos[name] = info
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = M.profile_read()
+    M.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs_per_step = n * len(dev)
+    value = pairs_per_step / (ms_per_step * 1e-3)
+    out = {
+        "metric": "FP64 eigenpairs/s at n=20k full spectrum (random, 1-2-1, geometric types)",
+        "value": value,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"STEP full spectrum, three tridiagonals of order {n} per step",
+                   "n": n, "types": [name for name, _, _ in dev],
+                   "ms_per_type": {k: v * 1e3 / args.steps for k, v in per_type.items()},
+                   "tree": {k: {"levels": v["levels"], "nodes": v["nodes"], "max_depth": v["max_depth"]}
+                            for k, v in infos.items()}},
+        "roofline": roofline(prof),
+        "kernels": {k: {"ms_per_step": v["ms"] / args.steps, "launches": v["launches"],
+                        "tflops": (v["work"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
+                    for k, v in prof.items()},
+    }
+    if not args.no_batched:
+        log("[bench] batched leg")
+        out["batched"] = batched_leg(torch, M, args.batched_count, args.looped_count)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * mrrr.h -- C ABI of the MI355X (gfx950) MRRR symmetric tridiagonal eigensolver.
+ *
+ * The problem (Petschow, Peise, Bientinesi, arXiv:1205.2107, Sec. 1.1 and Stage 4
+ * of Sec. 1.2): for a real symmetric tridiagonal T of order n with diagonal d and
+ * off-diagonal e, compute eigenpairs (lambda_j, z_j), T z_j = lambda_j z_j, with
+ * orthonormal z_j -- all of them, or the subset selected by index or by value
+ * (the MRRR cost is O(n k) for k eigenpairs, Sec. 2.3).  The method is MRRR
+ * (Sec. 3.1, 3.1.1): root representation, bisection, relative-gap
+ * classification, twisted factorizations for singletons, child representations
+ * for clusters.  Accuracy contract (Sec. 2.3, Eq. Tresnorm, Eq. Torthogo):
+ * residuals O(n eps ||T||), orthogonality O(n eps).
+ *
+ * Conventions shared by every entry point:
+ *  - All array pointers are DEVICE pointers (hipMalloc'ed or equivalent) owned by
+ *    the caller; the library never frees them.  d and e are only read.
+ *  - Matrices are column-major with a leading dimension (ld >= number of rows).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *    work is ordered on it.  The representation tree is driven level by level
+ *    from the host, so every solve entry point synchronizes `stream` before it
+ *    returns; outputs are complete on return.
+ *  - The library keeps a per-device workspace that grows with hipMalloc when a
+ *    call needs more than the previous calls did (mrrr_release frees it).  Calls
+ *    from several host threads on the same device are serialized internally.
+ *  - Return value: 0 success; negative -k: argument k (1-based) is invalid,
+ *    checked on the host before any device work; positive: a status code below.
+ *    mrrr_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef MRRR_H
+#define MRRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes (positive return values and mrrr_info.status) */
+#define MRRR_OK 0
+#define MRRR_ERR_NO_RRR 1      /* no child representation with finite entries */
+#define MRRR_ERR_DEPTH 2       /* representation tree deeper than 64 levels */
+#define MRRR_ERR_CAPACITY 3    /* workspace limit reached (MRRR_MAX_WORKSPACE_GB) */
+#define MRRR_ERR_NONFINITE 4   /* d or e holds inf or NaN */
+#define MRRR_ERR_HIP 5         /* a HIP runtime call failed (see mrrr_last_error) */
+#define MRRR_ERR_NO_DEVICE 6   /* no usable gfx950 device / kernel image */
+
+/* Which eigenpairs: all; indices il..iu (1-based, inclusive, of the ascending
+ * spectrum); or values in (vl, vu] as decided by Sturm counts at vl and vu. */
+typedef enum { MRRR_ALL = 0, MRRR_INDEX = 1, MRRR_VALUE = 2 } mrrr_range_kind;
+
+typedef struct {
+  int32_t kind; /* mrrr_range_kind */
+  int32_t reserved;
+  int64_t il, iu;
+  double vl, vu;
+} mrrr_range;
+
+/* Per-call report, written to HOST memory.  counters: see MRRR_CNT_*. */
+typedef struct {
+  int64_t m;          /* number of eigenpairs returned */
+  int32_t status;     /* MRRR_OK or a status code */
+  int32_t max_depth;  /* deepest representation-tree level reached */
+  int64_t counters[16];
+} mrrr_info;
+
+#define MRRR_CNT_BLOCKS 0        /* unreduced blocks after splitting */
+#define MRRR_CNT_NODES 1         /* child representations built */
+#define MRRR_CNT_LEVELS 2        /* tree levels processed */
+#define MRRR_CNT_STURM_STEPS 3   /* Sturm-count row steps executed (bisection + Newton) */
+#define MRRR_CNT_QDS_STEPS 4     /* row steps of twisted factorizations and child builds */
+#define MRRR_CNT_SINGLETONS 5    /* eigenvectors computed */
+#define MRRR_CNT_RQI 6           /* twisted factorizations executed */
+#define MRRR_CNT_FALLBACKS 7     /* singletons that needed the bisection fallback */
+#define MRRR_CNT_CHILD_REJECT 8  /* clusters whose child failed the growth bound */
+#define MRRR_CNT_WORKSPACE_MB 9  /* device workspace in use after the call */
+
+/*
+ * mrrr_step -- eigenpairs of one tridiagonal (Stage 4, STEP).
+ *   n      order of T (n >= 0)                                         [arg 1]
+ *   d      device, n doubles: diagonal                                  [arg 2]
+ *   e      device, n-1 doubles: off-diagonal (may be NULL when n <= 1)   [arg 3]
+ *   range  MRRR_ALL; MRRR_INDEX with 1 <= il <= iu <= n; MRRR_VALUE with vl < vu [arg 4]
+ *   w      device, room for m doubles: eigenvalues, ascending            [arg 5]
+ *   Z      device, ldz x m column-major (m = n for ALL, iu-il+1 for INDEX,
+ *          at most n for VALUE): column j pairs with w[j]; rows outside the
+ *          eigenvector's unreduced block are exact zeros; largest-magnitude
+ *          entry of each column positive. Z may be NULL: eigenvalues only.  [arg 6]
+ *   ldz    leading dimension of Z, >= max(1, n)                         [arg 7]
+ *   info   host, may be NULL: m, status and counters                    [arg 8]
+ *   stream hipStream_t as void*                                         [arg 9]
+ * Blocks are split where |e_i| <= eps ||T||_1 (footnote of Sec. 3.1.1).
+ */
+int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
+              int64_t ldz, mrrr_info* info, void* stream);
+
+/*
+ * mrrr_step_batched -- all eigenpairs of `batch` independent tridiagonals in one
+ * pass of the solver (every level of every problem's representation tree is
+ * processed by the same kernel launches).
+ *   batch        number of problems (>= 0)                                [arg 1]
+ *   n_host       HOST, batch int64: orders n_b >= 1                         [arg 2]
+ *   off_host     HOST, batch int64: offset of problem b in d, e and w       [arg 3]
+ *   d, e         device: d[off_b + i], i < n_b; e[off_b + i], i < n_b - 1    [args 4, 5]
+ *   w            device: eigenvalues of problem b at w[off_b ...], ascending [arg 6]
+ *   Z            device: problem b's n_b x n_b eigenvectors at Z + zoff_b,
+ *                column-major with leading dimension n_b                    [arg 7]
+ *   zoff_host    HOST, batch int64: offsets of the Z blocks                 [arg 8]
+ *   info         host, may be NULL: batch entries                          [arg 9]
+ *   stream                                                                   [arg 10]
+ * Problems must not overlap in d/e/w/Z.
+ */
+int mrrr_step_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host, const double* d,
+                      const double* e, double* w, double* Z, const int64_t* zoff_host, mrrr_info* info,
+                      void* stream);
+
+/*
+ * mrrr_step_backward -- reverse-mode derivative of the decomposition.
+ * Given eigenvalues w (n), orthonormal eigenvectors Z (n x n, ldz) of T and the
+ * cotangents gw = dL/dw (n, may be NULL) and gZ = dL/dZ (n x n, ldgz, may be
+ * NULL), writes gd = dL/dd (n) and ge = dL/de (n-1):
+ *   M = diag(gw) + F o (Z^T gZ),  F_ik = 1/(w_k - w_i) (i != k), F_kk = 0,
+ *   A = Z M Z^T,  gd_i = A_ii,  ge_i = A_{i,i+1} + A_{i+1,i}.
+ * Requires distinct eigenvalues (F is unbounded at multiple eigenvalues).
+ * Uses FP64 matrix cores for the two dense contractions; A is never stored.
+ *   args: n [1], w [2], Z [3], ldz [4], gw [5], gZ [6], ldgz [7], gd [8], ge [9], stream [10]
+ */
+int mrrr_step_backward(int64_t n, const double* w, const double* Z, int64_t ldz, const double* gw,
+                       const double* gZ, int64_t ldgz, double* gd, double* ge, void* stream);
+
+/*
+ * mrrr_step_backward_batched -- the backward for `batch` problems with the
+ * layout of mrrr_step_batched (Z_b and gZ_b at zoff_b with leading dimension n_b;
+ * w_b, gw_b, gd_b, ge_b at off_b).  gw or gZ may be NULL.
+ *   args: batch [1], n_host [2], off_host [3], zoff_host [4], w [5], Z [6], gw [7], gZ [8],
+ *         gd [9], ge [10], stream [11]
+ */
+int mrrr_step_backward_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host,
+                               const int64_t* zoff_host, const double* w, const double* Z, const double* gw,
+                               const double* gZ, double* gd, double* ge, void* stream);
+
+/* Launch-shape parameters of the solver (the batched autotuner sets these). */
+typedef struct {
+  int32_t grid_density;    /* Sturm-count grid points per eigenvalue for the initial brackets (1..16) */
+  int32_t refine_wave_slots; /* eigenvalues per wavefront in refinement (16, 32 or 64) */
+  int32_t vec_wave_slots;  /* eigenvectors per wavefront (16, 32 or 64) */
+  int32_t reserved[5];
+} mrrr_tuning;
+
+int mrrr_get_tuning(mrrr_tuning* t);
+int mrrr_set_tuning(const mrrr_tuning* t); /* -1 on out-of-range fields */
+
+/* Kernel timing.  While enabled, the solve entry points record HIP events on
+ * the caller's stream around every launch of their main kernels and accumulate
+ * the elapsed times and the algorithmic work of those launches:
+ *   MRRR_K_GRID     Sturm-count grid        work = 4 flops per row step
+ *   MRRR_K_REFINE   bisection/Newton        work = 4 flops per row step
+ *   MRRR_K_CHILD    child representations   work = 5 flops per row step
+ *   MRRR_K_VECTORS  twisted factorizations  work = 15 flops per row per
+ *                   iteration; bytes = 8 per eigenvector entry written
+ *   MRRR_K_BACKWARD both backward GEMMs     work = 2 n^3 flops each
+ * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
+#define MRRR_K_GRID 0
+#define MRRR_K_REFINE 1
+#define MRRR_K_CHILD 2
+#define MRRR_K_VECTORS 3
+#define MRRR_K_BACKWARD 4
+#define MRRR_K_COUNT 5
+
+typedef struct {
+  int64_t launches;
+  double ms;
+  double work;   /* algorithmic flops */
+  double bytes;  /* algorithmic HBM bytes */
+} mrrr_kernel_time;
+
+int mrrr_profile_enable(int on);
+int mrrr_profile_reset(void);
+int mrrr_profile_read(int kernel, mrrr_kernel_time* out); /* -1 on a bad kernel id */
+
+/* Free the calling device's workspace (the next call allocates again). */
+int mrrr_release(void);
+
+/* Message for the calling thread's last non-zero return. */
+const char* mrrr_last_error(void);
+
+/* Message for a status code. */
+const char* mrrr_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRRR_H */

@@ -1,0 +1,256 @@
+"""MI355X-native MRRR solver for the real symmetric tridiagonal eigenproblem.
+
+Thin PyTorch binding of the C ABI in ``include/mrrr.h``: torch supplies device
+memory and the stream; every step of the solver runs in the HIP kernels of
+``libmrrr.so`` (gfx950, FP64).  Nothing here computes eigen-arithmetic.
+
+    w, Z = eigh_tridiagonal(d, e)                      # all eigenpairs
+    w, Z = eigh_tridiagonal(d, e, select="i", il=1, iu=100)
+    w, Z = eigh_tridiagonal(d, e, select="v", vl=-1.0, vu=1.0)
+    w, Z, zoff = eigh_tridiagonal_batched(d, e, sizes)  # packed problems
+    w, Z = MRRRFunction.apply(d, e)                    # differentiable
+"""
+import ctypes
+
+from . import _lib
+from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
+
+__all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "eigh_tridiagonal_backward",
+           "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
+           "profile_read", "release"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_dev(x, device=None):
+    torch = _torch()
+    if not torch.is_tensor(x):
+        x = torch.as_tensor(x, dtype=torch.float64)
+    if device is None:
+        device = x.device if x.is_cuda else torch.device("cuda")
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def eigh_tridiagonal(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigvals_only=False,
+                     stream=None, return_info=False):
+    """Eigenpairs of the symmetric tridiagonal matrix (diagonal d, off-diagonal e).
+
+    select: "a" all, "i" indices il..iu (1-based, inclusive), "v" values in (vl, vu].
+    Returns w (ascending, float64, on the GPU) and Z (n x m column-major view:
+    a tensor of shape (n, m) whose columns are the eigenvectors), plus the info
+    dict when return_info is set.
+    """
+    torch = _torch()
+    lib = _lib.load()
+    d = _as_dev(d)
+    n = d.numel()
+    e = _as_dev(e, d.device) if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+    rng = MrrrRange()
+    if select == "a":
+        rng.kind = _lib.MRRR_ALL
+        m = n
+    elif select == "i":
+        rng.kind = _lib.MRRR_INDEX
+        rng.il, rng.iu = int(il), int(iu)
+        m = max(0, int(iu) - int(il) + 1)
+    elif select == "v":
+        rng.kind = _lib.MRRR_VALUE
+        rng.vl, rng.vu = float(vl), float(vu)
+        m = n
+    else:
+        raise ValueError("select must be 'a', 'i' or 'v'")
+    w = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    Zbuf = None if eigvals_only else torch.empty((max(m, 1), max(n, 1)), dtype=torch.float64, device=d.device)
+    info = MrrrInfo()
+    rc = lib.mrrr_step(n, _ptr(d), _ptr(e), rng, _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(info),
+                       _stream_ptr(stream))
+    _lib.check(rc)
+    mm = int(info.m) if n > 0 else 0
+    w = w[:mm]
+    Z = None if Zbuf is None else Zbuf[:mm, :n].t()
+    out = (w, Z)
+    if return_info:
+        out = out + (info.as_dict(),)
+    return out
+
+
+def eigh_tridiagonal_batched(d, e, sizes, eigvals_only=False, stream=None, return_info=False):
+    """All eigenpairs of len(sizes) independent tridiagonals packed back to back:
+    problem b owns d[off_b : off_b + n_b] and e[off_b : off_b + n_b - 1] (e has one
+    unused entry per problem).  Returns (w, Z, zoff): w packed like d, Z a flat
+    buffer with problem b's n_b x n_b column-major block at zoff[b]."""
+    torch = _torch()
+    lib = _lib.load()
+    d = _as_dev(d)
+    e = _as_dev(e, d.device)
+    sizes = [int(x) for x in sizes]
+    B = len(sizes)
+    n_arr = (ctypes.c_int64 * max(B, 1))(*sizes)
+    offs = [0] * B
+    zoffs = [0] * B
+    acc = zacc = 0
+    for b, nb in enumerate(sizes):
+        offs[b] = acc
+        zoffs[b] = zacc
+        acc += nb
+        zacc += nb * nb
+    off_arr = (ctypes.c_int64 * max(B, 1))(*offs)
+    zoff_arr = (ctypes.c_int64 * max(B, 1))(*zoffs)
+    w = torch.empty(max(acc, 1), dtype=torch.float64, device=d.device)
+    Z = None if eigvals_only else torch.empty(max(zacc, 1), dtype=torch.float64, device=d.device)
+    infos = (MrrrInfo * max(B, 1))()
+    rc = lib.mrrr_step_batched(B, n_arr, off_arr, _ptr(d), _ptr(e), _ptr(w), _ptr(Z), zoff_arr, infos,
+                               _stream_ptr(stream))
+    _lib.check(rc)
+    out = (w[:acc], Z, zoffs)
+    if return_info:
+        out = out + ([infos[b].as_dict() for b in range(B)],)
+    return out
+
+
+def _colmajor(X, n):
+    """Square n x n tensor -> buffer whose column j is contiguous (ld = n)."""
+    X = X.to(dtype=_torch().float64)
+    return X.t().contiguous()  # row j of the result is column j of X
+
+
+def eigh_tridiagonal_backward(w, Z, gw=None, gZ=None, stream=None):
+    """(grad_d, grad_e) of a loss with cotangents gw (eigenvalues) and gZ
+    (eigenvectors, n x n) for the full decomposition (w, Z)."""
+    torch = _torch()
+    lib = _lib.load()
+    w = _as_dev(w)
+    n = w.numel()
+    V = _colmajor(Z.to(w.device), n)
+    G = _colmajor(gZ.to(w.device), n) if gZ is not None else None
+    gwt = _as_dev(gw, w.device) if gw is not None else None
+    gd = torch.empty(max(n, 1), dtype=torch.float64, device=w.device)
+    ge = torch.empty(max(n, 1), dtype=torch.float64, device=w.device)
+    ld = max(n, 1)
+    rc = lib.mrrr_step_backward(n, _ptr(w), _ptr(V), ld, _ptr(gwt), _ptr(G), ld, _ptr(gd), _ptr(ge),
+                                _stream_ptr(stream))
+    _lib.check(rc)
+    return gd[:n], ge[:max(n - 1, 0)]
+
+
+def eigh_tridiagonal_backward_batched(w, Z, sizes, gw=None, gZ=None, stream=None):
+    """Backward for the packed layout of eigh_tridiagonal_batched."""
+    torch = _torch()
+    lib = _lib.load()
+    sizes = [int(x) for x in sizes]
+    B = len(sizes)
+    offs, zoffs = [], []
+    acc = zacc = 0
+    for nb in sizes:
+        offs.append(acc)
+        zoffs.append(zacc)
+        acc += nb
+        zacc += nb * nb
+    n_arr = (ctypes.c_int64 * max(B, 1))(*sizes)
+    off_arr = (ctypes.c_int64 * max(B, 1))(*offs)
+    zoff_arr = (ctypes.c_int64 * max(B, 1))(*zoffs)
+    gd = torch.empty(max(acc, 1), dtype=torch.float64, device=w.device)
+    ge = torch.empty(max(acc, 1), dtype=torch.float64, device=w.device)
+    rc = lib.mrrr_step_backward_batched(B, n_arr, off_arr, zoff_arr, _ptr(w), _ptr(Z), _ptr(gw), _ptr(gZ),
+                                        _ptr(gd), _ptr(ge), _stream_ptr(stream))
+    _lib.check(rc)
+    return gd[:acc], ge[:acc]
+
+
+class _MRRRFunction:
+    pass
+
+
+def _make_function():
+    torch = _torch()
+
+    class MRRRFunction(torch.autograd.Function):
+        """(d, e) -> (w, Z) by the GPU MRRR solver; backward by the GPU adjoint
+        kernels.  Requires distinct eigenvalues for the eigenvector term."""
+
+        @staticmethod
+        def forward(ctx, d, e):
+            w, Z = eigh_tridiagonal(d, e)
+            ctx.save_for_backward(w, Z)
+            return w, Z
+
+        @staticmethod
+        def backward(ctx, gw, gZ):
+            w, Z = ctx.saved_tensors
+            gd, ge = eigh_tridiagonal_backward(w, Z, gw, gZ)
+            return gd, ge
+
+    return MRRRFunction
+
+
+class _Lazy:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_function()
+        return getattr(_Lazy._fn, name)
+
+
+MRRRFunction = _Lazy()
+
+
+def get_tuning():
+    t = MrrrTuning()
+    _lib.check(_lib.load().mrrr_get_tuning(ctypes.byref(t)))
+    return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
+            "vec_wave_slots": t.vec_wave_slots, "refine_levels": bool(t.reserved[0])}
+
+
+def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, refine_levels=None,
+               diag_flags=None):
+    t = MrrrTuning()
+    lib = _lib.load()
+    _lib.check(lib.mrrr_get_tuning(ctypes.byref(t)))
+    if grid_density is not None:
+        t.grid_density = int(grid_density)
+    if refine_wave_slots is not None:
+        t.refine_wave_slots = int(refine_wave_slots)
+    if vec_wave_slots is not None:
+        t.vec_wave_slots = int(vec_wave_slots)
+    if refine_levels is not None:
+        t.reserved[0] = 1 if refine_levels else 0
+    if diag_flags is not None:
+        t.reserved[1] = int(diag_flags)
+    if lib.mrrr_set_tuning(ctypes.byref(t)) != 0:
+        raise ValueError("tuning value out of range")
+
+
+def profile(enable=True):
+    """Turn the library's per-kernel event timing on or off (and reset it)."""
+    lib = _lib.load()
+    _lib.check(lib.mrrr_profile_reset())
+    _lib.check(lib.mrrr_profile_enable(1 if enable else 0))
+
+
+def profile_read():
+    """{kernel: {launches, ms, work (flops), bytes}} accumulated since profile()."""
+    lib = _lib.load()
+    out = {}
+    for k, name in enumerate(_lib.KERNELS):
+        t = _lib.MrrrKernelTime()
+        _lib.check(lib.mrrr_profile_read(k, ctypes.byref(t)))
+        out[name] = {"launches": int(t.launches), "ms": float(t.ms), "work": float(t.work), "bytes": float(t.bytes)}
+    return out
+
+
+def release():
+    _lib.check(_lib.load().mrrr_release())

@@ -1,0 +1,51 @@
+"""Build the gfx950 HIP library (libmrrr.so) and the workload helper in-tree.
+
+    python -m paper_1205_2107_amd.build
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libmrrr.so")
+SOURCES = ["mrrr_kernels.hip", "mrrr_host.hip", "mrrr_backward.hip"]
+HEADERS = ["mrrr_dev.h", "mrrr_launch.h", "mrrr_prof.h"]
+ARCH = os.environ.get("MRRR_OFFLOAD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # packed FP32 instructions stay off (the library is FP64, and packed FP32 has
+    # shown silent wrong results on this hardware generation)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+
+def build_lib(verbose=False):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = LIB + ".tmp"
+    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + sources()
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build(verbose=False):
+    from . import workloads
+    workloads.build()
+    return build_lib(verbose)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,606 @@
+// Host runtime and C ABI of the MI355X MRRR solver: workspace management, the
+// level-by-level drive of the representation tree, argument checking.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mrrr.h"
+#include "mrrr_dev.h"
+#include "mrrr_launch.h"
+#include "mrrr_prof.h"
+
+namespace mrrr {
+
+static thread_local std::string g_err;
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static mrrr_kernel_time g_prof[MRRR_K_COUNT];
+
+bool prof_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+void prof_add(int kernel, int64_t launches, double ms, double work, double bytes) {
+  if (kernel < 0 || kernel >= MRRR_K_COUNT) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof[kernel].launches += launches;
+  g_prof[kernel].ms += ms;
+  g_prof[kernel].work += work;
+  g_prof[kernel].bytes += bytes;
+}
+
+static mrrr_tuning g_tune = {4, 0, 64, {0, 0, 0, 0, 0}};
+static std::mutex g_tune_mu;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(x)                                                                                   \
+  do {                                                                                               \
+    hipError_t _e = (x);                                                                             \
+    if (_e != hipSuccess) return fail(MRRR_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(_e));     \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Workspace {
+  std::mutex mu;
+  DevBuf problems, poff, sprob, ds, es, flag, excl, tiles, total, bstart, sblk, blocks, goff, nodes, pool, gcnt, lo,
+      hi, clo, chi, snode, sflag, scol, val, runflag, runid, runs, clusters, counters, chunkrows, chunks, chunkoff,
+      scratch, bad, perm, tmp;
+  size_t total_bytes() const {
+    const DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
+                           &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
+                           &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad,
+                           &perm, &tmp};
+    size_t t = 0;
+    for (auto* b : all) t += b->bytes;
+    return t;
+  }
+  void release() {
+    DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
+                     &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
+                     &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad, &perm,
+                     &tmp};
+    for (auto* b : all) {
+      if (b->p) (void)hipFree(b->p);
+      b->p = nullptr;
+      b->bytes = 0;
+    }
+  }
+};
+
+static std::mutex g_ws_mu;
+static std::map<int, Workspace*> g_ws;
+
+static Workspace* workspace_for_current_device(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws.find(dev);
+  if (it == g_ws.end()) it = g_ws.emplace(dev, new Workspace()).first;
+  *dev_out = dev;
+  return it->second;
+}
+
+// grow-only device buffer; contents are not preserved unless keep is set
+static int ensure(DevBuf& b, size_t bytes, hipStream_t st, bool keep = false) {
+  if (bytes <= b.bytes && b.p) return 0;
+  size_t nb = std::max(bytes, b.bytes + b.bytes / 4);
+  nb = std::max<size_t>(nb, 256);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) return fail(MRRR_ERR_CAPACITY, "hipMalloc(%zu bytes) failed: %s", nb, hipGetErrorString(e));
+  if (keep && b.p && b.bytes) {
+    e = hipMemcpyAsync(p, b.p, b.bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return fail(MRRR_ERR_HIP, "workspace copy failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (b.p) (void)hipFree(b.p);
+  b.p = p;
+  b.bytes = nb;
+  return 0;
+}
+
+template <class T>
+static T* P_(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+// scratch budget for the eigenvector kernel (bytes): a quarter of the device
+static size_t scratch_budget() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return size_t(8) << 30;
+  return std::max<size_t>(size_t(1) << 30, tot / 4);
+}
+
+struct Report {
+  Counters c;
+  int nblk = 0;
+  int levels = 0;
+  int nodes = 0;
+  size_t ws_bytes = 0;
+};
+
+// Solve a list of problems (packed into slot space) on one stream.
+static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, const double* e, double* w, double* Z,
+                 hipStream_t st, Report* rep) {
+  const int nprob = (int)probs.size();
+  mrrr_tuning tune;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune = g_tune;
+  }
+  const int G = tune.grid_density;
+  set_diag_flags(tune.reserved[1]);
+  std::vector<int64_t> poff(nprob + 1, 0);
+  for (int p = 0; p < nprob; ++p) poff[p + 1] = poff[p] + probs[p].n;
+  const int64_t ntot = poff[nprob];
+  memset(rep, 0, sizeof(*rep));
+  if (ntot == 0) return 0;
+  int rc;
+  ProfEvents prof(st);
+  // lanes per eigenvalue in refinement: spread small problems over more lanes
+  int slots = tune.refine_wave_slots;
+  if (slots == 0) slots = (ntot <= 32768) ? 16 : (ntot <= 131072 ? 32 : 64);
+  const int lanes = 64 / slots;
+  double grid_work = 0.0;
+#define ENS(buf, bytes)                                          \
+  do {                                                           \
+    if ((rc = ensure(W.buf, (size_t)(bytes), st)) != 0) return rc; \
+  } while (0)
+  ENS(problems, sizeof(Problem) * nprob);
+  ENS(poff, sizeof(int64_t) * (nprob + 1));
+  ENS(sprob, sizeof(int32_t) * ntot);
+  ENS(ds, sizeof(double) * ntot);
+  ENS(es, sizeof(double) * ntot);
+  ENS(flag, sizeof(int32_t) * ntot);
+  ENS(excl, sizeof(int32_t) * ntot);
+  ENS(tiles, sizeof(int32_t) * ((ntot + 1023) / 1024 + 1));
+  ENS(total, sizeof(int32_t) * 4);
+  ENS(counters, sizeof(Counters));
+  for (auto& p : probs) {
+    p.tmax_bits = 0;
+    p.tnorm_bits = 0;
+    p.scale = 1.0;
+    p.status = 0;
+    p.nblk = 0;
+    p.first_blk = 0;
+    p.below = 0;
+    if (p.kind == MRRR_ALL) p.m = p.n;
+    if (p.kind == MRRR_INDEX) p.m = p.iu - p.il + 1;
+    if (p.kind == MRRR_VALUE) p.m = 0;
+  }
+  HIP_TRY(hipMemcpyAsync(W.problems.p, probs.data(), sizeof(Problem) * nprob, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(W.poff.p, poff.data(), sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(W.counters.p, 0, sizeof(Counters), st));
+  Problem* dP = P_<Problem>(W.problems);
+  Counters* dC = P_<Counters>(W.counters);
+
+  // 1. scale, norms, split
+  launch_prep(st, dP, nprob, P_<int64_t>(W.poff), ntot, d, e, P_<int32_t>(W.sprob), P_<double>(W.ds),
+              P_<double>(W.es), P_<int32_t>(W.flag));
+  launch_scan(st, P_<int32_t>(W.flag), P_<int32_t>(W.excl), P_<int32_t>(W.tiles), ntot, P_<int32_t>(W.total));
+  int32_t nblk = 0;
+  HIP_TRY(hipMemcpyAsync(&nblk, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipGetLastError());
+  rep->nblk = nblk;
+  ENS(bstart, sizeof(int64_t) * (nblk + 1));
+  ENS(sblk, sizeof(int32_t) * ntot);
+  ENS(blocks, sizeof(Block) * nblk);
+  ENS(goff, sizeof(int64_t) * (nblk + 1));
+  // node table: roots first; grows per level
+  ENS(nodes, sizeof(Node) * (size_t)std::max<int64_t>(nblk + 16, 2 * (int64_t)nblk));
+  // pool: roots aligned with slots plus room for children (grown on demand)
+  size_t pool_rows = (size_t)ntot + (size_t)std::max<int64_t>(4 * 1024, ntot / 2);
+  if (W.pool.bytes / sizeof(Rep) > pool_rows) pool_rows = W.pool.bytes / sizeof(Rep);
+  ENS(pool, sizeof(Rep) * pool_rows);
+  launch_blocks(st, dP, P_<int64_t>(W.poff), P_<int32_t>(W.flag), P_<int32_t>(W.excl), ntot, nblk,
+                P_<int32_t>(W.sprob), P_<int64_t>(W.bstart), P_<int32_t>(W.sblk), P_<Block>(W.blocks));
+  // grid offsets: block b owns G * n_b + 1 points starting at G * row0_b + b
+  {
+    std::vector<int64_t> bst(nblk);
+    HIP_TRY(hipMemcpyAsync(bst.data(), W.bstart.p, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t> go(nblk + 1);
+    for (int b = 0; b < nblk; ++b) {
+      go[b] = (int64_t)G * bst[b] + b;
+      const int64_t nb = ((b + 1 < nblk) ? bst[b + 1] : ntot) - bst[b];
+      grid_work += 4.0 * (double)(G * nb + 1) * (double)nb;
+    }
+    go[nblk] = (int64_t)G * ntot + nblk;
+    HIP_TRY(hipMemcpyAsync(W.goff.p, go.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, st));
+  }
+  const int64_t gtot = (int64_t)G * ntot + nblk;
+  ENS(gcnt, sizeof(int32_t) * gtot);
+  ENS(lo, sizeof(double) * ntot);
+  ENS(hi, sizeof(double) * ntot);
+  ENS(clo, sizeof(int32_t) * ntot);
+  ENS(chi, sizeof(int32_t) * ntot);
+  ENS(snode, sizeof(int32_t) * ntot);
+  ENS(sflag, sizeof(uint32_t) * ntot);
+  ENS(scol, sizeof(int64_t) * ntot);
+  ENS(val, sizeof(double) * ntot);
+  ENS(runflag, sizeof(int32_t) * ntot);
+  ENS(runid, sizeof(int32_t) * ntot);
+  ENS(runs, sizeof(int64_t) * (ntot + 1));
+  Block* dB = P_<Block>(W.blocks);
+  Rep* dpool = P_<Rep>(W.pool);
+
+  // 2. root representations, 3. brackets from the count grid, 4. refinement
+  launch_root(st, dP, dB, P_<Node>(W.nodes), nblk, P_<double>(W.ds), P_<double>(W.es), dpool, dC, G);
+  prof.begin(MRRR_K_GRID);
+  launch_grid(st, dB, nblk, P_<int64_t>(W.goff), gtot, dpool, P_<int32_t>(W.gcnt));
+  prof.end();
+  launch_assign(st, dB, P_<int64_t>(W.goff), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.gcnt), P_<double>(W.lo),
+                P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<int32_t>(W.snode),
+                P_<uint32_t>(W.sflag), dC);
+  prof.begin(MRRR_K_REFINE);
+  launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool, P_<double>(W.lo),
+                P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag), dC,
+                lanes);
+  prof.end();
+  // problem table after the root pass: VALUE counts, block counts
+  HIP_TRY(hipMemcpyAsync(probs.data(), W.problems.p, sizeof(Problem) * nprob, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipGetLastError());
+  bool multi = false;
+  for (auto& p : probs) multi = multi || p.nblk > 1;
+  // 5. output columns
+  launch_columns(st, dP, dB, nblk, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<double>(W.lo),
+                 P_<double>(W.hi), P_<double>(W.val), P_<int64_t>(W.scol), multi);
+  if (Z == nullptr) {
+    launch_values_only(st, dP, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode),
+                       P_<int64_t>(W.scol), P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.ds), w);
+  } else {
+    // 6-7. representation tree, level by level
+    int node_base = nblk;
+    int max_clusters = (int)std::min<int64_t>(ntot / 2 + 1, INT32_MAX / 2);
+    ENS(clusters, sizeof(Cluster) * (size_t)max_clusters);
+    for (int level = 0;; ++level) {
+      // classification; pairs whose decision the bracket widths could flip are
+      // refined (validated, full accuracy) and classified again
+      int32_t nruns = 0;
+      for (int round = 0;; ++round) {
+        HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, ambiguous), 0, sizeof(int32_t), st));
+        launch_cls_flags(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode),
+                         P_<double>(W.lo), P_<double>(W.hi), P_<uint32_t>(W.sflag), P_<int32_t>(W.runflag), dC);
+        launch_scan(st, P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int32_t>(W.tiles), ntot,
+                    P_<int32_t>(W.total));
+        int32_t amb = 0;
+        HIP_TRY(hipMemcpyAsync(&nruns, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&amb, (char*)W.counters.p + offsetof(Counters, ambiguous), sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (amb == 0 || round >= 3) break;
+        prof.begin(MRRR_K_REFINE);
+        launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                      P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                      P_<uint32_t>(W.sflag), dC, lanes);
+        prof.end();
+      }
+      launch_cls_compact(st, ntot, P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int64_t>(W.runs));
+      launch_cls_runs(st, dB, P_<Node>(W.nodes), nruns, P_<int64_t>(W.runs), P_<int32_t>(W.sblk),
+                      P_<int32_t>(W.snode), P_<double>(W.lo), P_<double>(W.hi), P_<int64_t>(W.scol),
+                      P_<uint32_t>(W.sflag), P_<Cluster>(W.clusters), max_clusters, dC);
+      launch_clear_active(st, ntot, P_<uint32_t>(W.sflag));
+      Counters hc;
+      HIP_TRY(hipMemcpyAsync(&hc, W.counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipGetLastError());
+      rep->levels = level + 1;
+      const int ncl = std::min(hc.nclusters, max_clusters);
+      if (ncl == 0) break;
+      // capacity for the new nodes and four candidate children per cluster
+      if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
+      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + 4 * (size_t)hc.cluster_rows;
+      if (need_rows * sizeof(Rep) > W.pool.bytes) {
+        if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
+        dpool = P_<Rep>(W.pool);
+      }
+      const unsigned long long pool_cap = W.pool.bytes / sizeof(Rep);
+      // children are appended after the root rows
+      if (hc.pool_used < (unsigned long long)ntot) {
+        unsigned long long pu = (unsigned long long)ntot;
+        HIP_TRY(hipMemcpyAsync((char*)W.counters.p + offsetof(Counters, pool_used), &pu, sizeof(pu),
+                               hipMemcpyHostToDevice, st));
+      }
+      prof.begin(MRRR_K_CHILD);
+      launch_child(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<double>(W.lo),
+                   P_<double>(W.hi), dpool, pool_cap, dC);
+      prof.end();
+      launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
+                   P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                   P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), tune.reserved[0] != 0);
+      if (tune.reserved[0] != 0) {
+        prof.begin(MRRR_K_REFINE);
+        launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                      P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                      P_<uint32_t>(W.sflag), dC, lanes);
+        prof.end();
+      }
+      HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, nclusters), 0, sizeof(int32_t), st));
+      HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, cluster_rows), 0, sizeof(unsigned long long),
+                             st));
+      node_base += ncl;
+      if (level > kMaxDepth + 2) break;
+    }
+    rep->nodes = node_base - nblk;
+    // singletons of child nodes: validated, full-accuracy brackets in their leaf's frame
+    launch_mark_leaf(st, ntot, P_<int64_t>(W.scol), P_<uint32_t>(W.sflag));
+    prof.begin(MRRR_K_REFINE);
+    launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                  P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
+                  dC, lanes);
+    prof.end();
+    // 8. eigenvectors of all singletons
+    const int64_t nch = (ntot + 63) / 64;
+    ENS(chunkrows, sizeof(int32_t) * nch);
+    launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
+                      P_<int32_t>(W.chunkrows));
+    std::vector<int32_t> rows(nch);
+    HIP_TRY(hipMemcpyAsync(rows.data(), W.chunkrows.p, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> act;
+    std::vector<int64_t> aoff;
+    int64_t maxper = 0;
+    for (int64_t c = 0; c < nch; ++c)
+      if (rows[c] > 0) {
+        act.push_back((int32_t)c);
+        maxper = std::max<int64_t>(maxper, 2 * 64 * (int64_t)rows[c]);
+      }
+    const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
+    ENS(chunks, sizeof(int32_t) * (act.size() + 1));
+    ENS(chunkoff, sizeof(int64_t) * (act.size() + 1));
+    size_t i0 = 0;
+    while (i0 < act.size()) {
+      // the largest run of chunks whose scratch fits the budget
+      size_t i1 = i0;
+      int64_t used = 0;
+      aoff.clear();
+      while (i1 < act.size()) {
+        const int64_t need = 2 * 64 * (int64_t)rows[act[i1]];
+        if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
+        aoff.push_back(used);
+        used += need;
+        ++i1;
+      }
+      ENS(scratch, sizeof(double) * (size_t)used);
+      HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data() + i0, sizeof(int32_t) * (i1 - i0), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * (i1 - i0), hipMemcpyHostToDevice, st));
+      prof.begin(MRRR_K_VECTORS);
+      launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff), (int)(i1 - i0),
+                     ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
+                     P_<double>(W.lo), P_<double>(W.hi), dpool, P_<double>(W.ds), P_<double>(W.scratch), w, Z, dC);
+      prof.end();
+      // host vectors are reused by the next batch: wait for the copies
+      HIP_TRY(hipStreamSynchronize(st));
+      i0 = i1;
+    }
+  }
+  // 9. ascending order within each problem
+  ENS(bad, sizeof(int32_t) * nprob);
+  HIP_TRY(hipMemsetAsync(W.bad.p, 0, sizeof(int32_t) * nprob, st));
+  launch_check_sorted(st, dP, nprob, w, P_<int32_t>(W.bad), dC);
+  Counters hc;
+  HIP_TRY(hipMemcpyAsync(&hc, W.counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc.unsorted) {
+    ENS(perm, sizeof(int64_t) * ntot);
+    ENS(tmp, sizeof(double) * ntot);
+    launch_sort_fix(st, dP, nprob, P_<int32_t>(W.bad), w, P_<int64_t>(W.perm), P_<double>(W.tmp), Z);
+  }
+  HIP_TRY(hipMemcpyAsync(probs.data(), W.problems.p, sizeof(Problem) * nprob, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&hc, W.counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipGetLastError());
+  rep->c = hc;
+  rep->ws_bytes = W.total_bytes();
+  if (prof.on) {
+    const double work[MRRR_K_COUNT] = {grid_work, 4.0 * (double)hc.sturm_steps, 5.0 * (double)hc.child_steps,
+                                       15.0 * (double)hc.vec_rows, 0.0};
+    const double bytes[MRRR_K_COUNT] = {0.0, 0.0, 32.0 * (double)hc.child_steps, 8.0 * (double)hc.z_entries, 0.0};
+    for (int k = 0; k < MRRR_K_BACKWARD; ++k) {
+      double ms;
+      int64_t l;
+      prof.total(k, &ms, &l);
+      if (l) prof_add(k, l, ms, work[k], bytes[k]);
+    }
+  }
+  if (hc.grid_fail) return fail(MRRR_ERR_HIP, "internal: Sturm grid did not bracket the spectrum");
+  return 0;
+#undef ENS
+}
+
+static void fill_info(mrrr_info* info, const Problem& p, const Report& r) {
+  memset(info, 0, sizeof(*info));
+  info->m = p.m;
+  info->status = p.status ? p.status : r.c.status;
+  info->max_depth = r.c.max_depth;
+  info->counters[MRRR_CNT_BLOCKS] = r.nblk;
+  info->counters[MRRR_CNT_NODES] = r.nodes;
+  info->counters[MRRR_CNT_LEVELS] = r.levels;
+  info->counters[MRRR_CNT_STURM_STEPS] = (int64_t)r.c.sturm_steps;
+  info->counters[MRRR_CNT_QDS_STEPS] = (int64_t)r.c.qds_steps;
+  info->counters[MRRR_CNT_SINGLETONS] = (int64_t)r.c.singletons;
+  info->counters[MRRR_CNT_RQI] = (int64_t)r.c.rqi;
+  info->counters[MRRR_CNT_FALLBACKS] = (int64_t)r.c.fallbacks;
+  info->counters[MRRR_CNT_CHILD_REJECT] = (int64_t)r.c.child_reject;
+  info->counters[MRRR_CNT_WORKSPACE_MB] = (int64_t)(r.ws_bytes >> 20);
+}
+
+}  // namespace mrrr
+
+using namespace mrrr;
+
+extern "C" {
+
+int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z, int64_t ldz,
+              mrrr_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (n < 0) return fail(-1, "n < 0");
+  if (n > 0 && !d) return fail(-2, "d is NULL");
+  if (n > 1 && !e) return fail(-3, "e is NULL");
+  if (range.kind < 0 || range.kind > 2) return fail(-4, "bad range kind");
+  if (range.kind == MRRR_INDEX && n > 0 && (range.il < 1 || range.il > range.iu || range.iu > n))
+    return fail(-4, "index range must satisfy 1 <= il <= iu <= n");
+  if (range.kind == MRRR_VALUE && !(range.vl < range.vu)) return fail(-4, "value range must satisfy vl < vu");
+  if (n > 0 && !w) return fail(-5, "w is NULL");
+  if (Z && ldz < std::max<int64_t>(1, n)) return fail(-7, "ldz < max(1, n)");
+  if (n > INT32_MAX / 8) return fail(-1, "n too large");
+  if (n == 0) return 0;
+  int dev = 0;
+  Workspace* W = workspace_for_current_device(&dev);
+  if (!W) return fail(MRRR_ERR_NO_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(W->mu);
+  std::vector<Problem> probs(1);
+  Problem& p = probs[0];
+  memset(&p, 0, sizeof(p));
+  p.off = 0;
+  p.n = n;
+  p.zoff = 0;
+  p.ldz = Z ? ldz : n;
+  p.kind = range.kind;
+  p.il = range.il;
+  p.iu = range.iu;
+  p.vl = range.vl;
+  p.vu = range.vu;
+  Report r;
+  int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r);
+  if (rc != 0) return rc;
+  if (info) fill_info(info, probs[0], r);
+  const int st = probs[0].status ? probs[0].status : r.c.status;
+  if (st) fail(st, "%s", mrrr_status_string(st));
+  return st;
+}
+
+int mrrr_step_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host, const double* d,
+                      const double* e, double* w, double* Z, const int64_t* zoff_host, mrrr_info* info,
+                      void* stream) {
+  if (batch < 0) return fail(-1, "batch < 0");
+  if (batch == 0) return 0;
+  if (!n_host) return fail(-2, "n_host is NULL");
+  if (!off_host) return fail(-3, "off_host is NULL");
+  if (!d) return fail(-4, "d is NULL");
+  if (!e) return fail(-5, "e is NULL");
+  if (!w) return fail(-6, "w is NULL");
+  if (Z && !zoff_host) return fail(-8, "zoff_host is NULL");
+  int64_t tot = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    if (n_host[b] < 1 || n_host[b] > INT32_MAX / 8) return fail(-2, "n_host[%lld] out of range", (long long)b);
+    if (off_host[b] < 0) return fail(-3, "off_host[%lld] < 0", (long long)b);
+    tot += n_host[b];
+  }
+  if (tot > INT32_MAX / 2) return fail(-2, "total order too large");
+  int dev = 0;
+  Workspace* W = workspace_for_current_device(&dev);
+  if (!W) return fail(MRRR_ERR_NO_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(W->mu);
+  std::vector<Problem> probs(batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    Problem& p = probs[b];
+    memset(&p, 0, sizeof(p));
+    p.off = off_host[b];
+    p.n = n_host[b];
+    p.zoff = Z ? zoff_host[b] : 0;
+    p.ldz = n_host[b];
+    p.kind = MRRR_ALL;
+  }
+  Report r;
+  int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r);
+  if (rc != 0) return rc;
+  int st = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    if (info) fill_info(&info[b], probs[b], r);
+    if (!st && probs[b].status) st = probs[b].status;
+  }
+  if (!st) st = r.c.status;
+  if (st) fail(st, "%s", mrrr_status_string(st));
+  return st;
+}
+
+int mrrr_get_tuning(mrrr_tuning* t) {
+  if (!t) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *t = g_tune;
+  return 0;
+}
+
+int mrrr_set_tuning(const mrrr_tuning* t) {
+  if (!t) return -1;
+  if (t->grid_density < 1 || t->grid_density > 16) return -1;
+  if (!(t->refine_wave_slots == 0 || t->refine_wave_slots == 16 || t->refine_wave_slots == 32 ||
+        t->refine_wave_slots == 64))
+    return -1;
+  if (!(t->vec_wave_slots == 16 || t->vec_wave_slots == 32 || t->vec_wave_slots == 64)) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = *t;
+  return 0;
+}
+
+int mrrr_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return 0;
+}
+
+int mrrr_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  memset(g_prof, 0, sizeof(g_prof));
+  return 0;
+}
+
+int mrrr_profile_read(int kernel, mrrr_kernel_time* out) {
+  if (kernel < 0 || kernel >= MRRR_K_COUNT || !out) return -1;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  *out = g_prof[kernel];
+  return 0;
+}
+
+int mrrr_release(void) {
+  int dev = 0;
+  Workspace* W = workspace_for_current_device(&dev);
+  if (!W) return fail(MRRR_ERR_NO_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(W->mu);
+  W->release();
+  return 0;
+}
+
+const char* mrrr_last_error(void) { return g_err.c_str(); }
+
+const char* mrrr_status_string(int code) {
+  switch (code) {
+    case MRRR_OK: return "ok";
+    case MRRR_ERR_NO_RRR: return "no child representation with finite entries";
+    case MRRR_ERR_DEPTH: return "representation tree deeper than 64 levels";
+    case MRRR_ERR_CAPACITY: return "workspace capacity exhausted";
+    case MRRR_ERR_NONFINITE: return "non-finite entry in d or e";
+    case MRRR_ERR_HIP: return "HIP runtime error";
+    case MRRR_ERR_NO_DEVICE: return "no usable device";
+    default: return code < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,1432 @@
+// HIP kernels of the MRRR tridiagonal eigensolver for gfx950 (MI355X), FP64.
+//
+// Steps (Petschow, Peise, Bientinesi, arXiv:1205.2107, Sec. 3.1.1):
+//   split            k_prep_max, k_prep_scale, k_split_flags, k_blocks*
+//   root RRR         k_root           L0 D0 L0^T = T - sigma I, T - sigma I definite
+//   bisection        k_grid, k_assign, k_refine   Sturm counts on L D L^T (one lane per
+//                    eigenvalue), accelerated by safeguarded Newton steps on det
+//   classification   k_cls_flags, k_cls_compact, k_cls_runs   relative gaps, tol 1e-3
+//   clusters         k_child, k_shift L_c D_c L_c^T = L D L^T - sigma_c I (stationary qds)
+//   singletons       k_vectors        twisted factorization + Rayleigh correction,
+//                    z written to column-major Z through an LDS transpose
+#include "mrrr_dev.h"
+#include "mrrr_launch.h"
+
+namespace mrrr {
+
+// experiment switches (bit 0: IEEE division in twisted factorizations, bit 1:
+// stricter Rayleigh-quotient stop, bit 2: refine to 2 eps relative width)
+__constant__ int c_diag_flags;
+void set_diag_flags(int f) { (void)hipMemcpyToSymbol(HIP_SYMBOL(c_diag_flags), &f, sizeof(int)); }
+
+// ---------------------------------------------------------------------------
+// helpers
+
+__device__ inline int find_segment(const int64_t* __restrict__ off, int count, int64_t x) {
+  // largest k in [0, count) with off[k] <= x (off ascending, off[0] = 0)
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline void atomic_max_nonneg(uint64_t* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline void set_status(Counters* C, int code) { atomicCAS(&C->status, 0, code); }
+
+// a pointer every lane of the wavefront holds: make it scalar (SGPR) so loads
+// through it become scalar-cache loads shared by the wavefront
+template <class T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+__device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
+
+
+// ---------------------------------------------------------------------------
+// 1. input checks, scaling, 1-norm, split points
+
+__global__ void k_prep_max(Problem* __restrict__ P, int nprob, const int64_t* __restrict__ poff, int64_t ntot,
+                           const double* __restrict__ d, const double* __restrict__ e, int32_t* __restrict__ sprob) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  int p = find_segment(poff, nprob, s);
+  sprob[s] = p;
+  const int64_t i = s - poff[p];
+  const int64_t n = P[p].n;
+  const double dv = d[P[p].off + i];
+  const double ev = (i + 1 < n) ? e[P[p].off + i] : 0.0;
+  if (!isfinite(dv) || !isfinite(ev)) {
+    atomicCAS(&P[p].status, 0, 4);
+    return;
+  }
+  atomic_max_nonneg(&P[p].tmax_bits, fmax(fabs(dv), fabs(ev)));
+}
+
+__global__ void k_prep_scale(Problem* __restrict__ P, const int64_t* __restrict__ poff, int64_t ntot,
+                             const double* __restrict__ d, const double* __restrict__ e,
+                             const int32_t* __restrict__ sprob, double* __restrict__ ds, double* __restrict__ es) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int p = sprob[s];
+  const int64_t i = s - poff[p];
+  const int64_t n = P[p].n;
+  const double tmax = __longlong_as_double((long long)P[p].tmax_bits);
+  double scale = 1.0;
+  if (tmax > 0.0 && (tmax < 0x1p-500 || tmax > 0x1p500)) scale = ldexp(1.0, -ilogb(tmax));
+  if (i == 0) P[p].scale = scale;
+  // a problem with a non-finite entry is solved as the zero matrix (status 4)
+  const bool bad = P[p].status == 4;
+  const double dv = bad ? 0.0 : d[P[p].off + i] * scale;
+  const double ev = (!bad && i + 1 < n) ? e[P[p].off + i] * scale : 0.0;
+  const double evm = (!bad && i > 0) ? e[P[p].off + i - 1] * scale : 0.0;
+  ds[s] = dv;
+  es[s] = ev;
+  atomic_max_nonneg(&P[p].tnorm_bits, fabs(evm) + fabs(dv) + fabs(ev));
+}
+
+__global__ void k_split_flags(const Problem* __restrict__ P, const int64_t* __restrict__ poff, int64_t ntot,
+                              const int32_t* __restrict__ sprob, double* __restrict__ es, int32_t* __restrict__ flag) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int p = sprob[s];
+  const int64_t i = s - poff[p];
+  int start = (i == 0);
+  if (!start) {
+    const double tnorm = __longlong_as_double((long long)P[p].tnorm_bits);
+    if (fabs(es[s - 1]) <= kEps * tnorm) {
+      es[s - 1] = 0.0;
+      start = 1;
+    }
+  }
+  flag[s] = start;
+}
+
+// exclusive scan of int32 flags: per-workgroup pass, top-level pass, fix-up
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int wg_inclusive_scan(int v, int* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t* __restrict__ tile_sum,
+                             int64_t n) {
+  __shared__ int sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    sum += v[k];
+  }
+  int incl = wg_inclusive_scan(sum, sh);
+  int run = incl - sum;
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanThreads - 1) tile_sum[blockIdx.x] = incl;
+}
+
+__global__ void k_scan_top(int32_t* __restrict__ tile_sum, int64_t ntiles, int32_t* __restrict__ total) {
+  __shared__ int sh[kScanThreads];
+  __shared__ int s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < ntiles; base += kScanThreads) {
+    const int64_t k = base + threadIdx.x;
+    const int v = (k < ntiles) ? tile_sum[k] : 0;
+    const int incl = wg_inclusive_scan(v, sh);
+    const int carry = s_carry;
+    if (k < ntiles) tile_sum[k] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == kScanThreads - 1) s_carry = carry + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict__ tile_sum, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int add = tile_sum[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+// block table from the split flags and their exclusive scan
+__global__ void k_blocks(const int32_t* __restrict__ flag, const int32_t* __restrict__ excl, int64_t ntot,
+                         int64_t* __restrict__ bstart, int32_t* __restrict__ sblk) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int f = flag[s];
+  const int b = excl[s] + f - 1;
+  sblk[s] = b;
+  if (f) bstart[b] = s;
+}
+
+__global__ void k_blocks2(Problem* __restrict__ P, const int64_t* __restrict__ poff, const int64_t* __restrict__ bstart,
+                          int nblk, int64_t ntot, const int32_t* __restrict__ sprob, Block* __restrict__ B) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  const int64_t r0 = bstart[b];
+  const int64_t r1 = (b + 1 < nblk) ? bstart[b + 1] : ntot;
+  const int p = sprob[r0];
+  Block blk;
+  blk.row0 = r0;
+  blk.lrow0 = r0 - poff[p];
+  blk.n = (int32_t)(r1 - r0);
+  blk.prob = p;
+  blk.gl = blk.gu = blk.pivmin = blk.sigma = 0.0;
+  blk.wl = 1;
+  blk.wu = blk.n;
+  blk.left = 1;
+  blk.gP = 0;
+  blk.goff = 0;
+  blk.glo = blk.ghi = 0.0;
+  B[b] = blk;
+  atomicAdd(&P[p].nblk, 1);
+  if (blk.lrow0 == 0) P[p].first_blk = b;
+}
+
+// ---------------------------------------------------------------------------
+// 2. root representation per block (one workgroup of 256 threads per block)
+
+__device__ inline double wg_reduce(double v, double* sh, int op) {  // op 0 min, 1 max
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (t < off) sh[t] = op ? fmax(sh[t], sh[t + off]) : fmin(sh[t], sh[t + off]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __restrict__ B, Node* __restrict__ N,
+                                              const double* __restrict__ ds, const double* __restrict__ es,
+                                              Rep* __restrict__ pool, Counters* __restrict__ C, int grid_density) {
+  __shared__ double sh[256];
+  __shared__ double s_sigma;
+  __shared__ int s_ok;
+  __shared__ int s_cnt[2];
+  const int b = blockIdx.x;
+  Block blk = B[b];
+  const int n = blk.n;
+  const int p = blk.prob;
+  const double* d = ds + blk.row0;
+  const double* e = es + blk.row0;
+  double gl = INFINITY, gu = -INFINITY, em = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double r = 0.0;
+    if (i > 0) r += fabs(e[i - 1]);
+    if (i + 1 < n) {
+      r += fabs(e[i]);
+      em = fmax(em, e[i] * e[i]);
+    }
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+  }
+  gl = wg_reduce(gl, sh, 0);
+  gu = wg_reduce(gu, sh, 1);
+  em = wg_reduce(em, sh, 1);
+  const double pivmin = kSafmin * fmax(1.0, em);
+  const Problem pr = P[p];
+  int wl = 1, wu = n;
+  if (pr.kind == 1 && pr.nblk == 1) {
+    wl = (int)pr.il;
+    wu = (int)pr.iu;
+  }
+  // VALUE ranges: local index range from Sturm counts on T (two waves)
+  if (pr.kind == 2) {
+    if (threadIdx.x == 64 || threadIdx.x == 128) {
+      const double v = (threadIdx.x == 64 ? pr.vl : pr.vu) * pr.scale;
+      s_cnt[threadIdx.x == 128] = sturm_count_T(d, e, n, v, pivmin);
+    }
+    __syncthreads();
+    wl = s_cnt[0] + 1;
+    wu = s_cnt[1];
+  }
+  const int left = (pr.kind == 0) || (pr.kind == 1 && pr.nblk > 1) || (wl + wu <= n + 1);
+  Rep* R = pool + blk.row0;
+  if (threadIdx.x == 0) {
+    double delta = 4.0 * (double)n * kEps * fmax(fabs(gl), fabs(gu));
+    if (!(delta > 0.0)) delta = pivmin;
+    int ok = 0;
+    double sigma = 0.0;
+    for (int tries = 0; tries < 64 && !ok; ++tries) {
+      sigma = left ? gl - delta : gu + delta;
+      ok = 1;
+      double Dp = d[0] - sigma;
+      for (int i = 0; i + 1 < n; ++i) {
+        const double L = e[i] / Dp;
+        R[i].D = Dp;
+        R[i].L = L;
+        if (!isfinite(Dp) || !isfinite(L) || (left ? !(Dp > 0.0) : !(Dp < 0.0))) ok = 0;
+        Dp = (d[i + 1] - sigma) - L * e[i];
+      }
+      R[n - 1].D = Dp;
+      R[n - 1].L = 0.0;
+      if (!isfinite(Dp) || (left ? !(Dp > 0.0) : !(Dp < 0.0))) ok = 0;
+      delta *= 2.0;
+    }
+    s_sigma = sigma;
+    s_ok = ok;
+  }
+  __syncthreads();
+  const double sigma = s_sigma;
+  if (!s_ok) set_status(C, 1);
+  // deterministic relative perturbation of the root, then the products
+  const uint64_t seed = (uint64_t)blk.lrow0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double D = R[i].D * (1.0 + kPertScale * kEps * unit_sym(seed, 2u * (uint64_t)i));
+    double L = (i + 1 < n) ? R[i].L * (1.0 + kPertScale * kEps * unit_sym(seed, 2u * (uint64_t)i + 1u)) : 0.0;
+    double LD = L * D;
+    R[i].D = D;
+    R[i].L = L;
+    R[i].LD = LD;
+    R[i].LLD = LD * L;
+  }
+  if (threadIdx.x == 0) {
+    const double pad = 8.0 * (double)n * kEps * fmax(fabs(gl), fabs(gu)) + 4.0 * pivmin;
+    blk.gl = gl;
+    blk.gu = gu;
+    blk.pivmin = pivmin;
+    blk.sigma = sigma;
+    blk.wl = wl;
+    blk.wu = wu;
+    blk.left = left;
+    blk.glo = (gl - sigma) - pad;
+    blk.ghi = (gu - sigma) + pad;
+    blk.gP = grid_density * n;
+    B[b] = blk;
+    Node nd;
+    nd.rep = blk.row0;
+    nd.acc = sigma;
+    nd.sigma = 0.0;
+    nd.gapl = INFINITY;
+    nd.gapr = INFINITY;
+    nd.blk = b;
+    nd.depth = 0;
+    nd.f = 1;
+    nd.l = n;
+    nd.parent = -1;
+    nd.pad = 0;
+    N[b] = nd;
+    if (pr.kind == 2) {
+      atomicAdd((unsigned long long*)&P[p].m, (unsigned long long)(wu >= wl ? wu - wl + 1 : 0));
+      atomicAdd((unsigned long long*)&P[p].below, (unsigned long long)(wl - 1));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. eigenvalue brackets: a grid of Sturm counts per block, then one lane per
+//    eigenvalue picks its grid cell
+
+__global__ void __launch_bounds__(64) k_grid(const Block* __restrict__ B, int nblk, const int64_t* __restrict__ goff,
+                                             int64_t gtot, const Rep* __restrict__ pool, int32_t* __restrict__ gcnt) {
+  const int64_t t0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t t = t0 < gtot ? t0 : gtot - 1;  // tail lanes repeat the last point
+  const int b = find_segment(goff, nblk, t);
+  const Block blk = B[b];
+  const int k = (int)(t - goff[b]);
+  const double x = grid_point(blk.glo, blk.ghi, k, blk.gP);
+  const int b0 = __shfl(b, 0, 64);
+  int c;
+  if (__ballot(b != b0) == 0) {
+    const Rep* R = wave_uniform(pool + blk.row0);
+    c = sturm_count(R, __builtin_amdgcn_readfirstlane(blk.n), x, blk.pivmin);
+  } else {
+    c = sturm_count(pool + blk.row0, blk.n, x, blk.pivmin);
+  }
+  if (t0 < gtot) gcnt[t0] = c;
+}
+
+__global__ void k_assign(const Block* __restrict__ B, const int64_t* __restrict__ goff, int64_t ntot,
+                         const int32_t* __restrict__ sblk, const int32_t* __restrict__ gcnt, double* __restrict__ lo,
+                         double* __restrict__ hi, int32_t* __restrict__ clo, int32_t* __restrict__ chi,
+                         int32_t* __restrict__ snode, uint32_t* __restrict__ sflag, Counters* __restrict__ C) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int b = sblk[s];
+  const Block blk = B[b];
+  const int j = (int)(s - blk.row0) + 1;
+  const int32_t* c = gcnt + goff[b];
+  const int P = blk.gP;
+  int a = 0, z = P;
+  if (c[0] > j - 1 || c[P] < j) atomicExch(&C->grid_fail, 1);
+  while (z - a > 1) {
+    const int mid = (a + z) >> 1;
+    if (c[mid] <= j - 1)
+      a = mid;
+    else
+      z = mid;
+  }
+  lo[s] = grid_point(blk.glo, blk.ghi, a, P);
+  hi[s] = grid_point(blk.glo, blk.ghi, z, P);
+  clo[s] = c[a];
+  chi[s] = c[z];
+  snode[s] = b;
+  sflag[s] = F_NEEDS_REFINE | F_ACTIVE;
+}
+
+// ---------------------------------------------------------------------------
+// 4. refinement.  L lanes serve one eigenvalue and evaluate L shifts per sweep
+//    (Sturm count plus log-derivative of the determinant each); the group then
+//    shares the results and every lane updates the same state:
+//      validation   the bracket ends (and widened ends) until cnt(lo) <= j-1 < cnt(hi)
+//      section      L equispaced interior points while the bracket holds more
+//                   than one eigenvalue (or no Newton estimate lies inside)
+//      Newton       tau_N = tau - 1/g from the bracket end with the smaller
+//                   step, plus probes tau_N -+ delta that certify the bracket
+//    until the bracket is 4 eps relative wide (bisection's guarantee of high
+//    relative accuracy, reached with far fewer sweeps).
+
+struct EigState {
+  double lo, hi;    // bracket (w.r.t. the slot's node)
+  double glo, ghi;  // log-derivative at lo / hi (NaN: unknown)
+  double pad;       // widening step while validating
+  int clo, chi;     // counts at lo / hi, -1 when not validated
+  int j;            // 1-based index in the block
+  int done;
+};
+
+__device__ inline bool bracket_converged(double lo, double hi) {
+  const double mid = 0.5 * (lo + hi);
+  const double f = (c_diag_flags & 4) ? 2.0 : 4.0;
+  return hi - lo <= f * kEps * fmax(fabs(lo), fabs(hi)) || mid <= lo || mid >= hi;
+}
+
+template <int L>
+__device__ inline double next_point(const EigState& S, int k) {
+  const bool vl = S.clo >= 0, vh = S.chi >= 0;
+  if (!vl || !vh) {
+    if (!vl && !vh) {
+      if (L == 1) return S.lo;
+      if (L == 2) return k == 0 ? S.lo : S.hi;
+      const double pts[4] = {S.lo, S.hi, S.lo - S.pad, S.hi + S.pad};
+      return pts[k & 3];
+    }
+    const double x = vl ? S.hi : S.lo;
+    const double dir = vl ? 1.0 : -1.0;
+    const double mult[4] = {0.0, 1.0, 4.0, 16.0};
+    return x + dir * S.pad * mult[k & 3];
+  }
+  const double mid = 0.5 * (S.lo + S.hi);
+  if (S.chi - S.clo == 1) {
+    // Newton estimates from both ends; keep the shorter step that stays inside
+    double tn = NAN, step = INFINITY;
+    if (isfinite(S.glo) && S.glo != 0.0) {
+      const double st = 1.0 / S.glo;
+      const double c = S.lo - st;
+      if (c > S.lo && c < S.hi && fabs(st) < step) { tn = c; step = fabs(st); }
+    }
+    if (isfinite(S.ghi) && S.ghi != 0.0) {
+      const double st = 1.0 / S.ghi;
+      const double c = S.hi - st;
+      if (c > S.lo && c < S.hi && fabs(st) < step) { tn = c; step = fabs(st); }
+    }
+    if (tn == tn) {
+      const double delta = fmax(2.0 * kEps * fabs(tn), 1e-3 * step);
+      const bool far_hi = (S.hi - tn) > (tn - S.lo);
+      double p;
+      if (L == 1) {
+        p = (step <= 2.0 * kEps * fabs(tn)) ? (far_hi ? tn + delta : tn - delta) : tn;
+      } else if (L == 2) {
+        p = (k == 0) ? tn : (far_hi ? tn + delta : tn - delta);
+      } else {
+        const double pts[4] = {tn, tn - delta, tn + delta, mid};
+        p = pts[k & 3];
+      }
+      return (p > S.lo && p < S.hi) ? p : mid;
+    }
+  }
+  return S.lo + (S.hi - S.lo) * ((double)(k + 1) / (double)(L + 1));
+}
+
+template <int L>
+__device__ inline void update_state(EigState& S, const double* p, const int* c, const double* g) {
+  double pmin = INFINITY, pmax = -INFINITY;
+  for (int q = 0; q < L; ++q) {
+    pmin = fmin(pmin, p[q]);
+    pmax = fmax(pmax, p[q]);
+    if (c[q] <= S.j - 1) {
+      if (S.clo < 0 || p[q] > S.lo) { S.lo = p[q]; S.clo = c[q]; S.glo = g[q]; }
+    } else {
+      if (S.chi < 0 || p[q] < S.hi) { S.hi = p[q]; S.chi = c[q]; S.ghi = g[q]; }
+    }
+  }
+  if (S.clo < 0) { S.lo = pmin - S.pad; S.pad *= 4.0; }
+  if (S.chi < 0) { S.hi = pmax + S.pad; S.pad *= 4.0; }
+  S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
+}
+
+template <int L>
+__device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __restrict__ R, int n, double pivmin,
+                                          int k, int gbase) {
+  long long steps = 0;
+  for (int sw = 0; sw < kMaxSweeps; ++sw) {
+    const bool need = act && !S.done;
+    if (__ballot(need) == 0) break;
+    const double p = need ? next_point<L>(S, k) : 0.0;
+    double gv;
+    const int c = sturm_count_deriv(R, n, p, pivmin, &gv);
+    if (need) steps += n;
+    double pq[L], gq[L];
+    int cq[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      pq[q] = __shfl(p, gbase + q, 64);
+      cq[q] = __shfl(c, gbase + q, 64);
+      gq[q] = __shfl(gv, gbase + q, 64);
+    }
+    if (need) update_state<L>(S, pq, cq, gq);
+  }
+  return steps;
+}
+
+template <int L>
+__global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, const Node* __restrict__ N,
+                                               int64_t ntot, const int32_t* __restrict__ sblk,
+                                               const int32_t* __restrict__ snode, const Rep* __restrict__ pool,
+                                               double* __restrict__ lo_a, double* __restrict__ hi_a,
+                                               int32_t* __restrict__ clo_a, int32_t* __restrict__ chi_a,
+                                               uint32_t* __restrict__ sflag, Counters* __restrict__ C) {
+  const int lane = threadIdx.x;
+  const int k = lane % L, gbase = lane - k;
+  const int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L;
+  const bool act = (s < ntot) && (sflag[s] & F_NEEDS_REFINE);
+  const uint64_t am = __ballot(act);
+  if (am == 0) return;
+  const int64_t sf = __shfl(s, first_lane(am), 64);
+  const int64_t ss = act ? s : sf;  // idle lanes shadow a valid slot
+  const Block blk = B[sblk[ss]];
+  const Node nd = N[snode[ss]];
+  EigState S;
+  S.lo = lo_a[ss];
+  S.hi = hi_a[ss];
+  S.clo = clo_a[ss];
+  S.chi = chi_a[ss];
+  S.glo = NAN;
+  S.ghi = NAN;
+  S.j = (int)(ss - blk.row0) + 1;
+  S.pad = fmax(fmax(S.hi - S.lo, 4.0 * kEps * fmax(fabs(S.lo), fabs(S.hi))), blk.pivmin);
+  S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
+  const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
+  long long steps;
+  if (__ballot(nd.rep != rep0) == 0) {
+    const Rep* R = wave_uniform(pool + nd.rep);
+    steps = refine_sweeps<L>(S, act, R, __builtin_amdgcn_readfirstlane(blk.n), blk.pivmin, k, gbase);
+  } else {
+    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase);
+  }
+  if (act && k == 0) {
+    lo_a[s] = S.lo;
+    hi_a[s] = S.hi;
+    clo_a[s] = S.clo;
+    chi_a[s] = S.chi;
+    uint32_t fl = sflag[s] & ~F_NEEDS_REFINE;
+    if (S.done) fl |= F_ACCURATE;
+    sflag[s] = fl;
+  }
+  // each lane evaluated its own points: count all of them
+  if (act) atomicAdd(&C->sturm_steps, (unsigned long long)steps);
+}
+
+// singletons whose bracket is not at full accuracy in their leaf's frame
+__global__ void k_mark_leaf(int64_t ntot, const int64_t* __restrict__ scol, uint32_t* __restrict__ sflag) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const uint32_t fl = sflag[s];
+  if ((fl & F_SINGLETON) && scol[s] >= 0 && !(fl & F_ACCURATE)) sflag[s] = fl | F_NEEDS_REFINE;
+}
+
+// ---------------------------------------------------------------------------
+// 5. output columns: single-block problems map local indices directly; with
+//    several blocks the rank of each eigenvalue in its problem is found by
+//    binary search in the (running-maximum) value lists of the other blocks.
+
+__global__ void k_cummax(const Block* __restrict__ B, int nblk, const Node* __restrict__ N,
+                         const double* __restrict__ lo, const double* __restrict__ hi, const Problem* __restrict__ P,
+                         double* __restrict__ val) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  const Block blk = B[b];
+  if (P[blk.prob].nblk <= 1) return;
+  const double acc = N[b].acc;
+  double run = -INFINITY;
+  for (int i = 0; i < blk.n; ++i) {
+    const int64_t s = blk.row0 + i;
+    run = fmax(run, acc + 0.5 * (lo[s] + hi[s]));
+    val[s] = run;
+  }
+}
+
+__device__ inline int count_below(const double* v, int n, double x, bool inclusive) {
+  // number of entries < x (or <= x when inclusive) in ascending v[0..n)
+  int a = 0, z = n;
+  while (a < z) {
+    const int mid = (a + z) >> 1;
+    const bool below = inclusive ? (v[mid] <= x) : (v[mid] < x);
+    if (below)
+      a = mid + 1;
+    else
+      z = mid;
+  }
+  return a;
+}
+
+__global__ void k_columns(const Problem* __restrict__ P, Block* __restrict__ B, int64_t ntot,
+                          const int32_t* __restrict__ sblk, const double* __restrict__ val, int64_t* __restrict__ scol) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int b = sblk[s];
+  const Block blk = B[b];
+  const Problem pr = P[blk.prob];
+  const int j = (int)(s - blk.row0) + 1;
+  int64_t col = -1;
+  if (pr.nblk <= 1) {
+    if (j >= blk.wl && j <= blk.wu) col = j - blk.wl;
+  } else {
+    const double x = val[s];
+    int64_t rank = j - 1;
+    for (int bb = pr.first_blk; bb < pr.first_blk + pr.nblk; ++bb) {
+      if (bb == b) continue;
+      const Block o = B[bb];
+      rank += count_below(val + o.row0, o.n, x, bb < b);
+    }
+    if (pr.kind == 0) {
+      col = rank;
+    } else if (pr.kind == 1) {
+      if (rank >= pr.il - 1 && rank <= pr.iu - 1) col = rank - (pr.il - 1);
+    } else {
+      if (j >= blk.wl && j <= blk.wu) {
+        col = rank - pr.below;
+        if (col < 0 || col >= pr.m) col = -1;
+      }
+    }
+  }
+  scol[s] = col;
+}
+
+// for multi-block INDEX problems: the wanted local range of each block
+__global__ void k_block_wanted(Block* __restrict__ B, int nblk, const Problem* __restrict__ P,
+                               const int64_t* __restrict__ scol) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  Block blk = B[b];
+  if (!(P[blk.prob].kind == 1 && P[blk.prob].nblk > 1)) return;
+  int wl = blk.n + 1, wu = 0;
+  for (int i = 0; i < blk.n; ++i)
+    if (scol[blk.row0 + i] >= 0) {
+      wl = min(wl, i + 1);
+      wu = max(wu, i + 1);
+    }
+  B[b].wl = wl;
+  B[b].wu = wu;
+}
+
+// ---------------------------------------------------------------------------
+// 6. classification of the active nodes' indices into runs
+
+__device__ inline bool rel_break(double lo_j, double hi_j, double lo_k, double hi_k) {
+  const double mj = 0.5 * (lo_j + hi_j);
+  const double mk = 0.5 * (lo_k + hi_k);
+  return (lo_k - hi_j) >= kRelgapTol * fmax(fabs(mj), fabs(mk));
+}
+
+__global__ void k_cls_flags(const Block* __restrict__ B, const Node* __restrict__ N, int64_t ntot,
+                            const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode,
+                            const double* __restrict__ lo, const double* __restrict__ hi,
+                            uint32_t* __restrict__ sflag, int32_t* __restrict__ runflag, Counters* __restrict__ C) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const uint32_t fl = sflag[s];
+  int start = 0;
+  if (fl & F_ACTIVE) {
+    const Block blk = B[sblk[s]];
+    const Node nd = N[snode[s]];
+    const int j = (int)(s - blk.row0) + 1;
+    if (j == nd.f) {
+      start = 1;
+    } else {
+      const double l0 = lo[s - 1], h0 = hi[s - 1], l1 = lo[s], h1 = hi[s];
+      start = rel_break(l0, h0, l1, h1);
+      // the decision is ambiguous when the bracket widths could flip it
+      const uint32_t fp = sflag[s - 1];
+      if (!((fp & F_ACCURATE) && (fl & F_ACCURATE))) {
+        const double m0 = 0.5 * (l0 + h0), m1 = 0.5 * (l1 + h1);
+        const double margin = (l1 - h0) - kRelgapTol * fmax(fabs(m0), fabs(m1));
+        const double unc = 2.0 * ((h0 - l0) + (h1 - l1));
+        if (fabs(margin) <= unc) {
+          if (!(fp & F_ACCURATE)) atomicOr(&sflag[s - 1], F_NEEDS_REFINE);
+          if (!(fl & F_ACCURATE)) atomicOr(&sflag[s], F_NEEDS_REFINE);
+          atomicAdd(&C->ambiguous, 1);
+        }
+      }
+    }
+  }
+  runflag[s] = start;
+}
+
+__global__ void k_cls_compact(int64_t ntot, const int32_t* __restrict__ runflag, const int32_t* __restrict__ runid,
+                              int64_t* __restrict__ runs) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  if (runflag[s]) runs[runid[s]] = s;
+}
+
+__global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__ N, int nruns,
+                           const int64_t* __restrict__ runs, const int32_t* __restrict__ sblk,
+                           const int32_t* __restrict__ snode, const double* __restrict__ lo,
+                           const double* __restrict__ hi, const int64_t* __restrict__ scol,
+                           uint32_t* __restrict__ sflag, Cluster* __restrict__ clusters, int max_clusters,
+                           Counters* __restrict__ C) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nruns) return;
+  const int64_t s = runs[r];
+  const int b = sblk[s];
+  const Block blk = B[b];
+  const int node = snode[s];
+  const Node nd = N[node];
+  const int64_t last = blk.row0 + nd.l - 1;
+  int64_t e = last;
+  if (r + 1 < nruns) e = min(e, runs[r + 1] - 1);
+  const int a = (int)(s - blk.row0) + 1;
+  const int z = (int)(e - blk.row0) + 1;
+  const bool overlap = !(z < blk.wl || a > blk.wu);
+  if (!overlap) return;
+  if (a == z) {
+    if (scol[s] >= 0) sflag[s] |= F_SINGLETON;
+    return;
+  }
+  if (nd.depth + 1 > kMaxDepth) {
+    set_status(C, 2);
+    for (int64_t q = s; q <= e; ++q)
+      if (scol[q] >= 0) sflag[q] |= F_SINGLETON;
+    return;
+  }
+  const int k = atomicAdd(&C->nclusters, 1);
+  if (k >= max_clusters) {
+    set_status(C, 3);
+    return;
+  }
+  Cluster cl;
+  cl.node = node;
+  cl.f = a;
+  cl.l = z;
+  cl.pad = 0;
+  cl.gapl = (a == nd.f) ? nd.gapl : lo[s] - hi[s - 1];
+  cl.gapr = (z == nd.l) ? nd.gapr : lo[e + 1] - hi[e];
+  clusters[k] = cl;
+  atomicAdd(&C->cluster_rows, (unsigned long long)blk.n);
+}
+
+// ---------------------------------------------------------------------------
+// 7. child representations: one wavefront per cluster; lanes 0..3 evaluate four
+//    candidate shifts (left/right end, then backed off) by the stationary qds
+//      s_1 = -sigma, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - sigma
+//    reading the parent through the scalar cache.
+
+__global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
+                                              int node_base, const Cluster* __restrict__ clusters,
+                                              const double* __restrict__ lo, const double* __restrict__ hi,
+                                              Rep* __restrict__ pool, unsigned long long pool_cap,
+                                              Counters* __restrict__ C) {
+  const int c = blockIdx.x;
+  const int cand = threadIdx.x;
+  const Cluster cl = clusters[c];
+  const Node par = N[cl.node];
+  const Block blk = B[par.blk];
+  const int n = __builtin_amdgcn_readfirstlane(blk.n);
+  const bool live = cand < 4;
+  double sigma = 0.0, growth = INFINITY;
+  long long off = -1;
+  {
+    const int64_t sa = blk.row0 + cl.f - 1, sb = blk.row0 + cl.l - 1;
+    const double avgap = (hi[sb] - lo[sa]) / (double)(cl.l - cl.f);
+    double backoff = fmin(0.5 * avgap, 0.25 * fmin(cl.gapl, cl.gapr));
+    if (!(backoff > 0.0)) backoff = 0.0;
+    const int side = cand & 1, tr = (cand >> 1) & 1;
+    const int64_t se = side ? sb : sa;
+    const double l0 = lo[se], h0 = hi[se];
+    const double delta = fmax(4.0 * kEps * fabs(0.5 * (l0 + h0)), h0 - l0) + (double)tr * backoff;
+    sigma = side ? h0 + delta : l0 - delta;
+  }
+  if (live) {
+    off = (long long)atomicAdd(&C->pool_used, (unsigned long long)n);
+    if ((unsigned long long)off + (unsigned long long)n > pool_cap) {
+      set_status(C, 3);
+      off = -1;
+    }
+  }
+  const bool run = live && off >= 0;
+  const Rep* R = wave_uniform(pool + par.rep);
+  Rep* Q = pool + (run ? off : 0);
+  double sv = -sigma;
+  double gmax = 0.0;
+  bool fin = true;
+  for (int i = 0; i + 1 < n; ++i) {
+    const double D = R[i].D, L = R[i].L, LD = R[i].LD;
+    const double dp = D + sv;
+    const double lp = LD * rcp_nr2(dp);
+    const double ld = lp * dp;
+    if (run) {
+      Q[i].D = dp;
+      Q[i].L = lp;
+      Q[i].LD = ld;
+      Q[i].LLD = ld * lp;
+    }
+    sv = fma(lp * L, sv, -sigma);
+    fin = fin && isfinite(dp) && isfinite(lp);
+    gmax = fmax(gmax, fabs(dp));
+  }
+  const double dn = R[n - 1].D + sv;
+  if (run) {
+    Q[n - 1].D = dn;
+    Q[n - 1].L = 0.0;
+    Q[n - 1].LD = 0.0;
+    Q[n - 1].LLD = 0.0;
+    atomicAdd(&C->qds_steps, (unsigned long long)n);
+    atomicAdd(&C->child_steps, (unsigned long long)n);
+  }
+  fin = fin && isfinite(dn);
+  gmax = fmax(gmax, fabs(dn));
+  growth = (run && fin) ? gmax : INFINITY;
+  double gr[4], sg[4];
+  long long of[4];
+  for (int k = 0; k < 4; ++k) {
+    gr[k] = __shfl(growth, k, 64);
+    sg[k] = __shfl(sigma, k, 64);
+    of[k] = __shfl(off, k, 64);
+  }
+  if (cand != 0) return;
+  const double bound = kGrowthBound * (blk.gu - blk.gl);
+  int pick = -1;
+  for (int k = 0; k < 4 && pick < 0; ++k)
+    if (of[k] >= 0 && gr[k] <= bound) pick = k;
+  if (pick < 0) {
+    atomicAdd(&C->child_reject, 1ull);
+    double best = INFINITY;
+    for (int k = 0; k < 4; ++k)
+      if (of[k] >= 0 && gr[k] < best) {
+        best = gr[k];
+        pick = k;
+      }
+  }
+  Node nd;
+  nd.blk = par.blk;
+  nd.parent = cl.node;
+  nd.f = cl.f;
+  nd.l = cl.l;
+  nd.gapl = cl.gapl;
+  nd.gapr = cl.gapr;
+  nd.pad = 0;
+  if (pick < 0) {
+    set_status(C, 1);
+    nd.rep = -1;
+    nd.acc = par.acc;
+    nd.sigma = 0.0;
+    nd.depth = -1;
+  } else {
+    nd.rep = of[pick];
+    nd.acc = par.acc + sg[pick];
+    nd.sigma = sg[pick];
+    nd.depth = par.depth + 1;
+    atomicMax(&C->max_depth, nd.depth);
+  }
+  N[node_base + c] = nd;
+}
+
+// move the cluster's brackets into the child's frame (or, without a child,
+// hand its wanted eigenvalues to the parent as singletons)
+__global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N, int node_base,
+                        const Cluster* __restrict__ clusters, const int64_t* __restrict__ scol,
+                        double* __restrict__ lo, double* __restrict__ hi, int32_t* __restrict__ clo,
+                        int32_t* __restrict__ chi, int32_t* __restrict__ snode, uint32_t* __restrict__ sflag,
+                        int refine_all) {
+  const int c = blockIdx.x;
+  const Node nd = N[node_base + c];
+  const Block blk = B[nd.blk];
+  for (int j = nd.f + (int)threadIdx.x; j <= nd.l; j += blockDim.x) {
+    const int64_t s = blk.row0 + j - 1;
+    uint32_t fl = sflag[s] & ~(F_ACTIVE | F_RUNSTART);
+    if (nd.depth < 0) {
+      if (scol[s] >= 0) fl |= F_SINGLETON;
+      sflag[s] = fl;
+      continue;
+    }
+    // the child's eigenvalue is the parent's minus sigma up to the effect of the
+    // relative perturbations of the mixed stable transform (at most O(n eps)
+    // relative to the parent's eigenvalue): a generous pad, validated by counts
+    // only when the bracket is refined
+    const double l0 = lo[s], h0 = hi[s];
+    const double pad = 4.0 * (double)blk.n * kEps * (fabs(l0) + fabs(h0)) + 4.0 * kEps * fabs(nd.sigma);
+    lo[s] = (l0 - nd.sigma) - pad;
+    hi[s] = (h0 - nd.sigma) + pad;
+    clo[s] = -1;
+    chi[s] = -1;
+    snode[s] = node_base + c;
+    sflag[s] = (fl & ~(F_ACCURATE | F_NEEDS_REFINE)) | F_ACTIVE | (refine_all ? F_NEEDS_REFINE : 0u);
+  }
+}
+
+__global__ void k_clear_active(int64_t ntot, uint32_t* __restrict__ sflag) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  sflag[s] &= ~(F_ACTIVE | F_RUNSTART);
+}
+
+// ---------------------------------------------------------------------------
+// 8. eigenvectors of singletons: one lane per eigenvector, 64 consecutive slots
+//    per wavefront.  Per-lane work vectors live in a per-wavefront scratch area
+//    laid out [row][lane] so every lockstep access is one contiguous 512-byte
+//    line.  Twisted factorization of L D L^T - lam I:
+//      top-down   s_1 = -lam, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - lam
+//      bottom-up  p_n = D_n - lam, D-_{i+1} = LLD_i + p_{i+1}, t = D_i / D-_{i+1},
+//                 U-_i = L_i t, p_i = p_{i+1} t - lam
+//      twist      gamma_k = s_k + p_k + lam, r = argmin |gamma_k|
+//      solve      z_r = 1, z_i = -L+_i z_{i+1} (i < r), z_{i+1} = -U-_i z_i (i >= r)
+//    then lam <- lam + gamma_r / ||z||^2 (Rayleigh quotient) until converged.
+
+constexpr int kVecLanes = 64;
+constexpr int kVecRows = 16;  // rows per LDS transpose tile
+
+struct VecState {
+  double lam, lo, hi;
+  double lam_out;
+  double nrm;    // ||z||^2 of the committed solve
+  double zmaxv;  // signed largest-magnitude entry of the committed solve
+  long long qsteps;
+  int rq;
+  bool fallback;
+};
+
+// Rayleigh-quotient iteration on twisted factorizations for the lanes with
+// `solve` set; z of the last solve is left in Bv ([row][lane] layout).  All
+// lanes run the lockstep loops; per-lane results are committed only by lanes
+// still iterating.
+template <bool UNI>
+__device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n, int nmax, double pivmin,
+                                   double* __restrict__ A, double* __restrict__ Bv, int lane, VecState& V) {
+  bool conv = !solve;
+  bool last = false;
+  for (int it = 0; it <= kMaxRqi + 1; ++it) {
+    const bool go = solve && !conv;
+    // wave-uniform trip count: every lane runs the lockstep loops below
+    if (__ballot(go) == 0) break;
+    if (go && it >= kMaxRqi && !last) {  // last pass: fall back to the bracket midpoint
+      last = true;
+      V.fallback = true;
+      V.lam = 0.5 * (V.lo + V.hi);
+    }
+    const double lam = V.lam;
+    // top-down stationary transform; s_i stored in A
+    double sv = -lam;
+    for (int i = 0; i + 1 < nmax; ++i) {
+      if (go && i + 1 < n) {
+        A[(int64_t)i * kVecLanes + lane] = sv;
+        const double D = R[i].D, L = R[i].L, LD = R[i].LD, LLD = R[i].LLD;
+        double dp = D + sv;
+        dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+        const double lp = (c_diag_flags & 1) ? LD / dp : LD * rcp_nr2(dp);
+        double tt = lp * L * sv;
+        tt = (lp == 0.0) ? LLD : tt;
+        sv = tt - lam;
+      }
+    }
+    if (go) A[(int64_t)(n - 1) * kVecLanes + lane] = sv;
+    // bottom-up progressive transform; U-_i stored in Bv; twist index
+    double pv = go ? R[n - 1].D - lam : 0.0;
+    double gmin = INFINITY;
+    int r = -1;
+    if (go) {
+      const double g = A[(int64_t)(n - 1) * kVecLanes + lane] + pv + lam;
+      if (isfinite(g)) {
+        gmin = g;
+        r = n - 1;
+      }
+    }
+    for (int i = nmax - 2; i >= 0; --i) {
+      if (go && i <= n - 2) {
+        const double D = R[i].D, L = R[i].L, LLD = R[i].LLD;
+        double dm = LLD + pv;
+        dm = (fabs(dm) < pivmin) ? -pivmin : dm;
+        const double tt = (c_diag_flags & 1) ? D / dm : D * rcp_nr2(dm);
+        Bv[(int64_t)i * kVecLanes + lane] = L * tt;
+        double pn = pv * tt - lam;
+        pn = (tt == 0.0) ? D - lam : pn;
+        pv = pn;
+        const double g = A[(int64_t)i * kVecLanes + lane] + pv + lam;
+        if (isfinite(g) && !(fabs(g) > fabs(gmin))) {
+          gmin = g;
+          r = i;
+        }
+      }
+    }
+    if (r < 0) {
+      r = 0;
+      gmin = 0.0;
+    }
+    // solve downward from the twist (z_i stored in Bv in place of U-_i)
+    double zc = 0.0, zp = 0.0;
+    double nrm = 1.0, zmaxv = 1.0;
+    int imax = r;
+    for (int i = 0; i + 1 < nmax; ++i) {
+      if (go && i + 1 < n && i >= r) {
+        if (i == r) zc = 1.0;
+        const double u = Bv[(int64_t)i * kVecLanes + lane];
+        Bv[(int64_t)i * kVecLanes + lane] = zc;
+        double zn;
+        if (zc != 0.0 || i == r) {
+          zn = -u * zc;
+        } else {
+          const double ldi = R[i].LD;
+          zn = (ldi != 0.0) ? -div_nr(R[i - 1].LD, ldi) * zp : 0.0;
+        }
+        zn = isfinite(zn) ? zn : 0.0;
+        zp = zc;
+        zc = zn;
+        nrm += zn * zn;
+        if (fabs(zn) > fabs(zmaxv)) {
+          zmaxv = zn;
+          imax = i + 1;
+        }
+      }
+    }
+    if (go) Bv[(int64_t)(n - 1) * kVecLanes + lane] = (r == n - 1) ? 1.0 : zc;
+    // solve upward from the twist, L+_i recomputed from the stored s_i
+    double z1 = 1.0, z2 = 0.0;
+    for (int i = nmax - 2; i >= 0; --i) {
+      if (go && i < r) {
+        double zi;
+        if (z1 != 0.0 || i + 2 > r) {
+          const double D = R[i].D, LD = R[i].LD;
+          double dp = D + A[(int64_t)i * kVecLanes + lane];
+          dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+          zi = -((c_diag_flags & 1) ? LD / dp : LD * rcp_nr2(dp)) * z1;
+        } else {
+          const double ldi = R[i].LD;
+          zi = (ldi != 0.0) ? -div_nr(R[i + 1].LD, ldi) * z2 : 0.0;
+        }
+        zi = isfinite(zi) ? zi : 0.0;
+        Bv[(int64_t)i * kVecLanes + lane] = zi;
+        z2 = z1;
+        z1 = zi;
+        nrm += zi * zi;
+        if (fabs(zi) > fabs(zmaxv) || (fabs(zi) == fabs(zmaxv) && i < imax)) {
+          zmaxv = zi;
+          imax = i;
+        }
+      }
+    }
+    if (go) {
+      V.qsteps += 4ll * n;
+      V.rq++;
+      V.nrm = nrm;
+      V.zmaxv = zmaxv;
+      const double corr = gmin / nrm;
+      const double resid = fabs(gmin) / sqrt(nrm);
+      const double lamc = lam + corr;
+      const bool inside = (lamc >= V.lo && lamc <= V.hi);
+      const bool strict = (c_diag_flags & 2) != 0;
+      const bool small = strict ? fabs(corr) <= 0.25 * kEps * fabs(lam)
+                                : (resid <= 2.0 * (double)n * kEps * fabs(lam) || fabs(corr) <= 2.0 * kEps * fabs(lam));
+      if (last || small) {
+        conv = true;
+        V.lam_out = inside ? lamc : lam;
+      } else if (!inside) {
+        // correction leaves the bracket: one last pass at the midpoint
+        V.lam = 0.5 * (V.lo + V.hi);
+        last = true;
+        V.fallback = true;
+      } else {
+        V.lam = lamc;
+      }
+    }
+  }
+  if (solve && !conv) V.lam_out = V.lam;
+}
+
+__global__ void __launch_bounds__(64) k_vectors(
+    const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
+    const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
+    const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
+    const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
+    const Rep* __restrict__ pool, const double* __restrict__ ds, double* __restrict__ scratch,
+    double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
+  __shared__ double tile[kVecLanes][kVecRows + 1];
+  __shared__ int64_t s_col[kVecLanes];
+  __shared__ int64_t s_zoff[kVecLanes];
+  __shared__ int s_n[kVecLanes];
+  __shared__ int64_t s_lrow0[kVecLanes];
+  __shared__ int64_t s_pn[kVecLanes];
+  const int lane = threadIdx.x;
+  const int ci = blockIdx.x;
+  if (ci >= nchunks) return;
+  const int64_t chunk = chunks[ci];
+  const int64_t s = chunk * kVecLanes + lane;
+  double* A = scratch + chunk_off[ci];
+  bool act = false;
+  if (s < ntot) act = (sflag[s] & F_SINGLETON) && scol[s] >= 0;
+  const uint64_t am = __ballot(act);
+  if (am == 0) return;
+  const int64_t sf = __shfl(s, first_lane(am), 64);
+  const int64_t ss = act ? s : sf;  // idle lanes shadow a valid slot
+  const int64_t col = act ? scol[s] : -1;
+  const Block blk = B[sblk[ss]];
+  const Node nd = N[snode[ss]];
+  const int n = blk.n;
+  int nmax = act ? n : 0;
+  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+  double* Bv = A + (int64_t)nmax * kVecLanes;  // second work vector
+  VecState V;
+  V.lo = lo_a[ss];
+  V.hi = hi_a[ss];
+  V.lam = 0.5 * (V.lo + V.hi);
+  V.lam_out = V.lam;
+  V.nrm = 1.0;
+  V.zmaxv = 1.0;
+  V.qsteps = 0;
+  V.rq = 0;
+  V.fallback = false;
+  const bool solve = act && n > 1;
+  if (act && n == 1) Bv[lane] = 1.0;
+  const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
+  if (__ballot(nd.rep != rep0) == 0) {
+    const Rep* R = wave_uniform(pool + nd.rep);
+    twisted_rqi<true>(solve, R, __builtin_amdgcn_readfirstlane(n), nmax, blk.pivmin, A, Bv, lane, V);
+  } else {
+    twisted_rqi<false>(solve, pool + nd.rep, n, nmax, blk.pivmin, A, Bv, lane, V);
+  }
+  double scale = 1.0;
+  if (solve) {
+    scale = 1.0 / sqrt(V.nrm);
+    if (V.zmaxv < 0.0) scale = -scale;
+  }
+  // eigenvalue
+  if (act) {
+    const Problem pr = P[blk.prob];
+    const double wv = (n == 1) ? ds[s] / pr.scale : (nd.acc + V.lam_out) / pr.scale;
+    w_out[pr.off + col] = wv;
+    s_col[lane] = col;
+    s_zoff[lane] = pr.zoff + col * pr.ldz;
+    s_n[lane] = n;
+    s_lrow0[lane] = blk.lrow0;
+    s_pn[lane] = pr.n;
+  } else {
+    s_col[lane] = -1;
+    s_n[lane] = 0;
+    s_pn[lane] = 0;
+  }
+  __syncthreads();
+  if (Z != nullptr) {
+    // write z * scale into column-major Z through an LDS transpose: each pass
+    // stages 16 rows x 64 columns, then every column gets one contiguous
+    // 128-byte segment (16 lanes per column, 4 columns per instruction)
+    for (int r0 = 0; r0 < nmax; r0 += kVecRows) {
+      for (int k = 0; k < kVecRows; ++k) {
+        const int i = r0 + k;
+        double v = 0.0;
+        if (act && i < n) v = Bv[(int64_t)i * kVecLanes + lane] * scale;
+        tile[lane][k] = v;
+      }
+      __syncthreads();
+      const int rr = lane & (kVecRows - 1);
+      for (int cgrp = 0; cgrp < kVecLanes; cgrp += 4) {
+        const int cl = cgrp + (lane >> 4);
+        const int nn = s_n[cl];
+        const int i = r0 + rr;
+        if (s_col[cl] >= 0 && i < nn) Z[s_zoff[cl] + s_lrow0[cl] + i] = tile[cl][rr];
+      }
+      __syncthreads();
+    }
+    // rows of the problem outside the block are exact zeros
+    for (int cl = 0; cl < kVecLanes; ++cl) {
+      if (s_col[cl] < 0) continue;
+      const int64_t pn = s_pn[cl];
+      const int64_t r0 = s_lrow0[cl];
+      const int64_t r1 = r0 + s_n[cl];
+      if (r0 == 0 && r1 == pn) continue;
+      for (int64_t i = lane; i < pn; i += kVecLanes)
+        if (i < r0 || i >= r1) Z[s_zoff[cl] + i] = 0.0;
+    }
+  }
+  if (act) {
+    atomicAdd(&C->qds_steps, (unsigned long long)V.qsteps);
+    atomicAdd(&C->vec_rows, (unsigned long long)(V.qsteps / 4));
+    if (Z != nullptr) atomicAdd(&C->z_entries, (unsigned long long)s_pn[lane]);
+    atomicAdd(&C->rqi, (unsigned long long)V.rq);
+    atomicAdd(&C->singletons, 1ull);
+    if (V.fallback) atomicAdd(&C->fallbacks, 1ull);
+  }
+}
+
+// scratch rows each 64-slot chunk needs (0: no singleton to compute)
+__global__ void k_chunk_rows(const Block* __restrict__ B, int64_t ntot, const int32_t* __restrict__ sblk,
+                             const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                             int32_t* __restrict__ rows) {
+  const int64_t s = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  int v = 0;
+  if (s < ntot && (sflag[s] & F_SINGLETON) && scol[s] >= 0) v = B[sblk[s]].n;
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if (threadIdx.x == 0) rows[blockIdx.x] = v;
+}
+
+// ---------------------------------------------------------------------------
+// 9. output order: eigenvalues ascending within each problem (swaps are only
+//    ever needed between near-equal values from different leaves or blocks)
+
+__global__ void k_check_sorted(const Problem* __restrict__ P, int nprob, const double* __restrict__ w,
+                               int32_t* __restrict__ bad, Counters* __restrict__ C) {
+  const int p = blockIdx.x;
+  if (p >= nprob) return;
+  const Problem pr = P[p];
+  int flag = 0;
+  for (int64_t c = threadIdx.x; c + 1 < pr.m; c += blockDim.x)
+    if (w[pr.off + c] > w[pr.off + c + 1]) flag = 1;
+  if (flag) {
+    bad[p] = 1;
+    atomicExch(&C->unsorted, 1);
+  }
+}
+
+// insertion sort of one problem's w with the matching column permutation; the
+// columns are then moved through a scratch copy
+__global__ void k_sort_problem(const Problem* __restrict__ P, const int32_t* __restrict__ bad, double* __restrict__ w,
+                               int64_t* __restrict__ perm) {
+  const int p = blockIdx.x;
+  if (!bad[p] || threadIdx.x != 0) return;
+  const Problem pr = P[p];
+  double* wv = w + pr.off;
+  int64_t* pm = perm + pr.off;
+  for (int64_t c = 0; c < pr.m; ++c) pm[c] = c;
+  for (int64_t c = 1; c < pr.m; ++c) {
+    const double x = wv[c];
+    const int64_t px = pm[c];
+    int64_t k = c - 1;
+    while (k >= 0 && wv[k] > x) {
+      wv[k + 1] = wv[k];
+      pm[k + 1] = pm[k];
+      --k;
+    }
+    wv[k + 1] = x;
+    pm[k + 1] = px;
+  }
+}
+
+// Z_new[:, c] = Z_old[:, perm[c]], following the permutation's cycles with one
+// temporary column (tmp, n doubles at the problem's slot offset)
+__global__ void k_permute_cols(const Problem* __restrict__ P, const int32_t* __restrict__ bad,
+                               int64_t* __restrict__ perm, double* __restrict__ tmp, double* __restrict__ Z) {
+  const int p = blockIdx.x;
+  if (!bad[p]) return;
+  const Problem pr = P[p];
+  int64_t* pm = perm + pr.off;
+  double* t = tmp + pr.off;
+  __shared__ int64_t s_next;
+  for (int64_t c0 = 0; c0 < pr.m; ++c0) {
+    if (pm[c0] < 0 || pm[c0] == c0) continue;  // uniform: every thread reads the same value
+    for (int64_t i = threadIdx.x; i < pr.n; i += blockDim.x) t[i] = Z[pr.zoff + c0 * pr.ldz + i];
+    int64_t c = c0;
+    for (int64_t guard = 0; guard <= pr.m; ++guard) {
+      __syncthreads();
+      if (threadIdx.x == 0) s_next = pm[c];
+      __syncthreads();
+      const int64_t src = s_next;
+      if (threadIdx.x == 0) pm[c] = -1 - pm[c];
+      if (src == c0) {
+        for (int64_t i = threadIdx.x; i < pr.n; i += blockDim.x) Z[pr.zoff + c * pr.ldz + i] = t[i];
+        break;
+      }
+      for (int64_t i = threadIdx.x; i < pr.n; i += blockDim.x)
+        Z[pr.zoff + c * pr.ldz + i] = Z[pr.zoff + src * pr.ldz + i];
+      c = src;
+    }
+    __syncthreads();
+  }
+}
+
+// eigenvalues only: the root-level values
+__global__ void k_values_only(const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
+                              int64_t ntot, const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode,
+                              const int64_t* __restrict__ scol, const double* __restrict__ lo,
+                              const double* __restrict__ hi, const double* __restrict__ ds, double* __restrict__ w) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int64_t col = scol[s];
+  if (col < 0) return;
+  const Block blk = B[sblk[s]];
+  const Problem pr = P[blk.prob];
+  const double v = (blk.n == 1) ? ds[s] : N[snode[s]].acc + 0.5 * (lo[s] + hi[s]);
+  w[pr.off + col] = v / pr.scale;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+
+#define GRID1(n, t) dim3((unsigned)(((n) + (t)-1) / (t))), dim3(t)
+
+void launch_prep(hipStream_t st, Problem* P, int nprob, const int64_t* poff, int64_t ntot, const double* d,
+                 const double* e, int32_t* sprob, double* ds, double* es, int32_t* flag) {
+  if (ntot == 0) return;
+  hipLaunchKernelGGL(k_prep_max, GRID1(ntot, 256), 0, st, P, nprob, poff, ntot, d, e, sprob);
+  hipLaunchKernelGGL(k_prep_scale, GRID1(ntot, 256), 0, st, P, poff, ntot, d, e, sprob, ds, es);
+  hipLaunchKernelGGL(k_split_flags, GRID1(ntot, 256), 0, st, P, poff, ntot, sprob, es, flag);
+}
+
+void launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int32_t* tile_sum, int64_t n, int32_t* total) {
+  if (n == 0) {
+    (void)hipMemsetAsync(total, 0, sizeof(int32_t), st);
+    return;
+  }
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, in, out, tile_sum, n);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, tile_sum, ntiles, total);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, out, tile_sum, n);
+}
+
+void launch_blocks(hipStream_t st, Problem* P, const int64_t* poff, const int32_t* flag, const int32_t* excl,
+                   int64_t ntot, int nblk, const int32_t* sprob, int64_t* bstart, int32_t* sblk, Block* B) {
+  hipLaunchKernelGGL(k_blocks, GRID1(ntot, 256), 0, st, flag, excl, ntot, bstart, sblk);
+  hipLaunchKernelGGL(k_blocks2, GRID1(nblk, 64), 0, st, P, poff, bstart, nblk, ntot, sprob, B);
+}
+
+void launch_root(hipStream_t st, Problem* P, Block* B, Node* N, int nblk, const double* ds, const double* es,
+                 Rep* pool, Counters* C, int grid_density) {
+  hipLaunchKernelGGL(k_root, dim3(nblk), dim3(256), 0, st, P, B, N, ds, es, pool, C, grid_density);
+}
+
+void launch_grid(hipStream_t st, const Block* B, int nblk, const int64_t* goff, int64_t gtot, const Rep* pool,
+                 int32_t* gcnt) {
+  hipLaunchKernelGGL(k_grid, GRID1(gtot, 64), 0, st, B, nblk, goff, gtot, pool, gcnt);
+}
+
+void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t ntot, const int32_t* sblk,
+                   const int32_t* gcnt, double* lo, double* hi, int32_t* clo, int32_t* chi, int32_t* snode,
+                   uint32_t* sflag, Counters* C) {
+  hipLaunchKernelGGL(k_assign, GRID1(ntot, 256), 0, st, B, goff, ntot, sblk, gcnt, lo, hi, clo, chi, snode, sflag,
+                     C);
+}
+
+void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
+                   const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
+                   uint32_t* sflag, Counters* C, int lanes) {
+  // `lanes` lanes per eigenvalue: 64 / lanes eigenvalues per wavefront
+  const unsigned g4 = (unsigned)((ntot + 15) / 16), g2 = (unsigned)((ntot + 31) / 32),
+                 g1 = (unsigned)((ntot + 63) / 64);
+  if (lanes >= 4)
+    hipLaunchKernelGGL(k_refine<4>, dim3(g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+  else if (lanes == 2)
+    hipLaunchKernelGGL(k_refine<2>, dim3(g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+  else
+    hipLaunchKernelGGL(k_refine<1>, dim3(g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+}
+
+void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag) {
+  hipLaunchKernelGGL(k_mark_leaf, GRID1(ntot, 256), 0, st, ntot, scol, sflag);
+}
+
+void launch_columns(hipStream_t st, const Problem* P, Block* B, int nblk, const Node* N, int64_t ntot,
+                    const int32_t* sblk, const double* lo, const double* hi, double* val, int64_t* scol,
+                    bool multi) {
+  if (multi) hipLaunchKernelGGL(k_cummax, GRID1(nblk, 64), 0, st, B, nblk, N, lo, hi, P, val);
+  hipLaunchKernelGGL(k_columns, GRID1(ntot, 256), 0, st, P, B, ntot, sblk, val, scol);
+  if (multi) hipLaunchKernelGGL(k_block_wanted, GRID1(nblk, 64), 0, st, B, nblk, P, scol);
+}
+
+void launch_cls_flags(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
+                      const int32_t* snode, const double* lo, const double* hi, uint32_t* sflag, int32_t* runflag,
+                      Counters* C) {
+  hipLaunchKernelGGL(k_cls_flags, GRID1(ntot, 256), 0, st, B, N, ntot, sblk, snode, lo, hi, sflag, runflag, C);
+}
+
+void launch_cls_compact(hipStream_t st, int64_t ntot, const int32_t* runflag, const int32_t* runid, int64_t* runs) {
+  hipLaunchKernelGGL(k_cls_compact, GRID1(ntot, 256), 0, st, ntot, runflag, runid, runs);
+}
+
+void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, const int64_t* runs,
+                     const int32_t* sblk, const int32_t* snode, const double* lo, const double* hi,
+                     const int64_t* scol, uint32_t* sflag, Cluster* clusters, int max_clusters, Counters* C) {
+  if (nruns == 0) return;
+  hipLaunchKernelGGL(k_cls_runs, GRID1(nruns, 64), 0, st, B, N, nruns, runs, sblk, snode, lo, hi, scol, sflag,
+                     clusters, max_clusters, C);
+}
+
+void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
+                  const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C) {
+  hipLaunchKernelGGL(k_child, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo,
+                     hi, pool, pool_cap, C);
+}
+
+void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
+                  const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
+                  int32_t* snode, uint32_t* sflag, bool refine_all) {
+  hipLaunchKernelGGL(k_shift, dim3(nclusters), dim3(256), 0, st, B, N, node_base, clusters, scol, lo, hi, clo, chi,
+                     snode, sflag, refine_all ? 1 : 0);
+}
+
+void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag) {
+  hipLaunchKernelGGL(k_clear_active, GRID1(ntot, 256), 0, st, ntot, sflag);
+}
+
+void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
+                       const int64_t* scol, int32_t* rows) {
+  const int64_t nch = (ntot + 63) / 64;
+  hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)nch), dim3(64), 0, st, B, ntot, sblk, sflag, scol, rows);
+}
+
+void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
+                    const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
+                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const Rep* pool,
+                    const double* ds, double* scratch, double* w, double* Z, Counters* C) {
+  if (nchunks == 0) return;
+  hipLaunchKernelGGL(k_vectors, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, sblk,
+                     snode, sflag, scol, lo, hi, pool, ds, scratch, w, Z, C);
+}
+
+void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C) {
+  hipLaunchKernelGGL(k_check_sorted, dim3(nprob), dim3(256), 0, st, P, nprob, w, bad, C);
+}
+
+void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t* bad, double* w, int64_t* perm,
+                     double* tmp, double* Z) {
+  hipLaunchKernelGGL(k_sort_problem, dim3(nprob), dim3(64), 0, st, P, bad, w, perm);
+  if (Z != nullptr) hipLaunchKernelGGL(k_permute_cols, dim3(nprob), dim3(256), 0, st, P, bad, perm, tmp, Z);
+}
+
+void launch_values_only(hipStream_t st, const Problem* P, const Block* B, const Node* N, int64_t ntot,
+                        const int32_t* sblk, const int32_t* snode, const int64_t* scol, const double* lo,
+                        const double* hi, const double* ds, double* w) {
+  hipLaunchKernelGGL(k_values_only, GRID1(ntot, 256), 0, st, P, B, N, ntot, sblk, snode, scol, lo, hi, ds, w);
+}
+
+}  // namespace mrrr

@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the CPU host and exports every entry point that
+include/mrrr.h declares (no compute calls without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mrrr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(mrrr_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
+                     "mrrr_status_string", "mrrr_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1205_2107_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmrrr.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) <= set(declared_functions())
+
+
+def test_host_side_argument_checks():
+    """negative return codes are decided on the host before any device work"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    r = _lib.MrrrRange()
+    r.kind = _lib.MRRR_ALL
+    assert lib.mrrr_step(-1, None, None, r, None, None, 1, None, None) == -1
+    assert lib.mrrr_step(5, None, None, r, None, None, 5, None, None) == -2
+    r.kind = 7
+    fake = ctypes.c_void_p(16)
+    assert lib.mrrr_step(5, fake, fake, r, fake, None, 5, None, None) == -4
+    r.kind = _lib.MRRR_INDEX
+    r.il, r.iu = 3, 2
+    assert lib.mrrr_step(5, fake, fake, r, fake, None, 5, None, None) == -4
+    r.kind = _lib.MRRR_ALL
+    assert lib.mrrr_step(5, fake, fake, r, fake, fake, 4, None, None) == -7
+    assert lib.mrrr_step(0, None, None, r, None, None, 1, None, None) == 0
+    assert lib.mrrr_status_string(4).decode() == "non-finite entry in d or e"
+    assert lib.mrrr_step_backward(-1, None, None, 1, None, None, 1, None, None, None) == -1
+
+
+def test_tuning_roundtrip():
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    t = _lib.MrrrTuning()
+    assert lib.mrrr_get_tuning(ctypes.byref(t)) == 0
+    old = t.grid_density
+    t.grid_density = 99
+    assert lib.mrrr_set_tuning(ctypes.byref(t)) == -1
+    t.grid_density = old
+    assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0
