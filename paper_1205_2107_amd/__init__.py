@@ -212,11 +212,10 @@ def get_tuning():
     t = MrrrTuning()
     _lib.check(_lib.load().mrrr_get_tuning(ctypes.byref(t)))
     return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
-            "vec_wave_slots": t.vec_wave_slots, "refine_levels": bool(t.reserved[0])}
+            "vec_wave_slots": t.vec_wave_slots}
 
 
-def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, refine_levels=None,
-               diag_flags=None):
+def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None):
     t = MrrrTuning()
     lib = _lib.load()
     _lib.check(lib.mrrr_get_tuning(ctypes.byref(t)))
@@ -226,10 +225,6 @@ def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, r
         t.refine_wave_slots = int(refine_wave_slots)
     if vec_wave_slots is not None:
         t.vec_wave_slots = int(vec_wave_slots)
-    if refine_levels is not None:
-        t.reserved[0] = 1 if refine_levels else 0
-    if diag_flags is not None:
-        t.reserved[1] = int(diag_flags)
     if lib.mrrr_set_tuning(ctypes.byref(t)) != 0:
         raise ValueError("tuning value out of range")
 

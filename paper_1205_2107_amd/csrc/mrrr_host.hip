@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -65,12 +66,12 @@ struct Workspace {
   std::mutex mu;
   DevBuf problems, poff, sprob, ds, es, flag, excl, tiles, total, bstart, sblk, blocks, goff, nodes, pool, gcnt, lo,
       hi, clo, chi, snode, sflag, scol, val, runflag, runid, runs, clusters, counters, chunkrows, chunks, chunkoff,
-      scratch, bad, perm, tmp;
+      scratch, bad, perm, tmp, sgap;
   size_t total_bytes() const {
     const DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                            &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
                            &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad,
-                           &perm, &tmp};
+                           &perm, &tmp, &sgap};
     size_t t = 0;
     for (auto* b : all) t += b->bytes;
     return t;
@@ -79,7 +80,7 @@ struct Workspace {
     DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                      &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
                      &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad, &perm,
-                     &tmp};
+                     &tmp, &sgap};
     for (auto* b : all) {
       if (b->p) (void)hipFree(b->p);
       b->p = nullptr;
@@ -153,7 +154,6 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     tune = g_tune;
   }
   const int G = tune.grid_density;
-  set_diag_flags(tune.reserved[1]);
   std::vector<int64_t> poff(nprob + 1, 0);
   for (int p = 0; p < nprob; ++p) poff[p + 1] = poff[p] + probs[p].n;
   const int64_t ntot = poff[nprob];
@@ -243,6 +243,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   ENS(sflag, sizeof(uint32_t) * ntot);
   ENS(scol, sizeof(int64_t) * ntot);
   ENS(val, sizeof(double) * ntot);
+  ENS(sgap, sizeof(double) * ntot);
   ENS(runflag, sizeof(int32_t) * ntot);
   ENS(runid, sizeof(int32_t) * ntot);
   ENS(runs, sizeof(int64_t) * (ntot + 1));
@@ -304,7 +305,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       launch_cls_compact(st, ntot, P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int64_t>(W.runs));
       launch_cls_runs(st, dB, P_<Node>(W.nodes), nruns, P_<int64_t>(W.runs), P_<int32_t>(W.sblk),
                       P_<int32_t>(W.snode), P_<double>(W.lo), P_<double>(W.hi), P_<int64_t>(W.scol),
-                      P_<uint32_t>(W.sflag), P_<Cluster>(W.clusters), max_clusters, dC);
+                      P_<uint32_t>(W.sflag), P_<double>(W.sgap), P_<Cluster>(W.clusters), max_clusters, dC);
       launch_clear_active(st, ntot, P_<uint32_t>(W.sflag));
       Counters hc;
       HIP_TRY(hipMemcpyAsync(&hc, W.counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -313,9 +314,9 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       rep->levels = level + 1;
       const int ncl = std::min(hc.nclusters, max_clusters);
       if (ncl == 0) break;
-      // capacity for the new nodes and four candidate children per cluster
+      // capacity for the new nodes and one child representation per cluster
       if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
-      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + 4 * (size_t)hc.cluster_rows;
+      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + (size_t)hc.cluster_rows;
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
         if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
         dpool = P_<Rep>(W.pool);
@@ -333,14 +334,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       prof.end();
       launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
                    P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
-                   P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), tune.reserved[0] != 0);
-      if (tune.reserved[0] != 0) {
-        prof.begin(MRRR_K_REFINE);
-        launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
-                      P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
-                      P_<uint32_t>(W.sflag), dC, lanes);
-        prof.end();
-      }
+                   P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), P_<double>(W.sgap));
       HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, nclusters), 0, sizeof(int32_t), st));
       HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, cluster_rows), 0, sizeof(unsigned long long),
                              st));
@@ -393,7 +387,8 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       prof.begin(MRRR_K_VECTORS);
       launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff), (int)(i1 - i0),
                      ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
-                     P_<double>(W.lo), P_<double>(W.hi), dpool, P_<double>(W.ds), P_<double>(W.scratch), w, Z, dC);
+                     P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
+                     P_<double>(W.scratch), w, Z, dC);
       prof.end();
       // host vectors are reused by the next batch: wait for the copies
       HIP_TRY(hipStreamSynchronize(st));
@@ -418,6 +413,54 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   HIP_TRY(hipGetLastError());
   rep->c = hc;
   rep->ws_bytes = W.total_bytes();
+  // diagnostics: MRRR_DEBUG_DUMP=<file> writes the per-slot tree state
+  if (const char* path = getenv("MRRR_DEBUG_DUMP")) {
+    const int nnodes = nblk + rep->nodes;
+    std::vector<int32_t> hn(ntot);
+    std::vector<uint32_t> hf(ntot);
+    std::vector<double> hl(ntot), hh(ntot), hg(ntot);
+    std::vector<Node> nodes(nnodes);
+    HIP_TRY(hipMemcpy(hg.data(), W.sgap.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hn.data(), W.snode.p, sizeof(int32_t) * ntot, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hf.data(), W.sflag.p, sizeof(uint32_t) * ntot, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hl.data(), W.lo.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hh.data(), W.hi.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(nodes.data(), W.nodes.p, sizeof(Node) * nnodes, hipMemcpyDeviceToHost));
+    if (FILE* f = fopen(path, "wb")) {
+      const int64_t hdr[3] = {ntot, nnodes, (int64_t)sizeof(Node)};
+      fwrite(hdr, sizeof(hdr), 1, f);
+      fwrite(hn.data(), sizeof(int32_t), ntot, f);
+      fwrite(hf.data(), sizeof(uint32_t), ntot, f);
+      fwrite(hl.data(), sizeof(double), ntot, f);
+      fwrite(hh.data(), sizeof(double), ntot, f);
+      fwrite(nodes.data(), sizeof(Node), nnodes, f);
+      fwrite(hg.data(), sizeof(double), ntot, f);
+      // representation rows (D, L, LD, LLD) of the leaf nodes of the slots
+      // listed in MRRR_DEBUG_DUMP_SLOTS (comma separated)
+      std::vector<int> want;
+      if (const char* nl = getenv("MRRR_DEBUG_DUMP_SLOTS")) {
+        for (const char* q = nl; *q;) {
+          const long long sl = atoll(q);
+          if (sl >= 0 && sl < ntot) want.push_back(hn[sl]);
+          while (*q && *q != ',') ++q;
+          if (*q == ',') ++q;
+        }
+      }
+      std::sort(want.begin(), want.end());
+      want.erase(std::unique(want.begin(), want.end()), want.end());
+      for (int k : want) {
+        if (k < 0 || k >= nnodes || nodes[k].rep < 0) continue;
+        Block hb;
+        HIP_TRY(hipMemcpy(&hb, (Block*)W.blocks.p + nodes[k].blk, sizeof(Block), hipMemcpyDeviceToHost));
+        std::vector<Rep> rows(hb.n);
+        HIP_TRY(hipMemcpy(rows.data(), (Rep*)W.pool.p + nodes[k].rep, sizeof(Rep) * hb.n, hipMemcpyDeviceToHost));
+        const int64_t h2[2] = {k, hb.n};
+        fwrite(h2, sizeof(h2), 1, f);
+        fwrite(rows.data(), sizeof(Rep), hb.n, f);
+      }
+      fclose(f);
+    }
+  }
   if (prof.on) {
     const double work[MRRR_K_COUNT] = {grid_work, 4.0 * (double)hc.sturm_steps, 5.0 * (double)hc.child_steps,
                                        15.0 * (double)hc.vec_rows, 0.0};

@@ -14,11 +14,6 @@
 
 namespace mrrr {
 
-// experiment switches (bit 0: IEEE division in twisted factorizations, bit 1:
-// stricter Rayleigh-quotient stop, bit 2: refine to 2 eps relative width)
-__constant__ int c_diag_flags;
-void set_diag_flags(int f) { (void)hipMemcpyToSymbol(HIP_SYMBOL(c_diag_flags), &f, sizeof(int)); }
-
 // ---------------------------------------------------------------------------
 // helpers
 
@@ -339,6 +334,7 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
     nd.l = n;
     nd.parent = -1;
     nd.pad = 0;
+    nd.growth = 0.0;
     N[b] = nd;
     if (pr.kind == 2) {
       atomicAdd((unsigned long long*)&P[p].m, (unsigned long long)(wu >= wl ? wu - wl + 1 : 0));
@@ -421,8 +417,7 @@ struct EigState {
 
 __device__ inline bool bracket_converged(double lo, double hi) {
   const double mid = 0.5 * (lo + hi);
-  const double f = (c_diag_flags & 4) ? 2.0 : 4.0;
-  return hi - lo <= f * kEps * fmax(fabs(lo), fabs(hi)) || mid <= lo || mid >= hi;
+  return hi - lo <= 4.0 * kEps * fmax(fabs(lo), fabs(hi)) || mid <= lo || mid >= hi;
 }
 
 template <int L>
@@ -663,6 +658,16 @@ __device__ inline bool rel_break(double lo_j, double hi_j, double lo_k, double h
   return (lo_k - hi_j) >= kRelgapTol * fmax(fabs(mj), fabs(mk));
 }
 
+// absolute gap of slot s to its neighbours within node nd (the node's outer gaps
+// at its ends), from the brackets of the node's frame
+__device__ inline double slot_gap(const Node& nd, int64_t row0, int64_t s, const double* __restrict__ lo,
+                                  const double* __restrict__ hi) {
+  const int j = (int)(s - row0) + 1;
+  const double gl = (j == nd.f) ? nd.gapl : lo[s] - hi[s - 1];
+  const double gr = (j == nd.l) ? nd.gapr : lo[s + 1] - hi[s];
+  return fmax(fmin(gl, gr), 0.0);
+}
+
 __global__ void k_cls_flags(const Block* __restrict__ B, const Node* __restrict__ N, int64_t ntot,
                             const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode,
                             const double* __restrict__ lo, const double* __restrict__ hi,
@@ -708,8 +713,8 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
                            const int64_t* __restrict__ runs, const int32_t* __restrict__ sblk,
                            const int32_t* __restrict__ snode, const double* __restrict__ lo,
                            const double* __restrict__ hi, const int64_t* __restrict__ scol,
-                           uint32_t* __restrict__ sflag, Cluster* __restrict__ clusters, int max_clusters,
-                           Counters* __restrict__ C) {
+                           uint32_t* __restrict__ sflag, double* __restrict__ sgap, Cluster* __restrict__ clusters,
+                           int max_clusters, Counters* __restrict__ C) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nruns) return;
   const int64_t s = runs[r];
@@ -725,13 +730,19 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
   const bool overlap = !(z < blk.wl || a > blk.wu);
   if (!overlap) return;
   if (a == z) {
-    if (scol[s] >= 0) sflag[s] |= F_SINGLETON;
+    if (scol[s] >= 0) {
+      sflag[s] |= F_SINGLETON;
+      sgap[s] = slot_gap(nd, blk.row0, s, lo, hi);
+    }
     return;
   }
   if (nd.depth + 1 > kMaxDepth) {
     set_status(C, 2);
     for (int64_t q = s; q <= e; ++q)
-      if (scol[q] >= 0) sflag[q] |= F_SINGLETON;
+      if (scol[q] >= 0) {
+        sflag[q] |= F_SINGLETON;
+        sgap[q] = slot_gap(nd, blk.row0, q, lo, hi);
+      }
     return;
   }
   const int k = atomicAdd(&C->nclusters, 1);
@@ -751,119 +762,153 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// 7. child representations: one wavefront per cluster; lanes 0..3 evaluate four
-//    candidate shifts (left/right end, then backed off) by the stationary qds
+// 7. child representations: one wavefront per cluster.  Pass 1: lanes evaluate
+//    kChildCand candidate shifts -- both ends of the cluster, each with margins
+//    growing geometrically from the end eigenvalue's bracket to half the outer
+//    gap -- by the stationary qds
 //      s_1 = -sigma, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - sigma
-//    reading the parent through the scalar cache.
+//    reading the parent through the scalar cache and keeping only the element
+//    growth max|D+_i|.  The closest shift whose growth is within the bound wins
+//    (ties between the two ends: the smaller growth); without one, the least
+//    growth.  Pass 2: four lanes repeat the chosen transform and store D, L, LD,
+//    LLD of each row as one contiguous 32-byte write.
+
+constexpr int kChildLevels = 8;
+constexpr int kChildCand = 2 * kChildLevels;
+
+__device__ inline double child_sigma(const Cluster& cl, const Block& blk, const double* __restrict__ lo,
+                                     const double* __restrict__ hi, int cand, bool* valid) {
+  const int64_t sa = blk.row0 + cl.f - 1, sb = blk.row0 + cl.l - 1;
+  const int side = cand & 1, lev = cand >> 1;
+  const int64_t se = side ? sb : sa;
+  const double l0 = lo[se], h0 = hi[se];
+  const double d0 = fmax(4.0 * kEps * fabs(0.5 * (l0 + h0)), h0 - l0);
+  const double avgap = (hi[sb] - lo[sa]) / (double)(cl.l - cl.f);
+  const double gside = side ? cl.gapr : cl.gapl;
+  const double dmax = fmin(0.5 * gside, fmax(2.0 * avgap, d0));
+  double delta = d0;
+  *valid = true;
+  if (lev > 0) {
+    if (!(dmax > d0)) {
+      *valid = false;
+    } else {
+      delta = d0 * pow(dmax / d0, (double)lev / (double)(kChildLevels - 1));
+    }
+  }
+  return side ? h0 + delta : l0 - delta;
+}
 
 __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
                                               int node_base, const Cluster* __restrict__ clusters,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
                                               Rep* __restrict__ pool, unsigned long long pool_cap,
                                               Counters* __restrict__ C) {
+  __shared__ double s_sigma;
+  __shared__ long long s_off;
   const int c = blockIdx.x;
-  const int cand = threadIdx.x;
+  const int lane = threadIdx.x;
   const Cluster cl = clusters[c];
   const Node par = N[cl.node];
   const Block blk = B[par.blk];
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
-  const bool live = cand < 4;
-  double sigma = 0.0, growth = INFINITY;
-  long long off = -1;
-  {
-    const int64_t sa = blk.row0 + cl.f - 1, sb = blk.row0 + cl.l - 1;
-    const double avgap = (hi[sb] - lo[sa]) / (double)(cl.l - cl.f);
-    double backoff = fmin(0.5 * avgap, 0.25 * fmin(cl.gapl, cl.gapr));
-    if (!(backoff > 0.0)) backoff = 0.0;
-    const int side = cand & 1, tr = (cand >> 1) & 1;
-    const int64_t se = side ? sb : sa;
-    const double l0 = lo[se], h0 = hi[se];
-    const double delta = fmax(4.0 * kEps * fabs(0.5 * (l0 + h0)), h0 - l0) + (double)tr * backoff;
-    sigma = side ? h0 + delta : l0 - delta;
-  }
-  if (live) {
-    off = (long long)atomicAdd(&C->pool_used, (unsigned long long)n);
-    if ((unsigned long long)off + (unsigned long long)n > pool_cap) {
-      set_status(C, 3);
-      off = -1;
-    }
-  }
-  const bool run = live && off >= 0;
   const Rep* R = wave_uniform(pool + par.rep);
-  Rep* Q = pool + (run ? off : 0);
-  double sv = -sigma;
-  double gmax = 0.0;
+  bool valid = false;
+  double sigma = 0.0;
+  if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
+  // pass 1: growth of every candidate
+  double sv = -sigma, gmax = 0.0;
   bool fin = true;
   for (int i = 0; i + 1 < n; ++i) {
     const double D = R[i].D, L = R[i].L, LD = R[i].LD;
     const double dp = D + sv;
     const double lp = LD * rcp_nr2(dp);
-    const double ld = lp * dp;
-    if (run) {
-      Q[i].D = dp;
-      Q[i].L = lp;
-      Q[i].LD = ld;
-      Q[i].LLD = ld * lp;
-    }
     sv = fma(lp * L, sv, -sigma);
     fin = fin && isfinite(dp) && isfinite(lp);
     gmax = fmax(gmax, fabs(dp));
   }
-  const double dn = R[n - 1].D + sv;
-  if (run) {
-    Q[n - 1].D = dn;
-    Q[n - 1].L = 0.0;
-    Q[n - 1].LD = 0.0;
-    Q[n - 1].LLD = 0.0;
-    atomicAdd(&C->qds_steps, (unsigned long long)n);
-    atomicAdd(&C->child_steps, (unsigned long long)n);
+  {
+    const double dn = R[n - 1].D + sv;
+    fin = fin && isfinite(dn);
+    gmax = fmax(gmax, fabs(dn));
   }
-  fin = fin && isfinite(dn);
-  gmax = fmax(gmax, fabs(dn));
-  growth = (run && fin) ? gmax : INFINITY;
-  double gr[4], sg[4];
-  long long of[4];
-  for (int k = 0; k < 4; ++k) {
-    gr[k] = __shfl(growth, k, 64);
-    sg[k] = __shfl(sigma, k, 64);
-    of[k] = __shfl(off, k, 64);
-  }
-  if (cand != 0) return;
-  const double bound = kGrowthBound * (blk.gu - blk.gl);
-  int pick = -1;
-  for (int k = 0; k < 4 && pick < 0; ++k)
-    if (of[k] >= 0 && gr[k] <= bound) pick = k;
-  if (pick < 0) {
-    atomicAdd(&C->child_reject, 1ull);
-    double best = INFINITY;
-    for (int k = 0; k < 4; ++k)
-      if (of[k] >= 0 && gr[k] < best) {
-        best = gr[k];
-        pick = k;
+  const double growth = (valid && fin) ? gmax : INFINITY;
+  double gr[kChildCand];
+#pragma unroll
+  for (int k = 0; k < kChildCand; ++k) gr[k] = __shfl(growth, k, 64);
+  if (lane == 0) {
+    const double bound = kGrowthBound * (blk.gu - blk.gl);
+    int pick = -1;
+    for (int lev = 0; lev < kChildLevels && pick < 0; ++lev) {
+      const double a = gr[2 * lev], b = gr[2 * lev + 1];
+      if (a <= bound || b <= bound) pick = (a <= b) ? 2 * lev : 2 * lev + 1;
+    }
+    if (pick < 0) {
+      atomicAdd(&C->child_reject, 1ull);
+      double best = INFINITY;
+      for (int k = 0; k < kChildCand; ++k)
+        if (gr[k] < best) {
+          best = gr[k];
+          pick = k;
+        }
+    }
+    long long off = -1;
+    if (pick >= 0) {
+      off = (long long)atomicAdd(&C->pool_used, (unsigned long long)n);
+      if ((unsigned long long)off + (unsigned long long)n > pool_cap) {
+        set_status(C, 3);
+        off = -1;
       }
+    }
+    Node nd;
+    nd.blk = par.blk;
+    nd.parent = cl.node;
+    nd.f = cl.f;
+    nd.l = cl.l;
+    nd.gapl = cl.gapl;
+    nd.gapr = cl.gapr;
+    nd.pad = 0;
+    if (off < 0) {
+      if (pick < 0) set_status(C, 1);
+      nd.growth = INFINITY;
+      nd.rep = -1;
+      nd.acc = par.acc;
+      nd.sigma = 0.0;
+      nd.depth = -1;
+      s_sigma = 0.0;
+    } else {
+      bool v;
+      const double sg = child_sigma(cl, blk, lo, hi, pick, &v);
+      nd.rep = off;
+      nd.growth = gr[pick] / (blk.gu - blk.gl);
+      nd.acc = par.acc + sg;
+      nd.sigma = sg;
+      nd.depth = par.depth + 1;
+      atomicMax(&C->max_depth, nd.depth);
+      s_sigma = sg;
+      atomicAdd(&C->qds_steps, (unsigned long long)n);
+      atomicAdd(&C->child_steps, (unsigned long long)n);
+    }
+    s_off = off;
+    N[node_base + c] = nd;
   }
-  Node nd;
-  nd.blk = par.blk;
-  nd.parent = cl.node;
-  nd.f = cl.f;
-  nd.l = cl.l;
-  nd.gapl = cl.gapl;
-  nd.gapr = cl.gapr;
-  nd.pad = 0;
-  if (pick < 0) {
-    set_status(C, 1);
-    nd.rep = -1;
-    nd.acc = par.acc;
-    nd.sigma = 0.0;
-    nd.depth = -1;
-  } else {
-    nd.rep = of[pick];
-    nd.acc = par.acc + sg[pick];
-    nd.sigma = sg[pick];
-    nd.depth = par.depth + 1;
-    atomicMax(&C->max_depth, nd.depth);
+  __syncthreads();
+  const long long off = s_off;
+  if (off < 0 || lane >= 4) return;
+  // pass 2: lanes 0..3 repeat the chosen transform; lane q stores field q
+  const double sg = s_sigma;
+  double* Q = reinterpret_cast<double*>(pool + off);
+  sv = -sg;
+  for (int i = 0; i + 1 < n; ++i) {
+    const double D = R[i].D, L = R[i].L, LD = R[i].LD;
+    const double dp = D + sv;
+    const double lp = LD * rcp_nr2(dp);
+    const double ld = lp * dp;
+    const double v = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
+    Q[(int64_t)i * 4 + lane] = v;
+    sv = fma(lp * L, sv, -sg);
   }
-  N[node_base + c] = nd;
+  const double dn = R[n - 1].D + sv;
+  Q[(int64_t)(n - 1) * 4 + lane] = (lane == 0) ? dn : 0.0;
 }
 
 // move the cluster's brackets into the child's frame (or, without a child,
@@ -872,7 +917,7 @@ __global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N,
                         const Cluster* __restrict__ clusters, const int64_t* __restrict__ scol,
                         double* __restrict__ lo, double* __restrict__ hi, int32_t* __restrict__ clo,
                         int32_t* __restrict__ chi, int32_t* __restrict__ snode, uint32_t* __restrict__ sflag,
-                        int refine_all) {
+                        double* __restrict__ sgap) {
   const int c = blockIdx.x;
   const Node nd = N[node_base + c];
   const Block blk = B[nd.blk];
@@ -880,7 +925,10 @@ __global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N,
     const int64_t s = blk.row0 + j - 1;
     uint32_t fl = sflag[s] & ~(F_ACTIVE | F_RUNSTART);
     if (nd.depth < 0) {
-      if (scol[s] >= 0) fl |= F_SINGLETON;
+      if (scol[s] >= 0) {
+        fl |= F_SINGLETON;
+        sgap[s] = slot_gap(nd, blk.row0, s, lo, hi);
+      }
       sflag[s] = fl;
       continue;
     }
@@ -895,7 +943,7 @@ __global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N,
     clo[s] = -1;
     chi[s] = -1;
     snode[s] = node_base + c;
-    sflag[s] = (fl & ~(F_ACCURATE | F_NEEDS_REFINE)) | F_ACTIVE | (refine_all ? F_NEEDS_REFINE : 0u);
+    sflag[s] = (fl & ~(F_ACCURATE | F_NEEDS_REFINE)) | F_ACTIVE;
   }
 }
 
@@ -918,10 +966,20 @@ __global__ void k_clear_active(int64_t ntot, uint32_t* __restrict__ sflag) {
 //    then lam <- lam + gamma_r / ||z||^2 (Rayleigh quotient) until converged.
 
 constexpr int kVecLanes = 64;
+
+// angle accepted for a singleton's vector: eps * max(n / 16, 4 log2 n), a
+// small fraction of the O(n eps) orthogonality the method guarantees
+__device__ inline double rqi_angle_tol(int n) {
+  return kEps * fmax((double)n * 0.0625, 4.0 * fmax(1.0, log2((double)n)));
+}
 constexpr int kVecRows = 16;  // rows per LDS transpose tile
 
 struct VecState {
   double lam, lo, hi;
+  double gap;    // absolute gap to the nearest other eigenvalue of the leaf
+  double resid;  // smallest residual norm so far
+  double best;   // lambda of that solve
+  int stall;     // solves without a smaller residual
   double lam_out;
   double nrm;    // ||z||^2 of the committed solve
   double zmaxv;  // signed largest-magnitude entry of the committed solve
@@ -939,15 +997,10 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
                                    double* __restrict__ A, double* __restrict__ Bv, int lane, VecState& V) {
   bool conv = !solve;
   bool last = false;
-  for (int it = 0; it <= kMaxRqi + 1; ++it) {
+  for (int it = 0; it <= kMaxRqi; ++it) {
     const bool go = solve && !conv;
     // wave-uniform trip count: every lane runs the lockstep loops below
     if (__ballot(go) == 0) break;
-    if (go && it >= kMaxRqi && !last) {  // last pass: fall back to the bracket midpoint
-      last = true;
-      V.fallback = true;
-      V.lam = 0.5 * (V.lo + V.hi);
-    }
     const double lam = V.lam;
     // top-down stationary transform; s_i stored in A
     double sv = -lam;
@@ -957,7 +1010,7 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
         const double D = R[i].D, L = R[i].L, LD = R[i].LD, LLD = R[i].LLD;
         double dp = D + sv;
         dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-        const double lp = (c_diag_flags & 1) ? LD / dp : LD * rcp_nr2(dp);
+        const double lp = LD * rcp_nr2(dp);
         double tt = lp * L * sv;
         tt = (lp == 0.0) ? LLD : tt;
         sv = tt - lam;
@@ -980,7 +1033,7 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
         const double D = R[i].D, L = R[i].L, LLD = R[i].LLD;
         double dm = LLD + pv;
         dm = (fabs(dm) < pivmin) ? -pivmin : dm;
-        const double tt = (c_diag_flags & 1) ? D / dm : D * rcp_nr2(dm);
+        const double tt = D * rcp_nr2(dm);
         Bv[(int64_t)i * kVecLanes + lane] = L * tt;
         double pn = pv * tt - lam;
         pn = (tt == 0.0) ? D - lam : pn;
@@ -1032,7 +1085,7 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
           const double D = R[i].D, LD = R[i].LD;
           double dp = D + A[(int64_t)i * kVecLanes + lane];
           dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-          zi = -((c_diag_flags & 1) ? LD / dp : LD * rcp_nr2(dp)) * z1;
+          zi = -(LD * rcp_nr2(dp)) * z1;
         } else {
           const double ldi = R[i].LD;
           zi = (ldi != 0.0) ? -div_nr(R[i + 1].LD, ldi) * z2 : 0.0;
@@ -1056,13 +1109,36 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
       const double corr = gmin / nrm;
       const double resid = fabs(gmin) / sqrt(nrm);
       const double lamc = lam + corr;
-      const bool inside = (lamc >= V.lo && lamc <= V.hi);
-      const bool strict = (c_diag_flags & 2) != 0;
-      const bool small = strict ? fabs(corr) <= 0.25 * kEps * fabs(lam)
-                                : (resid <= 2.0 * (double)n * kEps * fabs(lam) || fabs(corr) <= 2.0 * kEps * fabs(lam));
+      // the bracket comes from Sturm counts whose rounding differs from the
+      // twisted factorization's; within a quarter of the gap of the bracket the
+      // nearest eigenvalue is still this one
+      const double slack = 0.25 * V.gap;
+      const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
+      // resid / gap bounds the sine of the angle between z and the eigenvector
+      // (gap theorem); otherwise stop once the correction is below half an ulp
+      // of lambda.  At the rounding floor (two solves without a smaller
+      // residual, or the iteration cap) the solve with the smallest residual
+      // is repeated, unless it is the current one.
+      const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
+      const bool improved = resid < V.resid;
+      if (improved) {
+        V.resid = resid;
+        V.best = lam;
+      } else {
+        V.stall++;
+      }
       if (last || small) {
         conv = true;
         V.lam_out = inside ? lamc : lam;
+      } else if (V.stall >= 2 || it + 1 >= kMaxRqi) {
+        V.fallback = true;
+        if (improved) {
+          conv = true;
+          V.lam_out = inside ? lamc : lam;
+        } else {
+          V.lam = V.best;
+          last = true;
+        }
       } else if (!inside) {
         // correction leaves the bracket: one last pass at the midpoint
         V.lam = 0.5 * (V.lo + V.hi);
@@ -1081,7 +1157,8 @@ __global__ void __launch_bounds__(64) k_vectors(
     const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
     const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
     const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
-    const Rep* __restrict__ pool, const double* __restrict__ ds, double* __restrict__ scratch,
+    const double* __restrict__ sgap, const Rep* __restrict__ pool, const double* __restrict__ ds,
+    double* __restrict__ scratch,
     double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
   __shared__ double tile[kVecLanes][kVecRows + 1];
   __shared__ int64_t s_col[kVecLanes];
@@ -1111,7 +1188,11 @@ __global__ void __launch_bounds__(64) k_vectors(
   VecState V;
   V.lo = lo_a[ss];
   V.hi = hi_a[ss];
+  V.gap = sgap[ss];
+  V.resid = INFINITY;
+  V.stall = 0;
   V.lam = 0.5 * (V.lo + V.hi);
+  V.best = V.lam;
   V.lam_out = V.lam;
   V.nrm = 1.0;
   V.zmaxv = 1.0;
@@ -1375,10 +1456,11 @@ void launch_cls_compact(hipStream_t st, int64_t ntot, const int32_t* runflag, co
 
 void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, const int64_t* runs,
                      const int32_t* sblk, const int32_t* snode, const double* lo, const double* hi,
-                     const int64_t* scol, uint32_t* sflag, Cluster* clusters, int max_clusters, Counters* C) {
+                     const int64_t* scol, uint32_t* sflag, double* sgap, Cluster* clusters, int max_clusters,
+                     Counters* C) {
   if (nruns == 0) return;
   hipLaunchKernelGGL(k_cls_runs, GRID1(nruns, 64), 0, st, B, N, nruns, runs, sblk, snode, lo, hi, scol, sflag,
-                     clusters, max_clusters, C);
+                     sgap, clusters, max_clusters, C);
 }
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
@@ -1389,9 +1471,9 @@ void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int no
 
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
-                  int32_t* snode, uint32_t* sflag, bool refine_all) {
+                  int32_t* snode, uint32_t* sflag, double* sgap) {
   hipLaunchKernelGGL(k_shift, dim3(nclusters), dim3(256), 0, st, B, N, node_base, clusters, scol, lo, hi, clo, chi,
-                     snode, sflag, refine_all ? 1 : 0);
+                     snode, sflag, sgap);
 }
 
 void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag) {
@@ -1406,11 +1488,11 @@ void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32
 
 void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
                     const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
-                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const Rep* pool,
-                    const double* ds, double* scratch, double* w, double* Z, Counters* C) {
+                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const double* sgap,
+                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C) {
   if (nchunks == 0) return;
   hipLaunchKernelGGL(k_vectors, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, sblk,
-                     snode, sflag, scol, lo, hi, pool, ds, scratch, w, Z, C);
+                     snode, sflag, scol, lo, hi, sgap, pool, ds, scratch, w, Z, C);
 }
 
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C) {

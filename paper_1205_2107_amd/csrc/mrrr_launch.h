@@ -4,8 +4,6 @@
 
 namespace mrrr {
 
-void set_diag_flags(int f);
-
 void launch_prep(hipStream_t st, Problem* P, int nprob, const int64_t* poff, int64_t ntot, const double* d,
                  const double* e, int32_t* sprob, double* ds, double* es, int32_t* flag);
 void launch_scan(hipStream_t st, const int32_t* in, int32_t* out, int32_t* tile_sum, int64_t n, int32_t* total);
@@ -30,19 +28,20 @@ void launch_cls_flags(hipStream_t st, const Block* B, const Node* N, int64_t nto
 void launch_cls_compact(hipStream_t st, int64_t ntot, const int32_t* runflag, const int32_t* runid, int64_t* runs);
 void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, const int64_t* runs,
                      const int32_t* sblk, const int32_t* snode, const double* lo, const double* hi,
-                     const int64_t* scol, uint32_t* sflag, Cluster* clusters, int max_clusters, Counters* C);
+                     const int64_t* scol, uint32_t* sflag, double* sgap, Cluster* clusters, int max_clusters,
+                     Counters* C);
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C);
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
-                  int32_t* snode, uint32_t* sflag, bool refine_all);
+                  int32_t* snode, uint32_t* sflag, double* sgap);
 void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag);
 void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
                        const int64_t* scol, int32_t* rows);
 void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
                     const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
-                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const Rep* pool,
-                    const double* ds, double* scratch, double* w, double* Z, Counters* C);
+                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const double* sgap,
+                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C);
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C);
 void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t* bad, double* w, int64_t* perm,
                      double* tmp, double* Z);
