@@ -49,7 +49,7 @@ def cpu_baseline(n):
     import oracle
     from paper_1205_2107_amd import workloads as W
     d, e = W.random_uniform(n, W.SEEDS["c2_random"])
-    k = 600
+    k = 1500
     t0 = time.perf_counter()
     w, Z, st = oracle.mrrr(d, e, kind=oracle.RANGE_INDEX, il=1, iu=k)
     dt = time.perf_counter() - t0

@@ -74,6 +74,7 @@ typedef struct {
 #define MRRR_CNT_FALLBACKS 7     /* singletons that needed the bisection fallback */
 #define MRRR_CNT_CHILD_REJECT 8  /* clusters whose child failed the growth bound */
 #define MRRR_CNT_WORKSPACE_MB 9  /* device workspace in use after the call */
+#define MRRR_CNT_WAVE_SOLVES 10  /* twisted-factorization rounds summed over wavefronts (lockstep cost) */
 
 /*
  * mrrr_step -- eigenpairs of one tridiagonal (Stage 4, STEP).

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libmrrr.so")
 
 MRRR_ALL, MRRR_INDEX, MRRR_VALUE = 0, 1, 2
 COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singletons", "twisted",
-                 "fallbacks", "child_reject", "workspace_mb")
+                 "fallbacks", "child_reject", "workspace_mb", "wave_solves")
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string")

@@ -108,6 +108,7 @@ struct Counters {
   unsigned long long z_entries;    // eigenvector entries written
   int32_t ambiguous;               // classifications that need refined brackets
   int32_t pad2;
+  unsigned long long wave_solves;  // twisted-factorization rounds summed over wavefronts
 };
 
 // ---------------------------------------------------------------------------

@@ -492,6 +492,7 @@ static void fill_info(mrrr_info* info, const Problem& p, const Report& r) {
   info->counters[MRRR_CNT_FALLBACKS] = (int64_t)r.c.fallbacks;
   info->counters[MRRR_CNT_CHILD_REJECT] = (int64_t)r.c.child_reject;
   info->counters[MRRR_CNT_WORKSPACE_MB] = (int64_t)(r.ws_bytes >> 20);
+  info->counters[MRRR_CNT_WAVE_SOLVES] = (int64_t)r.c.wave_solves;
 }
 
 }  // namespace mrrr

@@ -988,6 +988,57 @@ struct VecState {
   bool fallback;
 };
 
+// bookkeeping after one twisted solve of a lane still iterating: Rayleigh
+// correction, stopping rule, next shift
+__device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, int n, double gmin, double nrm,
+                                  double zmaxv, double lam) {
+  V.qsteps += 4ll * n;
+  V.rq++;
+  V.nrm = nrm;
+  V.zmaxv = zmaxv;
+  const double corr = gmin / nrm;
+  const double resid = fabs(gmin) / sqrt(nrm);
+  const double lamc = lam + corr;
+  // the bracket comes from Sturm counts whose rounding differs from the
+  // twisted factorization's; within a quarter of the gap of the bracket the
+  // nearest eigenvalue is still this one
+  const double slack = 0.25 * V.gap;
+  const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
+  // resid / gap bounds the sine of the angle between z and the eigenvector
+  // (gap theorem); otherwise stop once the correction is below half an ulp
+  // of lambda.  At the rounding floor (two solves without a smaller
+  // residual, or the iteration cap) the solve with the smallest residual
+  // is repeated, unless it is the current one.
+  const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
+  const bool improved = resid < V.resid;
+  if (improved) {
+    V.resid = resid;
+    V.best = lam;
+  } else {
+    V.stall++;
+  }
+  if (last || small) {
+    conv = true;
+    V.lam_out = inside ? lamc : lam;
+  } else if (V.stall >= 2 || it + 1 >= kMaxRqi) {
+    V.fallback = true;
+    if (improved) {
+      conv = true;
+      V.lam_out = inside ? lamc : lam;
+    } else {
+      V.lam = V.best;
+      last = true;
+    }
+  } else if (!inside) {
+    // correction leaves the bracket: one last pass at the midpoint
+    V.lam = 0.5 * (V.lo + V.hi);
+    last = true;
+    V.fallback = true;
+  } else {
+    V.lam = lamc;
+  }
+}
+
 // Rayleigh-quotient iteration on twisted factorizations for the lanes with
 // `solve` set; z of the last solve is left in Bv ([row][lane] layout).  All
 // lanes run the lockstep loops; per-lane results are committed only by lanes
@@ -1101,53 +1152,224 @@ __device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n,
         }
       }
     }
-    if (go) {
-      V.qsteps += 4ll * n;
-      V.rq++;
-      V.nrm = nrm;
-      V.zmaxv = zmaxv;
-      const double corr = gmin / nrm;
-      const double resid = fabs(gmin) / sqrt(nrm);
-      const double lamc = lam + corr;
-      // the bracket comes from Sturm counts whose rounding differs from the
-      // twisted factorization's; within a quarter of the gap of the bracket the
-      // nearest eigenvalue is still this one
-      const double slack = 0.25 * V.gap;
-      const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
-      // resid / gap bounds the sine of the angle between z and the eigenvector
-      // (gap theorem); otherwise stop once the correction is below half an ulp
-      // of lambda.  At the rounding floor (two solves without a smaller
-      // residual, or the iteration cap) the solve with the smallest residual
-      // is repeated, unless it is the current one.
-      const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
-      const bool improved = resid < V.resid;
-      if (improved) {
-        V.resid = resid;
-        V.best = lam;
-      } else {
-        V.stall++;
-      }
-      if (last || small) {
-        conv = true;
-        V.lam_out = inside ? lamc : lam;
-      } else if (V.stall >= 2 || it + 1 >= kMaxRqi) {
-        V.fallback = true;
-        if (improved) {
-          conv = true;
-          V.lam_out = inside ? lamc : lam;
-        } else {
-          V.lam = V.best;
-          last = true;
+    if (go) rqi_commit(V, conv, last, it, n, gmin, nrm, zmaxv, lam);
+  }
+  if (solve && !conv) V.lam_out = V.lam;
+}
+
+
+// ---------------------------------------------------------------------------
+// The same iteration for a wavefront whose lanes share one representation (and
+// so one n): software-pipelined.  Representation rows are staged in LDS one
+// group of kRing rows ahead (one 2 x 8-byte load per lane per group), and the
+// per-lane work vectors are read through a ring of kRing registers that is
+// refilled kRing rows ahead, so no row step waits on a memory round trip.
+
+constexpr int kRing = 32;
+
+// rows [row0, row0 + kRing) of a representation (4 doubles a row) spread over
+// the wave: lane l holds doubles l and l + 64 of the group; rows outside
+// [0, n) read as zero
+__device__ inline void stage_fetch(const double* __restrict__ Rd, int64_t nd4, int64_t row0, int lane,
+                                   double q[2]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int64_t idx = row0 * 4 + lane + 64 * k;
+    q[k] = (idx >= 0 && idx < nd4) ? Rd[idx] : 0.0;
+  }
+}
+
+__device__ inline void stage_put(double* __restrict__ st, int lane, const double q[2]) {
+  __syncthreads();
+  st[lane] = q[0];
+  st[lane + 64] = q[1];
+  __syncthreads();
+}
+
+__device__ inline void twisted_rqi_staged(bool solve, const double* __restrict__ Rd, int n, double pivmin,
+                                          double* __restrict__ A, double* __restrict__ Bv, int lane,
+                                          VecState& V, double* __restrict__ st) {
+  bool conv = !solve;
+  bool last = false;
+  const int64_t nd4 = 4 * (int64_t)n;
+  double q[2];
+  double ring[kRing];
+  for (int it = 0; it <= kMaxRqi; ++it) {
+    const bool go = solve && !conv;
+    if (__ballot(go) == 0) break;
+    const double lam = V.lam;
+    // top-down stationary transform; s_i stored in A
+    double sv = -lam;
+    stage_fetch(Rd, nd4, 0, lane, q);
+    for (int g = 0; g < n - 1; g += kRing) {
+      stage_put(st, lane, q);
+      stage_fetch(Rd, nd4, g + kRing, lane, q);
+#pragma unroll
+      for (int k = 0; k < kRing; ++k) {
+        const int i = g + k;
+        if (i + 1 < n) {
+          const double D = st[4 * k], L = st[4 * k + 1], LD = st[4 * k + 2], LLD = st[4 * k + 3];
+          if (go) A[(int64_t)i * kVecLanes + lane] = sv;
+          double dp = D + sv;
+          dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+          const double lp = LD * rcp_nr2(dp);
+          double tt = lp * L * sv;
+          tt = (lp == 0.0) ? LLD : tt;
+          sv = tt - lam;
         }
-      } else if (!inside) {
-        // correction leaves the bracket: one last pass at the midpoint
-        V.lam = 0.5 * (V.lo + V.hi);
-        last = true;
-        V.fallback = true;
-      } else {
-        V.lam = lamc;
       }
     }
+    if (go) A[(int64_t)(n - 1) * kVecLanes + lane] = sv;
+    // bottom-up progressive transform; U-_i stored in Bv; twist index
+    double pv = Rd[(int64_t)(n - 1) * 4] - lam;
+    double gmin = INFINITY;
+    int r = -1;
+    {
+      const double g = sv + pv + lam;
+      if (go && isfinite(g)) {
+        gmin = g;
+        r = n - 1;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRing; ++k) {
+      const int row = n - 2 - k;
+      ring[k] = (row >= 0) ? A[(int64_t)row * kVecLanes + lane] : 0.0;
+    }
+    stage_fetch(Rd, nd4, (int64_t)n - 1 - kRing, lane, q);
+    for (int g = n - 2; g >= 0; g -= kRing) {
+      const int base = g - kRing + 1;
+      stage_put(st, lane, q);
+      stage_fetch(Rd, nd4, (int64_t)base - kRing, lane, q);
+#pragma unroll
+      for (int k = 0; k < kRing; ++k) {
+        const int i = g - k;
+        const double a = ring[k];
+        if (i - kRing >= 0) ring[k] = A[(int64_t)(i - kRing) * kVecLanes + lane];
+        if (i >= 0) {
+          const int o = 4 * (kRing - 1 - k);
+          const double D = st[o], L = st[o + 1], LLD = st[o + 3];
+          double dm = LLD + pv;
+          dm = (fabs(dm) < pivmin) ? -pivmin : dm;
+          const double tt = D * rcp_nr2(dm);
+          if (go) Bv[(int64_t)i * kVecLanes + lane] = L * tt;
+          double pn = pv * tt - lam;
+          pn = (tt == 0.0) ? D - lam : pn;
+          pv = pn;
+          const double gv = a + pv + lam;
+          if (go && isfinite(gv) && !(fabs(gv) > fabs(gmin))) {
+            gmin = gv;
+            r = i;
+          }
+        }
+      }
+    }
+    if (go && r < 0) {
+      r = 0;
+      gmin = 0.0;
+    }
+    // wave-wide range of twist indices: rows below the smallest need no
+    // downward step, rows above the largest no upward step
+    int rmin = go ? r : n, rmax = go ? r : 0;
+    for (int o = 32; o > 0; o >>= 1) {
+      rmin = min(rmin, __shfl_xor(rmin, o, 64));
+      rmax = max(rmax, __shfl_xor(rmax, o, 64));
+    }
+    // solve downward from the twist (z_i stored in Bv in place of U-_i)
+    double zc = 0.0, zp = 0.0;
+    double nrm = 1.0, zmaxv = 1.0;
+    int imax = r;
+    {
+      const int i0 = min(rmin, n - 1);
+#pragma unroll
+      for (int k = 0; k < kRing; ++k) {
+        const int row = i0 + k;
+        ring[k] = (row + 1 < n) ? Bv[(int64_t)row * kVecLanes + lane] : 0.0;
+      }
+      double ldp = (i0 > 0) ? Rd[(int64_t)(i0 - 1) * 4 + 2] : 0.0;  // LD of the row above
+      stage_fetch(Rd, nd4, i0, lane, q);
+      for (int g = i0; g + 1 < n; g += kRing) {
+        stage_put(st, lane, q);
+        stage_fetch(Rd, nd4, (int64_t)g + kRing, lane, q);
+#pragma unroll
+        for (int k = 0; k < kRing; ++k) {
+          const int i = g + k;
+          const double u = ring[k];
+          if (i + kRing + 1 < n) ring[k] = Bv[(int64_t)(i + kRing) * kVecLanes + lane];
+          if (i + 1 < n) {
+            const double ldi = st[4 * k + 2];
+            if (go && i >= r) {
+              if (i == r) zc = 1.0;
+              Bv[(int64_t)i * kVecLanes + lane] = zc;
+              double zn;
+              if (zc != 0.0 || i == r) {
+                zn = -u * zc;
+              } else {
+                zn = (ldi != 0.0) ? -div_nr(ldp, ldi) * zp : 0.0;
+              }
+              zn = isfinite(zn) ? zn : 0.0;
+              zp = zc;
+              zc = zn;
+              nrm += zn * zn;
+              if (fabs(zn) > fabs(zmaxv)) {
+                zmaxv = zn;
+                imax = i + 1;
+              }
+            }
+            ldp = ldi;
+          }
+        }
+      }
+    }
+    if (go) Bv[(int64_t)(n - 1) * kVecLanes + lane] = (r == n - 1) ? 1.0 : zc;
+    // solve upward from the twist, L+_i recomputed from the stored s_i
+    {
+      const int i1 = max(rmax - 1, -1);
+      double z1 = 1.0, z2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kRing; ++k) {
+        const int row = i1 - k;
+        ring[k] = (row >= 0) ? A[(int64_t)row * kVecLanes + lane] : 0.0;
+      }
+      double ldn = (i1 + 1 < n && i1 >= 0) ? Rd[(int64_t)(i1 + 1) * 4 + 2] : 0.0;  // LD of the row below
+      stage_fetch(Rd, nd4, (int64_t)i1 - kRing + 1, lane, q);
+      for (int g = i1; g >= 0; g -= kRing) {
+        const int base = g - kRing + 1;
+        stage_put(st, lane, q);
+        stage_fetch(Rd, nd4, (int64_t)base - kRing, lane, q);
+#pragma unroll
+        for (int k = 0; k < kRing; ++k) {
+          const int i = g - k;
+          const double a = ring[k];
+          if (i - kRing >= 0) ring[k] = A[(int64_t)(i - kRing) * kVecLanes + lane];
+          if (i >= 0) {
+            const int o = 4 * (kRing - 1 - k);
+            const double D = st[o], LD = st[o + 2];
+            if (go && i < r) {
+              double zi;
+              if (z1 != 0.0 || i + 2 > r) {
+                double dp = D + a;
+                dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+                zi = -(LD * rcp_nr2(dp)) * z1;
+              } else {
+                zi = (LD != 0.0) ? -div_nr(ldn, LD) * z2 : 0.0;
+              }
+              zi = isfinite(zi) ? zi : 0.0;
+              Bv[(int64_t)i * kVecLanes + lane] = zi;
+              z2 = z1;
+              z1 = zi;
+              nrm += zi * zi;
+              if (fabs(zi) > fabs(zmaxv) || (fabs(zi) == fabs(zmaxv) && i < imax)) {
+                zmaxv = zi;
+                imax = i;
+              }
+            }
+            ldn = LD;
+          }
+        }
+      }
+    }
+    if (go) rqi_commit(V, conv, last, it, n, gmin, nrm, zmaxv, lam);
   }
   if (solve && !conv) V.lam_out = V.lam;
 }
@@ -1161,6 +1383,7 @@ __global__ void __launch_bounds__(64) k_vectors(
     double* __restrict__ scratch,
     double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
   __shared__ double tile[kVecLanes][kVecRows + 1];
+  __shared__ double stage[4 * kRing];
   __shared__ int64_t s_col[kVecLanes];
   __shared__ int64_t s_zoff[kVecLanes];
   __shared__ int s_n[kVecLanes];
@@ -1203,8 +1426,10 @@ __global__ void __launch_bounds__(64) k_vectors(
   if (act && n == 1) Bv[lane] = 1.0;
   const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
   if (__ballot(nd.rep != rep0) == 0) {
-    const Rep* R = wave_uniform(pool + nd.rep);
-    twisted_rqi<true>(solve, R, __builtin_amdgcn_readfirstlane(n), nmax, blk.pivmin, A, Bv, lane, V);
+    // per-lane copy of the (equal) pointer keeps the loads in the global
+    // address space; each lane fetches its own part of a staged group
+    const double* Rd = reinterpret_cast<const double*>(pool + nd.rep);
+    twisted_rqi_staged(solve, Rd, __builtin_amdgcn_readfirstlane(n), blk.pivmin, A, Bv, lane, V, stage);
   } else {
     twisted_rqi<false>(solve, pool + nd.rep, n, nmax, blk.pivmin, A, Bv, lane, V);
   }
@@ -1234,12 +1459,13 @@ __global__ void __launch_bounds__(64) k_vectors(
     // stages 16 rows x 64 columns, then every column gets one contiguous
     // 128-byte segment (16 lanes per column, 4 columns per instruction)
     for (int r0 = 0; r0 < nmax; r0 += kVecRows) {
-      for (int k = 0; k < kVecRows; ++k) {
-        const int i = r0 + k;
-        double v = 0.0;
-        if (act && i < n) v = Bv[(int64_t)i * kVecLanes + lane] * scale;
-        tile[lane][k] = v;
-      }
+      // all loads of the tile first (rows below nmax lie inside the work
+      // vector of every lane), then one wait
+      double v[kVecRows];
+#pragma unroll
+      for (int k = 0; k < kVecRows; ++k) v[k] = (r0 + k < nmax) ? Bv[(int64_t)(r0 + k) * kVecLanes + lane] : 0.0;
+#pragma unroll
+      for (int k = 0; k < kVecRows; ++k) tile[lane][k] = (act && r0 + k < n) ? v[k] * scale : 0.0;
       __syncthreads();
       const int rr = lane & (kVecRows - 1);
       for (int cgrp = 0; cgrp < kVecLanes; cgrp += 4) {
@@ -1268,6 +1494,11 @@ __global__ void __launch_bounds__(64) k_vectors(
     atomicAdd(&C->rqi, (unsigned long long)V.rq);
     atomicAdd(&C->singletons, 1ull);
     if (V.fallback) atomicAdd(&C->fallbacks, 1ull);
+  }
+  {
+    int rqm = V.rq;
+    for (int o = 32; o > 0; o >>= 1) rqm = max(rqm, __shfl_xor(rqm, o, 64));
+    if (lane == 0) atomicAdd(&C->wave_solves, (unsigned long long)rqm);
   }
 }
 
