@@ -44,7 +44,7 @@ def make_inputs(n):
 
 
 def cpu_baseline(n):
-    """Oracle (single-threaded C, as it stands) on a bounded sample: the 600
+    """Oracle (single-threaded C, as it stands) on a bounded sample: the 1500
     smallest eigenpairs of the random n = 20000 matrix."""
     import oracle
     from paper_1205_2107_amd import workloads as W

@@ -143,8 +143,8 @@ int mrrr_step_backward_batched(int64_t batch, const int64_t* n_host, const int64
 /* Launch-shape parameters of the solver (the batched autotuner sets these). */
 typedef struct {
   int32_t grid_density;    /* Sturm-count grid points per eigenvalue for the initial brackets (1..16) */
-  int32_t refine_wave_slots; /* eigenvalues per wavefront in refinement (16, 32 or 64) */
-  int32_t vec_wave_slots;  /* eigenvectors per wavefront (16, 32 or 64) */
+  int32_t refine_wave_slots; /* eigenvalues per wavefront in refinement (0 = automatic, 16, 32 or 64) */
+  int32_t vec_wave_slots;  /* eigenvectors per wavefront (0 = automatic, 8, 16 or 32) */
   int32_t reserved[5];
 } mrrr_tuning;
 

@@ -38,7 +38,7 @@ void prof_add(int kernel, int64_t launches, double ms, double work, double bytes
   g_prof[kernel].bytes += bytes;
 }
 
-static mrrr_tuning g_tune = {4, 0, 64, {0, 0, 0, 0, 0}};
+static mrrr_tuning g_tune = {4, 0, 0, {0, 0, 0, 0, 0}};
 static std::mutex g_tune_mu;
 
 static int fail(int code, const char* fmt, ...) {
@@ -349,10 +349,13 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                   P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
                   dC, lanes);
     prof.end();
-    // 8. eigenvectors of all singletons
-    const int64_t nch = (ntot + 63) / 64;
+    // 8. eigenvectors of all singletons (eigenvectors per wavefront: tuning,
+    //    32 by default; four work vectors of rows x slots doubles per wavefront)
+    int vslots = tune.vec_wave_slots;
+    if (vslots == 0) vslots = 32;
+    const int64_t nch = (ntot + vslots - 1) / vslots;
     ENS(chunkrows, sizeof(int32_t) * nch);
-    launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
+    launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), vslots,
                       P_<int32_t>(W.chunkrows));
     std::vector<int32_t> rows(nch);
     HIP_TRY(hipMemcpyAsync(rows.data(), W.chunkrows.p, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, st));
@@ -363,7 +366,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     for (int64_t c = 0; c < nch; ++c)
       if (rows[c] > 0) {
         act.push_back((int32_t)c);
-        maxper = std::max<int64_t>(maxper, 2 * 64 * (int64_t)rows[c]);
+        maxper = std::max<int64_t>(maxper, 4 * vslots * (int64_t)rows[c]);
       }
     const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
     ENS(chunks, sizeof(int32_t) * (act.size() + 1));
@@ -375,7 +378,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       int64_t used = 0;
       aoff.clear();
       while (i1 < act.size()) {
-        const int64_t need = 2 * 64 * (int64_t)rows[act[i1]];
+        const int64_t need = 4 * vslots * (int64_t)rows[act[i1]];
         if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
         aoff.push_back(used);
         used += need;
@@ -388,7 +391,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff), (int)(i1 - i0),
                      ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
                      P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
-                     P_<double>(W.scratch), w, Z, dC);
+                     P_<double>(W.scratch), w, Z, dC, vslots);
       prof.end();
       // host vectors are reused by the next batch: wait for the copies
       HIP_TRY(hipStreamSynchronize(st));
@@ -598,7 +601,8 @@ int mrrr_set_tuning(const mrrr_tuning* t) {
   if (!(t->refine_wave_slots == 0 || t->refine_wave_slots == 16 || t->refine_wave_slots == 32 ||
         t->refine_wave_slots == 64))
     return -1;
-  if (!(t->vec_wave_slots == 16 || t->vec_wave_slots == 32 || t->vec_wave_slots == 64)) return -1;
+  if (!(t->vec_wave_slots == 0 || t->vec_wave_slots == 8 || t->vec_wave_slots == 16 || t->vec_wave_slots == 32))
+    return -1;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = *t;
   return 0;

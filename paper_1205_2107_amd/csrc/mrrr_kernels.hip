@@ -484,16 +484,78 @@ __device__ inline void update_state(EigState& S, const double* p, const int* c, 
   S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
 }
 
+// ---------------------------------------------------------------------------
+// rows of a representation shared by a whole wavefront, staged through LDS in
+// groups of kSG rows: while one group is consumed (LDS broadcast reads), lane
+// l already holds doubles l, l + 64, l + 128, l + 192 of the next one, loaded
+// with four coalesced 512-byte wavefront loads -- one wait per group instead
+// of one per row.  body(i, D, L, LD, LLD) runs for i = 0 .. n - 1 in order.
+// st: 2 * 4 * kSG doubles of LDS; every lane of the wavefront must call.
+
+constexpr int kSG = 64;
+
+template <class Body>
+__device__ inline void staged_rows(const double* __restrict__ Rd, int n, double* __restrict__ st, Body&& body) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n4 = 4 * (int64_t)n;
+  double q[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t idx = lane + 64 * k;
+    q[k] = (idx < n4) ? Rd[idx] : 0.0;
+  }
+  for (int g0 = 0; g0 < n; g0 += kSG) {
+    double* buf = st + ((g0 / kSG) & 1) * (4 * kSG);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) buf[lane + 64 * k] = q[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t idx = (int64_t)(g0 + kSG) * 4 + lane + 64 * k;
+      q[k] = (idx < n4) ? Rd[idx] : 0.0;
+    }
+    const int m = min(kSG, n - g0);
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) body(g0 + j, buf[4 * j], buf[4 * j + 1], buf[4 * j + 2], buf[4 * j + 3]);
+  }
+}
+
+// Sturm count plus log-derivative (as sturm_count_deriv) for a wavefront
+// whose lanes share the representation
+__device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, double tau, double pivmin,
+                                         double* __restrict__ st, double* g_out) {
+  double s = -tau, ds = -1.0, g = 0.0;
+  int c = 0;
+  staged_rows(Rd, n, st, [&](int, double D, double, double, double LLD) {
+    double dp = D + s;
+    dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+    c += (dp < 0.0) ? 1 : 0;
+    const double inv = rcp_nr1(dp);
+    const double dsi = ds * inv;
+    g += dsi;
+    // the last row has LLD = 0; its update is harmless
+    ds = fma(LLD * D, dsi * inv, -1.0);
+    s = fma(s * inv, LLD, -tau);
+  });
+  if (!(s == s)) {
+    c = sturm_count(reinterpret_cast<const Rep*>(Rd), n, tau, pivmin);
+    g = NAN;
+  }
+  *g_out = g;
+  return c;
+}
+
 template <int L>
 __device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __restrict__ R, int n, double pivmin,
-                                          int k, int gbase) {
+                                          int k, int gbase, double* __restrict__ st) {
   long long steps = 0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     const bool need = act && !S.done;
     if (__ballot(need) == 0) break;
     const double p = need ? next_point<L>(S, k) : 0.0;
     double gv;
-    const int c = sturm_count_deriv(R, n, p, pivmin, &gv);
+    const int c = st ? staged_count_deriv(reinterpret_cast<const double*>(R), n, p, pivmin, st, &gv)
+                     : sturm_count_deriv(R, n, p, pivmin, &gv);
     if (need) steps += n;
     double pq[L], gq[L];
     int cq[L];
@@ -538,10 +600,12 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
   const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
   long long steps;
   if (__ballot(nd.rep != rep0) == 0) {
-    const Rep* R = wave_uniform(pool + nd.rep);
-    steps = refine_sweeps<L>(S, act, R, __builtin_amdgcn_readfirstlane(blk.n), blk.pivmin, k, gbase);
+    __shared__ double st[2 * 4 * kSG];
+    // per-lane copy of the (equal) pointer keeps the staged loads global
+    steps = refine_sweeps<L>(S, act, pool + nd.rep, __builtin_amdgcn_readfirstlane(blk.n), blk.pivmin, k, gbase,
+                             st);
   } else {
-    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase);
+    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase, nullptr);
   }
   if (act && k == 0) {
     lo_a[s] = S.lo;
@@ -805,32 +869,31 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
                                               Counters* __restrict__ C) {
   __shared__ double s_sigma;
   __shared__ long long s_off;
+  __shared__ double st[2 * 4 * kSG];
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   const Cluster cl = clusters[c];
   const Node par = N[cl.node];
   const Block blk = B[par.blk];
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
-  const Rep* R = wave_uniform(pool + par.rep);
+  const double* Rd = reinterpret_cast<const double*>(pool + par.rep);
   bool valid = false;
   double sigma = 0.0;
   if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
   // pass 1: growth of every candidate
   double sv = -sigma, gmax = 0.0;
   bool fin = true;
-  for (int i = 0; i + 1 < n; ++i) {
-    const double D = R[i].D, L = R[i].L, LD = R[i].LD;
+  staged_rows(Rd, n, st, [&](int i, double D, double L, double LD, double) {
     const double dp = D + sv;
+    gmax = fmax(gmax, fabs(dp));
+    if (i == n - 1) {
+      fin = fin && isfinite(dp);
+      return;
+    }
     const double lp = LD * rcp_nr2(dp);
     sv = fma(lp * L, sv, -sigma);
     fin = fin && isfinite(dp) && isfinite(lp);
-    gmax = fmax(gmax, fabs(dp));
-  }
-  {
-    const double dn = R[n - 1].D + sv;
-    fin = fin && isfinite(dn);
-    gmax = fmax(gmax, fabs(dn));
-  }
+  });
   const double growth = (valid && fin) ? gmax : INFINITY;
   double gr[kChildCand];
 #pragma unroll
@@ -893,22 +956,24 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   }
   __syncthreads();
   const long long off = s_off;
-  if (off < 0 || lane >= 4) return;
-  // pass 2: lanes 0..3 repeat the chosen transform; lane q stores field q
+  if (off < 0) return;
+  // pass 2: every lane repeats the chosen transform (the staging needs the
+  // whole wavefront); lanes 0..3 store field q of each row
   const double sg = s_sigma;
   double* Q = reinterpret_cast<double*>(pool + off);
   sv = -sg;
-  for (int i = 0; i + 1 < n; ++i) {
-    const double D = R[i].D, L = R[i].L, LD = R[i].LD;
+  staged_rows(Rd, n, st, [&](int i, double D, double L, double LD, double) {
     const double dp = D + sv;
+    if (i == n - 1) {
+      if (lane < 4) Q[(int64_t)i * 4 + lane] = (lane == 0) ? dp : 0.0;
+      return;
+    }
     const double lp = LD * rcp_nr2(dp);
     const double ld = lp * dp;
     const double v = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
-    Q[(int64_t)i * 4 + lane] = v;
+    if (lane < 4) Q[(int64_t)i * 4 + lane] = v;
     sv = fma(lp * L, sv, -sg);
-  }
-  const double dn = R[n - 1].D + sv;
-  Q[(int64_t)(n - 1) * 4 + lane] = (lane == 0) ? dn : 0.0;
+  });
 }
 
 // move the cluster's brackets into the child's frame (or, without a child,
@@ -954,26 +1019,35 @@ __global__ void k_clear_active(int64_t ntot, uint32_t* __restrict__ sflag) {
 }
 
 // ---------------------------------------------------------------------------
-// 8. eigenvectors of singletons: one lane per eigenvector, 64 consecutive slots
-//    per wavefront.  Per-lane work vectors live in a per-wavefront scratch area
-//    laid out [row][lane] so every lockstep access is one contiguous 512-byte
-//    line.  Twisted factorization of L D L^T - lam I:
-//      top-down   s_1 = -lam, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - lam
-//      bottom-up  p_n = D_n - lam, D-_{i+1} = LLD_i + p_{i+1}, t = D_i / D-_{i+1},
-//                 U-_i = L_i t, p_i = p_{i+1} t - lam
-//      twist      gamma_k = s_k + p_k + lam, r = argmin |gamma_k|
-//      solve      z_r = 1, z_i = -L+_i z_{i+1} (i < r), z_{i+1} = -U-_i z_i (i >= r)
-//    then lam <- lam + gamma_r / ||z||^2 (Rayleigh quotient) until converged.
+// 8. eigenvectors of singletons (Sec. 3.1.1, eq. errorangle): twisted
+//    factorization of L D L^T - lam I, one solve per Rayleigh-quotient step.
+//    Two lanes serve one eigenvector, 32 consecutive slots per wavefront:
+//      lane 2c     top-down stationary transform
+//                  s_1 = -lam,  s_{i+1} = s_i LLD_i / (D_i + s_i) - lam        (s_i -> S)
+//      lane 2c+1   bottom-up progressive transform
+//                  p_n = D_n - lam,  p_i = p_{i+1} D_i / (LLD_i + p_{i+1}) - lam  (p_i -> P)
+//    run concurrently: both are x' = x f / (b + x) - lam with (b, f) chosen by
+//    the lane's role.  Then
+//      twist   gamma_k = s_k + p_k + lam, r = argmin |gamma_k| (ties: smallest k),
+//              each lane scanning one half of k
+//      solve   z_r = 1; lane 2c walks up, z_i = -L+_i z_{i+1}, L+_i = LD_i / (D_i + s_i);
+//              lane 2c+1 walks down, z_{i+1} = -U-_i z_i, U-_i = L_i D_i / (LLD_i + p_{i+1});
+//              the quotients do not depend on z, so a step's dependency chain
+//              is one multiply
+//      then    lam <- lam + gamma_r / ||z||^2 until the stopping rule holds.
+//    Work vectors per wavefront: S and P, each [row][32] (z overwrites s above
+//    the twist and p below it).  Every lane reads its representation rows and
+//    work-vector entries through a ring of kPF registers refilled kPF steps
+//    ahead, so no step waits on a memory round trip.
 
-constexpr int kVecLanes = 64;
+constexpr int kPF = 16;         // prefetch depth, steps
+constexpr int kZRows = 32;      // rows per LDS transpose tile
 
 // angle accepted for a singleton's vector: eps * max(n / 16, 4 log2 n), a
 // small fraction of the O(n eps) orthogonality the method guarantees
 __device__ inline double rqi_angle_tol(int n) {
   return kEps * fmax((double)n * 0.0625, 4.0 * fmax(1.0, log2((double)n)));
 }
-constexpr int kVecRows = 16;  // rows per LDS transpose tile
-
 struct VecState {
   double lam, lo, hi;
   double gap;    // absolute gap to the nearest other eigenvalue of the leaf
@@ -1039,364 +1113,237 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   }
 }
 
-// Rayleigh-quotient iteration on twisted factorizations for the lanes with
-// `solve` set; z of the last solve is left in Bv ([row][lane] layout).  All
-// lanes run the lockstep loops; per-lane results are committed only by lanes
-// still iterating.
-template <bool UNI>
-__device__ inline void twisted_rqi(bool solve, const Rep* __restrict__ R, int n, int nmax, double pivmin,
-                                   double* __restrict__ A, double* __restrict__ Bv, int lane, VecState& V) {
+// t / den to about one ulp: reciprocal with one Newton step, then one
+// Newton correction of the quotient
+__device__ __forceinline__ double quot(double t, double den) {
+  const double r = rcp_nr1(den);
+  const double q0 = t * r;
+  const double res = fma(-den, q0, t);
+  return fma(r, res, q0);
+}
+
+__device__ __forceinline__ int clamp_row(int i, int n) { return min(max(i, 0), n - 1); }
+
+// compiler-only barrier: memory operations are not moved across it
+__device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
+
+// one Rayleigh-quotient iteration sequence for the eigenvector of lane pair c;
+// role 0 = top-down / upward lane, role 1 = bottom-up / downward lane.  Work
+// vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = L+_i then z above the
+// twist, W1 = U-_i then z from the twist down.  Returns the twist index of the
+// last solve (z is in W0 for rows < r and in W1 for rows >= r).
+template <int kPairSlots>
+__device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, int n, int nmax, double pivmin,
+                               double* __restrict__ S, double* __restrict__ P, double* __restrict__ W0,
+                               double* __restrict__ W1, int c, VecState& V) {
   bool conv = !solve;
   bool last = false;
+  int rout = 0;
+  // wave-uniform trip counts
+  int T = n - 1;
+  for (int o = 32; o > 0; o >>= 1) T = max(T, __shfl_xor(T, o, 64));
+  double* const X = role ? P : S;    // this lane's transform variable
+  double* const Wr = role ? W1 : W0;  // this lane's quotients, then z
   for (int it = 0; it <= kMaxRqi; ++it) {
     const bool go = solve && !conv;
-    // wave-uniform trip count: every lane runs the lockstep loops below
     if (__ballot(go) == 0) break;
     const double lam = V.lam;
-    // top-down stationary transform; s_i stored in A
-    double sv = -lam;
-    for (int i = 0; i + 1 < nmax; ++i) {
-      if (go && i + 1 < n) {
-        A[(int64_t)i * kVecLanes + lane] = sv;
-        const double D = R[i].D, L = R[i].L, LD = R[i].LD, LLD = R[i].LLD;
-        double dp = D + sv;
-        dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-        const double lp = LD * rcp_nr2(dp);
-        double tt = lp * L * sv;
-        tt = (lp == 0.0) ? LLD : tt;
-        sv = tt - lam;
+    // 1. the two transforms, concurrently; each step also stores the quotient
+    //    the solve will need (L+_i on the top lane, U-_i on the bottom lane)
+    double x;
+    if (role) {
+      x = R[n - 1].D - lam;
+      if (go) P[(int64_t)(n - 1) * kPairSlots + c] = x;
+    } else {
+      x = -lam;
+    }
+    {
+      Rep ring[kPF];
+#pragma unroll
+      for (int k = 0; k < kPF; ++k) ring[k] = R[clamp_row(role ? n - 2 - k : k, n)];
+      for (int t0 = 0; t0 < T; t0 += kPF) {
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+          const int t = t0 + k;
+          const Rep rr = ring[k];
+          if (t < T && go && t < n - 1) {
+            const int row = role ? n - 2 - t : t;
+            const double b = role ? rr.LLD : rr.D;
+            const double f = role ? rr.D : rr.LLD;
+            const double cz = role ? rr.D : rr.LD;
+            const double cq = role ? rr.L * rr.D : rr.LD;
+            double den = b + x;
+            den = (fabs(den) < pivmin) ? -pivmin : den;
+            const double rc = rcp_nr1(den);
+            const double xf = x * f;
+            const double q0 = xf * rc;
+            const double q = fma(rc, fma(-den, q0, xf), q0);
+            const double xn = (cz * rc == 0.0) ? f - lam : q - lam;
+            const double w0 = cq * rc;
+            const double w = fma(rc, fma(-den, w0, cq), w0);
+            const int64_t o = (int64_t)row * kPairSlots + c;
+            X[o] = role ? xn : x;
+            Wr[o] = w;
+            x = xn;
+          }
+          ring_fence();
+          ring[k] = R[clamp_row(role ? n - 2 - (t + kPF) : t + kPF, n)];
+        }
       }
     }
-    if (go) A[(int64_t)(n - 1) * kVecLanes + lane] = sv;
-    // bottom-up progressive transform; U-_i stored in Bv; twist index
-    double pv = go ? R[n - 1].D - lam : 0.0;
+    if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
+    __syncthreads();  // S and P complete and visible to the partner lane
+    // 2. twist index: lane 2c scans k < h, lane 2c+1 scans k >= h
+    const int h = n >> 1;
     double gmin = INFINITY;
     int r = -1;
+    {
+      const int kb = role ? h : 0;
+      const int kc = role ? n - h : h;
+      int T2 = kc;
+      for (int o = 32; o > 0; o >>= 1) T2 = max(T2, __shfl_xor(T2, o, 64));
+      double rs[kPF], rp[kPF];
+#pragma unroll
+      for (int k = 0; k < kPF; ++k) {
+        const int kk = clamp_row(kb + k, n);
+        rs[k] = S[(int64_t)kk * kPairSlots + c];
+        rp[k] = P[(int64_t)kk * kPairSlots + c];
+      }
+      for (int t0 = 0; t0 < T2; t0 += kPF) {
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+          const int t = t0 + k;
+          const double sv = rs[k], pv = rp[k];
+          if (t < T2 && go && t < kc) {
+            const double g = sv + pv + lam;
+            if (isfinite(g) && fabs(g) < fabs(gmin)) {
+              gmin = g;
+              r = kb + t;
+            }
+          }
+          const int kn = clamp_row(kb + t + kPF, n);
+          ring_fence();
+          rs[k] = S[(int64_t)kn * kPairSlots + c];
+          rp[k] = P[(int64_t)kn * kPairSlots + c];
+        }
+      }
+      // the partner's candidate; ties go to the smaller index (the upper half)
+      const double go_g = __shfl_xor(gmin, 1, 64);
+      const int go_r = __shfl_xor(r, 1, 64);
+      const double gt = role ? go_g : gmin, gb = role ? gmin : go_g;
+      const int rt = role ? go_r : r, rb = role ? r : go_r;
+      const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
+      gmin = take_b ? gb : gt;
+      r = take_b ? rb : rt;
+      if (r < 0) {
+        r = 0;
+        gmin = 0.0;
+      }
+    }
+    // 3. solves outward from the twist: z_i = -L+_i z_{i+1} upward (lane 2c),
+    //    z_{i+1} = -U-_i z_i downward (lane 2c+1); where a z is zero the row
+    //    of L D L^T - lam I gives the next one from the one before.  Rows are
+    //    visited in a wave-uniform order per role (top lanes from the largest
+    //    twist index of the wave down, bottom lanes from the smallest up), each
+    //    lane active on its own side of its twist, so every access is one
+    //    coalesced row of the work vector.
+    double nrm = 0.0, zbest = 0.0;
+    {
+      if (go && role) {
+        nrm = 1.0;
+        zbest = 1.0;
+      }
+      int rmax = (go && !role) ? r : 0;        // top lanes: rows rmax-1 .. 0
+      int rmin = (go && role) ? r : INT_MAX;   // bottom lanes: rows rmin .. n-2
+      for (int o = 32; o > 0; o >>= 1) {
+        rmax = max(rmax, __shfl_xor(rmax, o, 64));
+        rmin = min(rmin, __shfl_xor(rmin, o, 64));
+      }
+      if (rmin == INT_MAX) rmin = 0;  // no lane iterating: nothing to visit
+      int nb = (go && role) ? n - 1 - rmin : 0;
+      for (int o = 32; o > 0; o >>= 1) nb = max(nb, __shfl_xor(nb, o, 64));
+      const int T3 = max(rmax, nb);
+      const int base = role ? rmin : rmax - 1;
+      const int dir = role ? 1 : -1;
+      double rw[kPF];
+#pragma unroll
+      for (int k = 0; k < kPF; ++k) rw[k] = Wr[(int64_t)clamp_row(base + dir * k, n) * kPairSlots + c];
+      double zc = 1.0, zp = 0.0;
+      for (int t0 = 0; t0 < T3; t0 += kPF) {
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+          const int t = t0 + k;
+          const double w = rw[k];
+          const int row = base + dir * t;
+          const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
+          if (t < T3 && go && on) {
+            const bool first = role ? (row == r) : (row == r - 1);
+            double zn;
+            if (zc != 0.0 || first) {
+              zn = -w * zc;
+            } else if (zp != 0.0) {
+              const double ldi = R[row].LD;
+              const double ldn = R[row - dir].LD;
+              zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+            } else {
+              zn = 0.0;  // an underflowed tail stays zero
+            }
+            zn = isfinite(zn) ? zn : 0.0;
+            const int zrow = role ? row + 1 : row;
+            Wr[(int64_t)zrow * kPairSlots + c] = zn;
+            zp = zc;
+            zc = zn;
+            nrm += zn * zn;
+            // largest magnitude, ties to the smaller row
+            if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
+          }
+          ring_fence();
+          rw[k] = Wr[(int64_t)clamp_row(base + dir * (t + kPF), n) * kPairSlots + c];
+        }
+      }
+      if (go && role) W1[(int64_t)r * kPairSlots + c] = 1.0;
+      // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
+      const double nrm_o = __shfl_xor(nrm, 1, 64);
+      const double zb_o = __shfl_xor(zbest, 1, 64);
+      nrm += nrm_o;
+      const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
+      zbest = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+    }
+    __syncthreads();  // z complete before the next transform overwrites the work vectors
     if (go) {
-      const double g = A[(int64_t)(n - 1) * kVecLanes + lane] + pv + lam;
-      if (isfinite(g)) {
-        gmin = g;
-        r = n - 1;
-      }
+      rout = r;
+      rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
     }
-    for (int i = nmax - 2; i >= 0; --i) {
-      if (go && i <= n - 2) {
-        const double D = R[i].D, L = R[i].L, LLD = R[i].LLD;
-        double dm = LLD + pv;
-        dm = (fabs(dm) < pivmin) ? -pivmin : dm;
-        const double tt = D * rcp_nr2(dm);
-        Bv[(int64_t)i * kVecLanes + lane] = L * tt;
-        double pn = pv * tt - lam;
-        pn = (tt == 0.0) ? D - lam : pn;
-        pv = pn;
-        const double g = A[(int64_t)i * kVecLanes + lane] + pv + lam;
-        if (isfinite(g) && !(fabs(g) > fabs(gmin))) {
-          gmin = g;
-          r = i;
-        }
-      }
-    }
-    if (r < 0) {
-      r = 0;
-      gmin = 0.0;
-    }
-    // solve downward from the twist (z_i stored in Bv in place of U-_i)
-    double zc = 0.0, zp = 0.0;
-    double nrm = 1.0, zmaxv = 1.0;
-    int imax = r;
-    for (int i = 0; i + 1 < nmax; ++i) {
-      if (go && i + 1 < n && i >= r) {
-        if (i == r) zc = 1.0;
-        const double u = Bv[(int64_t)i * kVecLanes + lane];
-        Bv[(int64_t)i * kVecLanes + lane] = zc;
-        double zn;
-        if (zc != 0.0 || i == r) {
-          zn = -u * zc;
-        } else {
-          const double ldi = R[i].LD;
-          zn = (ldi != 0.0) ? -div_nr(R[i - 1].LD, ldi) * zp : 0.0;
-        }
-        zn = isfinite(zn) ? zn : 0.0;
-        zp = zc;
-        zc = zn;
-        nrm += zn * zn;
-        if (fabs(zn) > fabs(zmaxv)) {
-          zmaxv = zn;
-          imax = i + 1;
-        }
-      }
-    }
-    if (go) Bv[(int64_t)(n - 1) * kVecLanes + lane] = (r == n - 1) ? 1.0 : zc;
-    // solve upward from the twist, L+_i recomputed from the stored s_i
-    double z1 = 1.0, z2 = 0.0;
-    for (int i = nmax - 2; i >= 0; --i) {
-      if (go && i < r) {
-        double zi;
-        if (z1 != 0.0 || i + 2 > r) {
-          const double D = R[i].D, LD = R[i].LD;
-          double dp = D + A[(int64_t)i * kVecLanes + lane];
-          dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-          zi = -(LD * rcp_nr2(dp)) * z1;
-        } else {
-          const double ldi = R[i].LD;
-          zi = (ldi != 0.0) ? -div_nr(R[i + 1].LD, ldi) * z2 : 0.0;
-        }
-        zi = isfinite(zi) ? zi : 0.0;
-        Bv[(int64_t)i * kVecLanes + lane] = zi;
-        z2 = z1;
-        z1 = zi;
-        nrm += zi * zi;
-        if (fabs(zi) > fabs(zmaxv) || (fabs(zi) == fabs(zmaxv) && i < imax)) {
-          zmaxv = zi;
-          imax = i;
-        }
-      }
-    }
-    if (go) rqi_commit(V, conv, last, it, n, gmin, nrm, zmaxv, lam);
   }
   if (solve && !conv) V.lam_out = V.lam;
+  return rout;
 }
 
-
-// ---------------------------------------------------------------------------
-// The same iteration for a wavefront whose lanes share one representation (and
-// so one n): software-pipelined.  Representation rows are staged in LDS one
-// group of kRing rows ahead (one 2 x 8-byte load per lane per group), and the
-// per-lane work vectors are read through a ring of kRing registers that is
-// refilled kRing rows ahead, so no row step waits on a memory round trip.
-
-constexpr int kRing = 32;
-
-// rows [row0, row0 + kRing) of a representation (4 doubles a row) spread over
-// the wave: lane l holds doubles l and l + 64 of the group; rows outside
-// [0, n) read as zero
-__device__ inline void stage_fetch(const double* __restrict__ Rd, int64_t nd4, int64_t row0, int lane,
-                                   double q[2]) {
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int64_t idx = row0 * 4 + lane + 64 * k;
-    q[k] = (idx >= 0 && idx < nd4) ? Rd[idx] : 0.0;
-  }
-}
-
-__device__ inline void stage_put(double* __restrict__ st, int lane, const double q[2]) {
-  __syncthreads();
-  st[lane] = q[0];
-  st[lane + 64] = q[1];
-  __syncthreads();
-}
-
-__device__ inline void twisted_rqi_staged(bool solve, const double* __restrict__ Rd, int n, double pivmin,
-                                          double* __restrict__ A, double* __restrict__ Bv, int lane,
-                                          VecState& V, double* __restrict__ st) {
-  bool conv = !solve;
-  bool last = false;
-  const int64_t nd4 = 4 * (int64_t)n;
-  double q[2];
-  double ring[kRing];
-  for (int it = 0; it <= kMaxRqi; ++it) {
-    const bool go = solve && !conv;
-    if (__ballot(go) == 0) break;
-    const double lam = V.lam;
-    // top-down stationary transform; s_i stored in A
-    double sv = -lam;
-    stage_fetch(Rd, nd4, 0, lane, q);
-    for (int g = 0; g < n - 1; g += kRing) {
-      stage_put(st, lane, q);
-      stage_fetch(Rd, nd4, g + kRing, lane, q);
-#pragma unroll
-      for (int k = 0; k < kRing; ++k) {
-        const int i = g + k;
-        if (i + 1 < n) {
-          const double D = st[4 * k], L = st[4 * k + 1], LD = st[4 * k + 2], LLD = st[4 * k + 3];
-          if (go) A[(int64_t)i * kVecLanes + lane] = sv;
-          double dp = D + sv;
-          dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-          const double lp = LD * rcp_nr2(dp);
-          double tt = lp * L * sv;
-          tt = (lp == 0.0) ? LLD : tt;
-          sv = tt - lam;
-        }
-      }
-    }
-    if (go) A[(int64_t)(n - 1) * kVecLanes + lane] = sv;
-    // bottom-up progressive transform; U-_i stored in Bv; twist index
-    double pv = Rd[(int64_t)(n - 1) * 4] - lam;
-    double gmin = INFINITY;
-    int r = -1;
-    {
-      const double g = sv + pv + lam;
-      if (go && isfinite(g)) {
-        gmin = g;
-        r = n - 1;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kRing; ++k) {
-      const int row = n - 2 - k;
-      ring[k] = (row >= 0) ? A[(int64_t)row * kVecLanes + lane] : 0.0;
-    }
-    stage_fetch(Rd, nd4, (int64_t)n - 1 - kRing, lane, q);
-    for (int g = n - 2; g >= 0; g -= kRing) {
-      const int base = g - kRing + 1;
-      stage_put(st, lane, q);
-      stage_fetch(Rd, nd4, (int64_t)base - kRing, lane, q);
-#pragma unroll
-      for (int k = 0; k < kRing; ++k) {
-        const int i = g - k;
-        const double a = ring[k];
-        if (i - kRing >= 0) ring[k] = A[(int64_t)(i - kRing) * kVecLanes + lane];
-        if (i >= 0) {
-          const int o = 4 * (kRing - 1 - k);
-          const double D = st[o], L = st[o + 1], LLD = st[o + 3];
-          double dm = LLD + pv;
-          dm = (fabs(dm) < pivmin) ? -pivmin : dm;
-          const double tt = D * rcp_nr2(dm);
-          if (go) Bv[(int64_t)i * kVecLanes + lane] = L * tt;
-          double pn = pv * tt - lam;
-          pn = (tt == 0.0) ? D - lam : pn;
-          pv = pn;
-          const double gv = a + pv + lam;
-          if (go && isfinite(gv) && !(fabs(gv) > fabs(gmin))) {
-            gmin = gv;
-            r = i;
-          }
-        }
-      }
-    }
-    if (go && r < 0) {
-      r = 0;
-      gmin = 0.0;
-    }
-    // wave-wide range of twist indices: rows below the smallest need no
-    // downward step, rows above the largest no upward step
-    int rmin = go ? r : n, rmax = go ? r : 0;
-    for (int o = 32; o > 0; o >>= 1) {
-      rmin = min(rmin, __shfl_xor(rmin, o, 64));
-      rmax = max(rmax, __shfl_xor(rmax, o, 64));
-    }
-    // solve downward from the twist (z_i stored in Bv in place of U-_i)
-    double zc = 0.0, zp = 0.0;
-    double nrm = 1.0, zmaxv = 1.0;
-    int imax = r;
-    {
-      const int i0 = min(rmin, n - 1);
-#pragma unroll
-      for (int k = 0; k < kRing; ++k) {
-        const int row = i0 + k;
-        ring[k] = (row + 1 < n) ? Bv[(int64_t)row * kVecLanes + lane] : 0.0;
-      }
-      double ldp = (i0 > 0) ? Rd[(int64_t)(i0 - 1) * 4 + 2] : 0.0;  // LD of the row above
-      stage_fetch(Rd, nd4, i0, lane, q);
-      for (int g = i0; g + 1 < n; g += kRing) {
-        stage_put(st, lane, q);
-        stage_fetch(Rd, nd4, (int64_t)g + kRing, lane, q);
-#pragma unroll
-        for (int k = 0; k < kRing; ++k) {
-          const int i = g + k;
-          const double u = ring[k];
-          if (i + kRing + 1 < n) ring[k] = Bv[(int64_t)(i + kRing) * kVecLanes + lane];
-          if (i + 1 < n) {
-            const double ldi = st[4 * k + 2];
-            if (go && i >= r) {
-              if (i == r) zc = 1.0;
-              Bv[(int64_t)i * kVecLanes + lane] = zc;
-              double zn;
-              if (zc != 0.0 || i == r) {
-                zn = -u * zc;
-              } else {
-                zn = (ldi != 0.0) ? -div_nr(ldp, ldi) * zp : 0.0;
-              }
-              zn = isfinite(zn) ? zn : 0.0;
-              zp = zc;
-              zc = zn;
-              nrm += zn * zn;
-              if (fabs(zn) > fabs(zmaxv)) {
-                zmaxv = zn;
-                imax = i + 1;
-              }
-            }
-            ldp = ldi;
-          }
-        }
-      }
-    }
-    if (go) Bv[(int64_t)(n - 1) * kVecLanes + lane] = (r == n - 1) ? 1.0 : zc;
-    // solve upward from the twist, L+_i recomputed from the stored s_i
-    {
-      const int i1 = max(rmax - 1, -1);
-      double z1 = 1.0, z2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < kRing; ++k) {
-        const int row = i1 - k;
-        ring[k] = (row >= 0) ? A[(int64_t)row * kVecLanes + lane] : 0.0;
-      }
-      double ldn = (i1 + 1 < n && i1 >= 0) ? Rd[(int64_t)(i1 + 1) * 4 + 2] : 0.0;  // LD of the row below
-      stage_fetch(Rd, nd4, (int64_t)i1 - kRing + 1, lane, q);
-      for (int g = i1; g >= 0; g -= kRing) {
-        const int base = g - kRing + 1;
-        stage_put(st, lane, q);
-        stage_fetch(Rd, nd4, (int64_t)base - kRing, lane, q);
-#pragma unroll
-        for (int k = 0; k < kRing; ++k) {
-          const int i = g - k;
-          const double a = ring[k];
-          if (i - kRing >= 0) ring[k] = A[(int64_t)(i - kRing) * kVecLanes + lane];
-          if (i >= 0) {
-            const int o = 4 * (kRing - 1 - k);
-            const double D = st[o], LD = st[o + 2];
-            if (go && i < r) {
-              double zi;
-              if (z1 != 0.0 || i + 2 > r) {
-                double dp = D + a;
-                dp = (fabs(dp) < pivmin) ? -pivmin : dp;
-                zi = -(LD * rcp_nr2(dp)) * z1;
-              } else {
-                zi = (LD != 0.0) ? -div_nr(ldn, LD) * z2 : 0.0;
-              }
-              zi = isfinite(zi) ? zi : 0.0;
-              Bv[(int64_t)i * kVecLanes + lane] = zi;
-              z2 = z1;
-              z1 = zi;
-              nrm += zi * zi;
-              if (fabs(zi) > fabs(zmaxv) || (fabs(zi) == fabs(zmaxv) && i < imax)) {
-                zmaxv = zi;
-                imax = i;
-              }
-            }
-            ldn = LD;
-          }
-        }
-      }
-    }
-    if (go) rqi_commit(V, conv, last, it, n, gmin, nrm, zmaxv, lam);
-  }
-  if (solve && !conv) V.lam_out = V.lam;
-}
-
+template <int kPairSlots>
 __global__ void __launch_bounds__(64) k_vectors(
     const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
     const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
     const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
     const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
     const double* __restrict__ sgap, const Rep* __restrict__ pool, const double* __restrict__ ds,
-    double* __restrict__ scratch,
-    double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
-  __shared__ double tile[kVecLanes][kVecRows + 1];
-  __shared__ double stage[4 * kRing];
-  __shared__ int64_t s_col[kVecLanes];
-  __shared__ int64_t s_zoff[kVecLanes];
-  __shared__ int s_n[kVecLanes];
-  __shared__ int64_t s_lrow0[kVecLanes];
-  __shared__ int64_t s_pn[kVecLanes];
+    double* __restrict__ scratch, double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
+  __shared__ double tile[kPairSlots][kZRows + 1];
+  __shared__ int64_t s_col[kPairSlots];
+  __shared__ int64_t s_zoff[kPairSlots];
+  __shared__ int s_n[kPairSlots];
+  __shared__ int64_t s_lrow0[kPairSlots];
+  __shared__ int64_t s_pn[kPairSlots];
   const int lane = threadIdx.x;
+  const int c = lane >> 1;
+  const int role = lane & 1;
   const int ci = blockIdx.x;
   if (ci >= nchunks) return;
   const int64_t chunk = chunks[ci];
-  const int64_t s = chunk * kVecLanes + lane;
-  double* A = scratch + chunk_off[ci];
+  const int64_t s = chunk * kPairSlots + c;
+  double* S = scratch + chunk_off[ci];
+  const bool lane_slot = c < kPairSlots;  // lanes beyond 2 * kPairSlots idle
   bool act = false;
-  if (s < ntot) act = (sflag[s] & F_SINGLETON) && scol[s] >= 0;
+  if (lane_slot && s < ntot) act = (sflag[s] & F_SINGLETON) && scol[s] >= 0;
   const uint64_t am = __ballot(act);
   if (am == 0) return;
   const int64_t sf = __shfl(s, first_lane(am), 64);
@@ -1407,7 +1354,10 @@ __global__ void __launch_bounds__(64) k_vectors(
   const int n = blk.n;
   int nmax = act ? n : 0;
   for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-  double* Bv = A + (int64_t)nmax * kVecLanes;  // second work vector
+  double* Pv = S + (int64_t)nmax * kPairSlots;
+  double* W0 = Pv + (int64_t)nmax * kPairSlots;
+  double* W1 = W0 + (int64_t)nmax * kPairSlots;
+  const int cs = lane_slot ? c : 0;  // scratch column (idle lanes never store)
   VecState V;
   V.lo = lo_a[ss];
   V.hi = hi_a[ss];
@@ -1423,74 +1373,73 @@ __global__ void __launch_bounds__(64) k_vectors(
   V.rq = 0;
   V.fallback = false;
   const bool solve = act && n > 1;
-  if (act && n == 1) Bv[lane] = 1.0;
-  const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
-  if (__ballot(nd.rep != rep0) == 0) {
-    // per-lane copy of the (equal) pointer keeps the loads in the global
-    // address space; each lane fetches its own part of a staged group
-    const double* Rd = reinterpret_cast<const double*>(pool + nd.rep);
-    twisted_rqi_staged(solve, Rd, __builtin_amdgcn_readfirstlane(n), blk.pivmin, A, Bv, lane, V, stage);
-  } else {
-    twisted_rqi<false>(solve, pool + nd.rep, n, nmax, blk.pivmin, A, Bv, lane, V);
-  }
+  int r = 0;
+  if (act && n == 1 && role) W1[c] = 1.0;
+  r = pair_rqi<kPairSlots>(solve, role, pool + nd.rep, n, nmax, blk.pivmin, S, Pv, W0, W1, cs, V);
   double scale = 1.0;
   if (solve) {
     scale = 1.0 / sqrt(V.nrm);
     if (V.zmaxv < 0.0) scale = -scale;
   }
-  // eigenvalue
-  if (act) {
+  // eigenvalue (once per pair)
+  if (act && !role) {
     const Problem pr = P[blk.prob];
     const double wv = (n == 1) ? ds[s] / pr.scale : (nd.acc + V.lam_out) / pr.scale;
     w_out[pr.off + col] = wv;
-    s_col[lane] = col;
-    s_zoff[lane] = pr.zoff + col * pr.ldz;
-    s_n[lane] = n;
-    s_lrow0[lane] = blk.lrow0;
-    s_pn[lane] = pr.n;
-  } else {
-    s_col[lane] = -1;
-    s_n[lane] = 0;
-    s_pn[lane] = 0;
+    s_col[c] = col;
+    s_zoff[c] = pr.zoff + col * pr.ldz;
+    s_n[c] = n;
+    s_lrow0[c] = blk.lrow0;
+    s_pn[c] = pr.n;
+  } else if (!role && lane_slot) {
+    s_col[c] = -1;
+    s_n[c] = 0;
+    s_pn[c] = 0;
   }
   __syncthreads();
   if (Z != nullptr) {
-    // write z * scale into column-major Z through an LDS transpose: each pass
-    // stages 16 rows x 64 columns, then every column gets one contiguous
-    // 128-byte segment (16 lanes per column, 4 columns per instruction)
-    for (int r0 = 0; r0 < nmax; r0 += kVecRows) {
-      // all loads of the tile first (rows below nmax lie inside the work
-      // vector of every lane), then one wait
-      double v[kVecRows];
+    // z * scale into column-major Z through an LDS transpose: each pass stages
+    // 32 rows x 32 columns (lane 2c rows 0-15 of column c, lane 2c+1 rows
+    // 16-31), then every column gets one contiguous 256-byte segment
+    for (int r0 = 0; r0 < nmax; r0 += kZRows) {
+      double v[kZRows / 2];
 #pragma unroll
-      for (int k = 0; k < kVecRows; ++k) v[k] = (r0 + k < nmax) ? Bv[(int64_t)(r0 + k) * kVecLanes + lane] : 0.0;
+      for (int k = 0; k < kZRows / 2; ++k) {
+        const int row = r0 + role * (kZRows / 2) + k;
+        const double* src = (row < r) ? W0 : W1;
+        v[k] = (row < nmax) ? src[(int64_t)row * kPairSlots + cs] : 0.0;
+      }
+      if (lane_slot) {
 #pragma unroll
-      for (int k = 0; k < kVecRows; ++k) tile[lane][k] = (act && r0 + k < n) ? v[k] * scale : 0.0;
+        for (int k = 0; k < kZRows / 2; ++k) {
+          const int row = r0 + role * (kZRows / 2) + k;
+          tile[c][role * (kZRows / 2) + k] = (act && row < n) ? v[k] * scale : 0.0;
+        }
+      }
       __syncthreads();
-      const int rr = lane & (kVecRows - 1);
-      for (int cgrp = 0; cgrp < kVecLanes; cgrp += 4) {
-        const int cl = cgrp + (lane >> 4);
-        const int nn = s_n[cl];
+      const int rr = lane & (kZRows - 1);
+      for (int cg = 0; cg < kPairSlots; cg += 2) {
+        const int cl = cg + (lane >> 5);
         const int i = r0 + rr;
-        if (s_col[cl] >= 0 && i < nn) Z[s_zoff[cl] + s_lrow0[cl] + i] = tile[cl][rr];
+        if (s_col[cl] >= 0 && i < s_n[cl]) Z[s_zoff[cl] + s_lrow0[cl] + i] = tile[cl][rr];
       }
       __syncthreads();
     }
     // rows of the problem outside the block are exact zeros
-    for (int cl = 0; cl < kVecLanes; ++cl) {
+    for (int cl = 0; cl < kPairSlots; ++cl) {
       if (s_col[cl] < 0) continue;
       const int64_t pn = s_pn[cl];
       const int64_t r0 = s_lrow0[cl];
       const int64_t r1 = r0 + s_n[cl];
       if (r0 == 0 && r1 == pn) continue;
-      for (int64_t i = lane; i < pn; i += kVecLanes)
+      for (int64_t i = lane; i < pn; i += 64)
         if (i < r0 || i >= r1) Z[s_zoff[cl] + i] = 0.0;
     }
   }
-  if (act) {
+  if (act && !role) {
     atomicAdd(&C->qds_steps, (unsigned long long)V.qsteps);
     atomicAdd(&C->vec_rows, (unsigned long long)(V.qsteps / 4));
-    if (Z != nullptr) atomicAdd(&C->z_entries, (unsigned long long)s_pn[lane]);
+    if (Z != nullptr) atomicAdd(&C->z_entries, (unsigned long long)s_pn[c]);
     atomicAdd(&C->rqi, (unsigned long long)V.rq);
     atomicAdd(&C->singletons, 1ull);
     if (V.fallback) atomicAdd(&C->fallbacks, 1ull);
@@ -1502,13 +1451,13 @@ __global__ void __launch_bounds__(64) k_vectors(
   }
 }
 
-// scratch rows each 64-slot chunk needs (0: no singleton to compute)
+// scratch rows each chunk of `slots` slots needs (0: no singleton to compute)
 __global__ void k_chunk_rows(const Block* __restrict__ B, int64_t ntot, const int32_t* __restrict__ sblk,
-                             const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                             const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol, int slots,
                              int32_t* __restrict__ rows) {
-  const int64_t s = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * slots + (threadIdx.x & (slots - 1));
   int v = 0;
-  if (s < ntot && (sflag[s] & F_SINGLETON) && scol[s] >= 0) v = B[sblk[s]].n;
+  if ((int)threadIdx.x < slots && s < ntot && (sflag[s] & F_SINGLETON) && scol[s] >= 0) v = B[sblk[s]].n;
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   if (threadIdx.x == 0) rows[blockIdx.x] = v;
 }
@@ -1712,18 +1661,27 @@ void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag) {
 }
 
 void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
-                       const int64_t* scol, int32_t* rows) {
-  const int64_t nch = (ntot + 63) / 64;
-  hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)nch), dim3(64), 0, st, B, ntot, sblk, sflag, scol, rows);
+                       const int64_t* scol, int slots, int32_t* rows) {
+  const int64_t nch = (ntot + slots - 1) / slots;
+  hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)nch), dim3(64), 0, st, B, ntot, sblk, sflag, scol, slots, rows);
 }
 
 void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
                     const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
                     const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const double* sgap,
-                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C) {
+                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C,
+                    int slots) {
   if (nchunks == 0) return;
-  hipLaunchKernelGGL(k_vectors, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, sblk,
-                     snode, sflag, scol, lo, hi, sgap, pool, ds, scratch, w, Z, C);
+#define MRRR_VEC(SL)                                                                                             \
+  hipLaunchKernelGGL(k_vectors<SL>, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, sblk, \
+                     snode, sflag, scol, lo, hi, sgap, pool, ds, scratch, w, Z, C)
+  if (slots == 8)
+    MRRR_VEC(8);
+  else if (slots == 16)
+    MRRR_VEC(16);
+  else
+    MRRR_VEC(32);
+#undef MRRR_VEC
 }
 
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C) {
