@@ -57,12 +57,42 @@ def cpu_baseline(n):
             "sample": f"random n={n} (seed 2001), eigenpairs 1..{k} (il..iu), {dt:.1f} s on 1 host thread"}
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1205_2107_amd", "csrc", "mrrr_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_vectors_traffic_n20000.md")
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    when there is none or the kernel source changed since it was taken."""
+    if kernel != "vectors" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k.strip("`")] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(prof):
     """dominant kernel by event time; ALU-bound kernels against the FP64 vector
     peak, the eigenvector kernel against HBM bandwidth"""
     name = max(prof, key=lambda k: prof[k]["ms"])
     p = prof[name]
-    out = {"kernel": name, "launches": p["launches"], "avg_ms": p["ms"] / max(p["launches"], 1), "traffic": None}
+    out = {"kernel": name, "launches": p["launches"], "avg_ms": p["ms"] / max(p["launches"], 1),
+           "traffic": measured_traffic(name)}
     if name == "vectors":
         ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -113,6 +143,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--looped-count", type=int, default=512)
+    ap.add_argument("--profile-once", action="store_true",
+                    help="one warm-up and one solve of each input type (for a profiler run); no JSON")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="copy BYTES between two device buffers (counter calibration); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -124,10 +158,26 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.n
+    if args.copy_calib:
+        src = torch.ones(args.copy_calib // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {src.numel() * 8} bytes")
+        return
     log(f"[bench] generating inputs n={n}")
     inputs = make_inputs(n)
     dev = [(name, torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda")) for name, d, e in inputs]
     torch.cuda.synchronize()
+    if args.profile_once:
+        for name, d, e in dev:
+            M.eigh_tridiagonal(d, e)
+            torch.cuda.synchronize()
+            M.eigh_tridiagonal(d, e)
+            torch.cuda.synchronize()
+            log(f"[bench] profiled {name}")
+        return
     log("[bench] warmup")
     for _ in range(args.warmup):
         for name, d, e in dev:

@@ -21,7 +21,7 @@ constexpr double kRelgapTol = 1.0e-3;                     // Sec. 3.1.1 footnote
 constexpr int kMaxDepth = 64;
 constexpr double kGrowthBound = 8.0;   // child accepted outright if max|D_c| <= 8 spdiam
 constexpr double kPertScale = 4.0;     // root perturbation 4 eps u, u in [-1, 1)
-constexpr int kMaxRqi = 8;              // Rayleigh-quotient solves per singleton (one more to repeat the best)
+constexpr int kMaxRqi = 5;              // Rayleigh-quotient solves per singleton (one more to repeat the best)
 constexpr int kMaxSweeps = 200;        // refinement sweeps per eigenvalue (cap)
 
 // slot flags

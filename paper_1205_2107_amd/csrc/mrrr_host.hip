@@ -314,9 +314,9 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       rep->levels = level + 1;
       const int ncl = std::min(hc.nclusters, max_clusters);
       if (ncl == 0) break;
-      // capacity for the new nodes and one child representation per cluster
+      // capacity for the new nodes and two child-sized regions per cluster
       if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
-      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + (size_t)hc.cluster_rows;
+      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + 2 * (size_t)hc.cluster_rows;
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
         if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
         dpool = P_<Rep>(W.pool);

@@ -831,11 +831,11 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
 //    growing geometrically from the end eigenvalue's bracket to half the outer
 //    gap -- by the stationary qds
 //      s_1 = -sigma, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - sigma
-//    reading the parent through the scalar cache and keeping only the element
-//    growth max|D+_i|.  The closest shift whose growth is within the bound wins
-//    (ties between the two ends: the smaller growth); without one, the least
-//    growth.  Pass 2: four lanes repeat the chosen transform and store D, L, LD,
-//    LLD of each row as one contiguous 32-byte write.
+//    over LDS-staged parent rows, keeping the element growth max|D+_i|; the
+//    two closest candidates also store their rows as they go.  The closest
+//    shift whose growth is within the bound wins (ties between the two ends:
+//    the smaller growth); without one, the least growth.  Only when a farther
+//    candidate wins does pass 2 repeat its transform and store it.
 
 constexpr int kChildLevels = 8;
 constexpr int kChildCand = 2 * kChildLevels;
@@ -867,8 +867,6 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
                                               const double* __restrict__ lo, const double* __restrict__ hi,
                                               Rep* __restrict__ pool, unsigned long long pool_cap,
                                               Counters* __restrict__ C) {
-  __shared__ double s_sigma;
-  __shared__ long long s_off;
   __shared__ double st[2 * 4 * kSG];
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
@@ -877,9 +875,22 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   const Block blk = B[par.blk];
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
   const double* Rd = reinterpret_cast<const double*>(pool + par.rep);
+  // two child-sized regions: the closest candidates at the left and right end
+  // (lanes 0, 1) store their rows while pass 1 runs; usually one of them wins
+  long long base = -1;
+  if (lane == 0) {
+    base = (long long)atomicAdd(&C->pool_used, 2ull * (unsigned long long)n);
+    if ((unsigned long long)base + 2ull * (unsigned long long)n > pool_cap) {
+      set_status(C, 3);
+      base = -1;
+    }
+  }
+  base = __shfl(base, 0, 64);
   bool valid = false;
   double sigma = 0.0;
   if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
+  const bool spec = base >= 0 && lane < 2;
+  double* Qs = reinterpret_cast<double*>(pool + (base >= 0 ? base : 0) + (lane & 1) * (int64_t)n);
   // pass 1: growth of every candidate
   double sv = -sigma, gmax = 0.0;
   bool fin = true;
@@ -888,9 +899,22 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
     gmax = fmax(gmax, fabs(dp));
     if (i == n - 1) {
       fin = fin && isfinite(dp);
+      if (spec) {
+        Qs[(int64_t)i * 4] = dp;
+        Qs[(int64_t)i * 4 + 1] = 0.0;
+        Qs[(int64_t)i * 4 + 2] = 0.0;
+        Qs[(int64_t)i * 4 + 3] = 0.0;
+      }
       return;
     }
     const double lp = LD * rcp_nr2(dp);
+    if (spec) {
+      const double ld = lp * dp;
+      Qs[(int64_t)i * 4] = dp;
+      Qs[(int64_t)i * 4 + 1] = lp;
+      Qs[(int64_t)i * 4 + 2] = ld;
+      Qs[(int64_t)i * 4 + 3] = ld * lp;
+    }
     sv = fma(lp * L, sv, -sigma);
     fin = fin && isfinite(dp) && isfinite(lp);
   });
@@ -898,30 +922,27 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   double gr[kChildCand];
 #pragma unroll
   for (int k = 0; k < kChildCand; ++k) gr[k] = __shfl(growth, k, 64);
-  if (lane == 0) {
-    const double bound = kGrowthBound * (blk.gu - blk.gl);
-    int pick = -1;
-    for (int lev = 0; lev < kChildLevels && pick < 0; ++lev) {
-      const double a = gr[2 * lev], b = gr[2 * lev + 1];
-      if (a <= bound || b <= bound) pick = (a <= b) ? 2 * lev : 2 * lev + 1;
-    }
-    if (pick < 0) {
-      atomicAdd(&C->child_reject, 1ull);
-      double best = INFINITY;
-      for (int k = 0; k < kChildCand; ++k)
-        if (gr[k] < best) {
-          best = gr[k];
-          pick = k;
-        }
-    }
-    long long off = -1;
-    if (pick >= 0) {
-      off = (long long)atomicAdd(&C->pool_used, (unsigned long long)n);
-      if ((unsigned long long)off + (unsigned long long)n > pool_cap) {
-        set_status(C, 3);
-        off = -1;
+  // the same decision in every lane (identical inputs)
+  const double bound = kGrowthBound * (blk.gu - blk.gl);
+  int pick = -1;
+  for (int lev = 0; lev < kChildLevels && pick < 0; ++lev) {
+    const double a = gr[2 * lev], b = gr[2 * lev + 1];
+    if (a <= bound || b <= bound) pick = (a <= b) ? 2 * lev : 2 * lev + 1;
+  }
+  const bool forced = pick < 0;
+  if (forced) {
+    double best = INFINITY;
+    for (int k = 0; k < kChildCand; ++k)
+      if (gr[k] < best) {
+        best = gr[k];
+        pick = k;
       }
-    }
+  }
+  const long long off = (pick < 0 || base < 0) ? -1 : base + (pick < 2 ? pick : 0) * (long long)n;
+  bool v;
+  const double sg = (pick >= 0) ? child_sigma(cl, blk, lo, hi, pick, &v) : 0.0;
+  if (lane == 0) {
+    if (forced) atomicAdd(&C->child_reject, 1ull);
     Node nd;
     nd.blk = par.blk;
     nd.parent = cl.node;
@@ -937,29 +958,21 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
       nd.acc = par.acc;
       nd.sigma = 0.0;
       nd.depth = -1;
-      s_sigma = 0.0;
     } else {
-      bool v;
-      const double sg = child_sigma(cl, blk, lo, hi, pick, &v);
       nd.rep = off;
       nd.growth = gr[pick] / (blk.gu - blk.gl);
       nd.acc = par.acc + sg;
       nd.sigma = sg;
       nd.depth = par.depth + 1;
       atomicMax(&C->max_depth, nd.depth);
-      s_sigma = sg;
       atomicAdd(&C->qds_steps, (unsigned long long)n);
       atomicAdd(&C->child_steps, (unsigned long long)n);
     }
-    s_off = off;
     N[node_base + c] = nd;
   }
-  __syncthreads();
-  const long long off = s_off;
-  if (off < 0) return;
-  // pass 2: every lane repeats the chosen transform (the staging needs the
-  // whole wavefront); lanes 0..3 store field q of each row
-  const double sg = s_sigma;
+  if (off < 0 || pick < 2) return;
+  // pass 2 (a farther candidate won): every lane repeats its transform (the
+  // staging needs the whole wavefront); lanes 0..3 store field q of each row
   double* Q = reinterpret_cast<double*>(pool + off);
   sv = -sg;
   staged_rows(Rd, n, st, [&](int i, double D, double L, double LD, double) {
@@ -970,8 +983,8 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
     }
     const double lp = LD * rcp_nr2(dp);
     const double ld = lp * dp;
-    const double v = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
-    if (lane < 4) Q[(int64_t)i * 4 + lane] = v;
+    const double val = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
+    if (lane < 4) Q[(int64_t)i * 4 + lane] = val;
     sv = fma(lp * L, sv, -sg);
   });
 }
@@ -1021,32 +1034,30 @@ __global__ void k_clear_active(int64_t ntot, uint32_t* __restrict__ sflag) {
 // ---------------------------------------------------------------------------
 // 8. eigenvectors of singletons (Sec. 3.1.1, eq. errorangle): twisted
 //    factorization of L D L^T - lam I, one solve per Rayleigh-quotient step.
-//    Two lanes serve one eigenvector, 32 consecutive slots per wavefront:
+//    Two lanes serve one eigenvector, up to 32 consecutive slots per wavefront:
 //      lane 2c     top-down stationary transform
 //                  s_1 = -lam,  s_{i+1} = s_i LLD_i / (D_i + s_i) - lam        (s_i -> S)
 //      lane 2c+1   bottom-up progressive transform
 //                  p_n = D_n - lam,  p_i = p_{i+1} D_i / (LLD_i + p_{i+1}) - lam  (p_i -> P)
 //    run concurrently: both are x' = x f / (b + x) - lam with (b, f) chosen by
-//    the lane's role.  Then
+//    the lane's role; each step also stores the quotient the solve needs,
+//    L+_i = LD_i / (D_i + s_i) or U-_i = L_i D_i / (LLD_i + p_{i+1}).  Then
 //      twist   gamma_k = s_k + p_k + lam, r = argmin |gamma_k| (ties: smallest k),
 //              each lane scanning one half of k
-//      solve   z_r = 1; lane 2c walks up, z_i = -L+_i z_{i+1}, L+_i = LD_i / (D_i + s_i);
-//              lane 2c+1 walks down, z_{i+1} = -U-_i z_i, U-_i = L_i D_i / (LLD_i + p_{i+1});
-//              the quotients do not depend on z, so a step's dependency chain
-//              is one multiply
+//      solve   z_r = 1; lane 2c walks up, z_i = -L+_i z_{i+1}; lane 2c+1 walks
+//              down, z_{i+1} = -U-_i z_i (the dependency chain of a step is one
+//              multiply)
 //      then    lam <- lam + gamma_r / ||z||^2 until the stopping rule holds.
-//    Work vectors per wavefront: S and P, each [row][32] (z overwrites s above
-//    the twist and p below it).  Every lane reads its representation rows and
-//    work-vector entries through a ring of kPF registers refilled kPF steps
-//    ahead, so no step waits on a memory round trip.
+//    Work vectors per wavefront: S, P, W0 (L+, then z above the twist), W1 (U-,
+//    then z from the twist down), each [row][slots].  Every loop is software
+//    pipelined (pipelined()): loads run kHB .. 2 kHB - 1 steps ahead of use.
 
-constexpr int kPF = 16;         // prefetch depth, steps
 constexpr int kZRows = 32;      // rows per LDS transpose tile
 
-// angle accepted for a singleton's vector: eps * max(n / 16, 4 log2 n), a
+// angle accepted for a singleton's vector: eps * max(n / 8, 4 log2 n), a
 // small fraction of the O(n eps) orthogonality the method guarantees
 __device__ inline double rqi_angle_tol(int n) {
-  return kEps * fmax((double)n * 0.0625, 4.0 * fmax(1.0, log2((double)n)));
+  return kEps * fmax((double)n * 0.125, 4.0 * fmax(1.0, log2((double)n)));
 }
 struct VecState {
   double lam, lo, hi;
@@ -1080,9 +1091,9 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
   // resid / gap bounds the sine of the angle between z and the eigenvector
   // (gap theorem); otherwise stop once the correction is below half an ulp
-  // of lambda.  At the rounding floor (two solves without a smaller
-  // residual, or the iteration cap) the solve with the smallest residual
-  // is repeated, unless it is the current one.
+  // of lambda.  At the rounding floor (a solve without a smaller residual,
+  // or the iteration cap) the solve with the smallest residual is repeated,
+  // unless it is the current one.
   const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
   const bool improved = resid < V.resid;
   if (improved) {
@@ -1094,7 +1105,7 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   if (last || small) {
     conv = true;
     V.lam_out = inside ? lamc : lam;
-  } else if (V.stall >= 2 || it + 1 >= kMaxRqi) {
+  } else if (V.stall >= 1 || it + 1 >= kMaxRqi) {
     V.fallback = true;
     if (improved) {
       conv = true;
@@ -1127,6 +1138,50 @@ __device__ __forceinline__ int clamp_row(int i, int n) { return min(max(i, 0), n
 // compiler-only barrier: memory operations are not moved across it
 __device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
 
+// the three fields of a representation row the transforms use
+struct Row3 {
+  double D, LD, LLD;
+};
+__device__ __forceinline__ Row3 load_row3(const Rep* __restrict__ R, int i) {
+  Row3 r;
+  r.D = R[i].D;
+  r.LD = R[i].LD;
+  r.LLD = R[i].LLD;
+  return r;
+}
+
+constexpr int kHB = 8;  // steps per half of a double buffer
+
+// software pipeline over steps t = 0 .. T - 1 (T wave-uniform): the loads of
+// one half of kHB steps are issued while the other half is consumed, so every
+// value arrives kHB .. 2 kHB - 1 steps after its load was issued.  load(t)
+// must be in bounds for any t >= 0; step(t, v) sees steps in order.
+template <class Ld, class St>
+__device__ __forceinline__ void pipelined(int T, Ld&& load, St&& step) {
+  using V = decltype(load(0));
+  V a[kHB], b[kHB];
+#pragma unroll
+  for (int k = 0; k < kHB; ++k) a[k] = load(k);
+  for (int t0 = 0; t0 < T; t0 += 2 * kHB) {
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) b[k] = load(t0 + kHB + k);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) step(t0 + k, a[k]);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) a[k] = load(t0 + 2 * kHB + k);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) step(t0 + kHB + k, b[k]);
+    ring_fence();
+  }
+}
+
+struct Pair2 {
+  double s, p;
+};
+
 // one Rayleigh-quotient iteration sequence for the eigenvector of lane pair c;
 // role 0 = top-down / upward lane, role 1 = bottom-up / downward lane.  Work
 // vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = L+_i then z above the
@@ -1158,38 +1213,31 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       x = -lam;
     }
     {
-      Rep ring[kPF];
-#pragma unroll
-      for (int k = 0; k < kPF; ++k) ring[k] = R[clamp_row(role ? n - 2 - k : k, n)];
-      for (int t0 = 0; t0 < T; t0 += kPF) {
-#pragma unroll
-        for (int k = 0; k < kPF; ++k) {
-          const int t = t0 + k;
-          const Rep rr = ring[k];
-          if (t < T && go && t < n - 1) {
-            const int row = role ? n - 2 - t : t;
-            const double b = role ? rr.LLD : rr.D;
-            const double f = role ? rr.D : rr.LLD;
-            const double cz = role ? rr.D : rr.LD;
-            const double cq = role ? rr.L * rr.D : rr.LD;
-            double den = b + x;
-            den = (fabs(den) < pivmin) ? -pivmin : den;
-            const double rc = rcp_nr1(den);
-            const double xf = x * f;
-            const double q0 = xf * rc;
-            const double q = fma(rc, fma(-den, q0, xf), q0);
-            const double xn = (cz * rc == 0.0) ? f - lam : q - lam;
-            const double w0 = cq * rc;
-            const double w = fma(rc, fma(-den, w0, cq), w0);
-            const int64_t o = (int64_t)row * kPairSlots + c;
-            X[o] = role ? xn : x;
-            Wr[o] = w;
-            x = xn;
-          }
-          ring_fence();
-          ring[k] = R[clamp_row(role ? n - 2 - (t + kPF) : t + kPF, n)];
+      // rows in two buffers of kHB: one is consumed while the other's loads
+      // are in flight (prefetch distance kHB .. 2 kHB - 1 steps)
+      auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
+      auto step = [&](int t, const Row3& rr) {
+        if (t < T && go && t < n - 1) {
+          const int row = role ? n - 2 - t : t;
+          const double b = role ? rr.LLD : rr.D;
+          const double f = role ? rr.D : rr.LLD;
+          double den = b + x;
+          den = (fabs(den) < pivmin) ? -pivmin : den;
+          const double rc = rcp_nr1(den);
+          const double xf = x * f;
+          const double q0 = xf * rc;
+          const double q = fma(rc, fma(-den, q0, xf), q0);
+          const double xn = ((role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : q - lam;
+          // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
+          const double w0 = rr.LD * rc;
+          const double w = fma(rc, fma(-den, w0, rr.LD), w0);
+          const int64_t o = (int64_t)row * kPairSlots + c;
+          X[o] = role ? xn : x;
+          Wr[o] = w;
+          x = xn;
         }
-      }
+      };
+      pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
     }
     if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
     __syncthreads();  // S and P complete and visible to the partner lane
@@ -1202,31 +1250,24 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       const int kc = role ? n - h : h;
       int T2 = kc;
       for (int o = 32; o > 0; o >>= 1) T2 = max(T2, __shfl_xor(T2, o, 64));
-      double rs[kPF], rp[kPF];
-#pragma unroll
-      for (int k = 0; k < kPF; ++k) {
-        const int kk = clamp_row(kb + k, n);
-        rs[k] = S[(int64_t)kk * kPairSlots + c];
-        rp[k] = P[(int64_t)kk * kPairSlots + c];
-      }
-      for (int t0 = 0; t0 < T2; t0 += kPF) {
-#pragma unroll
-        for (int k = 0; k < kPF; ++k) {
-          const int t = t0 + k;
-          const double sv = rs[k], pv = rp[k];
-          if (t < T2 && go && t < kc) {
-            const double g = sv + pv + lam;
-            if (isfinite(g) && fabs(g) < fabs(gmin)) {
-              gmin = g;
-              r = kb + t;
+      pipelined(
+          T2,
+          [&](int t) {
+            const int64_t o = (int64_t)clamp_row(kb + t, n) * kPairSlots + c;
+            Pair2 v;
+            v.s = S[o];
+            v.p = P[o];
+            return v;
+          },
+          [&](int t, const Pair2& v) {
+            if (t < T2 && go && t < kc) {
+              const double g = v.s + v.p + lam;
+              if (isfinite(g) && fabs(g) < fabs(gmin)) {
+                gmin = g;
+                r = kb + t;
+              }
             }
-          }
-          const int kn = clamp_row(kb + t + kPF, n);
-          ring_fence();
-          rs[k] = S[(int64_t)kn * kPairSlots + c];
-          rp[k] = P[(int64_t)kn * kPairSlots + c];
-        }
-      }
+          });
       // the partner's candidate; ties go to the smaller index (the upper half)
       const double go_g = __shfl_xor(gmin, 1, 64);
       const int go_r = __shfl_xor(r, 1, 64);
@@ -1265,42 +1306,34 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       const int T3 = max(rmax, nb);
       const int base = role ? rmin : rmax - 1;
       const int dir = role ? 1 : -1;
-      double rw[kPF];
-#pragma unroll
-      for (int k = 0; k < kPF; ++k) rw[k] = Wr[(int64_t)clamp_row(base + dir * k, n) * kPairSlots + c];
       double zc = 1.0, zp = 0.0;
-      for (int t0 = 0; t0 < T3; t0 += kPF) {
-#pragma unroll
-        for (int k = 0; k < kPF; ++k) {
-          const int t = t0 + k;
-          const double w = rw[k];
-          const int row = base + dir * t;
-          const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
-          if (t < T3 && go && on) {
-            const bool first = role ? (row == r) : (row == r - 1);
-            double zn;
-            if (zc != 0.0 || first) {
-              zn = -w * zc;
-            } else if (zp != 0.0) {
-              const double ldi = R[row].LD;
-              const double ldn = R[row - dir].LD;
-              zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
-            } else {
-              zn = 0.0;  // an underflowed tail stays zero
+      pipelined(
+          T3, [&](int t) { return Wr[(int64_t)clamp_row(base + dir * t, n) * kPairSlots + c]; },
+          [&](int t, double w) {
+            const int row = base + dir * t;
+            const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
+            if (t < T3 && go && on) {
+              const bool first = role ? (row == r) : (row == r - 1);
+              double zn;
+              if (zc != 0.0 || first) {
+                zn = -w * zc;
+              } else if (zp != 0.0) {
+                const double ldi = R[row].LD;
+                const double ldn = R[row - dir].LD;
+                zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+              } else {
+                zn = 0.0;  // an underflowed tail stays zero
+              }
+              zn = isfinite(zn) ? zn : 0.0;
+              const int zrow = role ? row + 1 : row;
+              Wr[(int64_t)zrow * kPairSlots + c] = zn;
+              zp = zc;
+              zc = zn;
+              nrm += zn * zn;
+              // largest magnitude, ties to the smaller row
+              if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
             }
-            zn = isfinite(zn) ? zn : 0.0;
-            const int zrow = role ? row + 1 : row;
-            Wr[(int64_t)zrow * kPairSlots + c] = zn;
-            zp = zc;
-            zc = zn;
-            nrm += zn * zn;
-            // largest magnitude, ties to the smaller row
-            if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
-          }
-          ring_fence();
-          rw[k] = Wr[(int64_t)clamp_row(base + dir * (t + kPF), n) * kPairSlots + c];
-        }
-      }
+          });
       if (go && role) W1[(int64_t)r * kPairSlots + c] = 1.0;
       // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
       const double nrm_o = __shfl_xor(nrm, 1, 64);
