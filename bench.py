@@ -110,7 +110,10 @@ def batched_leg(torch, M, count, loop_count):
     d, e, ns, off = W.pack(probs)
     dt = torch.tensor(d, device="cuda")
     et = torch.tensor(e, device="cuda")
-    M.eigh_tridiagonal_batched(dt, et, ns)  # warm-up (workspace growth)
+    # launch shapes for this size mix (untimed: a coordinate search over about
+    # ten solves; the choice is cached for batches with the same size histogram)
+    tuning = M.autotune_batched(dt, et, ns)
+    M.eigh_tridiagonal_batched(dt, et, ns)  # warm-up
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
@@ -128,7 +131,7 @@ def batched_leg(torch, M, count, loop_count):
         M.eigh_tridiagonal(a, b)
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
-    return {"problems": count, "sum_n": int(ns.sum()), "seconds": tb, "solves_per_s": count / tb,
+    return {"problems": count, "sum_n": int(ns.sum()), "seconds": tb, "solves_per_s": count / tb, "tuning": tuning,
             "looped_problems": loop_count, "looped_solves_per_s": loop_count / tl,
             "speedup_vs_looped": (count / tb) / (loop_count / tl)}
 

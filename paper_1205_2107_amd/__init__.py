@@ -15,7 +15,7 @@ import ctypes
 from . import _lib
 from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 
-__all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "eigh_tridiagonal_backward",
+__all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
            "profile_read", "release"]
 
@@ -119,6 +119,36 @@ def eigh_tridiagonal_batched(d, e, sizes, eigvals_only=False, stream=None, retur
     if return_info:
         out = out + ([infos[b].as_dict() for b in range(B)],)
     return out
+
+
+def autotune_batched(d, e, sizes, stream=None):
+    """Pick launch shapes for batches shaped like this one (mrrr_autotune_batched):
+    a coordinate search timing about ten solves of the batch; the choice is cached
+    for later eigh_tridiagonal_batched calls with the same size histogram.
+    Returns the chosen tuning as a dict."""
+    torch = _torch()
+    lib = _lib.load()
+    d = _as_dev(d)
+    e = _as_dev(e, d.device)
+    sizes = [int(x) for x in sizes]
+    B = len(sizes)
+    n_arr = (ctypes.c_int64 * max(B, 1))(*sizes)
+    offs, zoffs = [0] * B, [0] * B
+    acc = zacc = 0
+    for b, nb in enumerate(sizes):
+        offs[b], zoffs[b] = acc, zacc
+        acc += nb
+        zacc += nb * nb
+    off_arr = (ctypes.c_int64 * max(B, 1))(*offs)
+    zoff_arr = (ctypes.c_int64 * max(B, 1))(*zoffs)
+    w = torch.empty(max(acc, 1), dtype=torch.float64, device=d.device)
+    Z = torch.empty(max(zacc, 1), dtype=torch.float64, device=d.device)
+    t = MrrrTuning()
+    rc = lib.mrrr_autotune_batched(B, n_arr, off_arr, _ptr(d), _ptr(e), _ptr(w), _ptr(Z), zoff_arr, ctypes.byref(t),
+                                   _stream_ptr(stream))
+    _lib.check(rc)
+    return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
+            "vec_wave_slots": t.vec_wave_slots}
 
 
 def _colmajor(X, n):

@@ -12,7 +12,7 @@ MRRR_ALL, MRRR_INDEX, MRRR_VALUE = 0, 1, 2
 COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singletons", "twisted",
                  "fallbacks", "child_reject", "workspace_mb", "wave_solves")
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
-           "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_profile_enable", "mrrr_profile_reset",
+           "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string")
 KERNELS = ("grid", "refine", "child", "vectors", "backward")
 
@@ -71,6 +71,8 @@ def load():
     lib.mrrr_step_backward.argtypes = [I64, P, P, I64, P, P, I64, P, P, P]
     lib.mrrr_step_backward_batched.restype = ctypes.c_int
     lib.mrrr_step_backward_batched.argtypes = [I64, PI64, PI64, PI64, P, P, P, P, P, P, P]
+    lib.mrrr_autotune_batched.restype = ctypes.c_int
+    lib.mrrr_autotune_batched.argtypes = [I64, PI64, PI64, P, P, P, P, PI64, ctypes.POINTER(MrrrTuning), P]
     lib.mrrr_get_tuning.restype = ctypes.c_int
     lib.mrrr_get_tuning.argtypes = [ctypes.POINTER(MrrrTuning)]
     lib.mrrr_set_tuning.restype = ctypes.c_int

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -146,10 +147,12 @@ struct Report {
 
 // Solve a list of problems (packed into slot space) on one stream.
 static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, const double* e, double* w, double* Z,
-                 hipStream_t st, Report* rep) {
+                 hipStream_t st, Report* rep, const mrrr_tuning* use = nullptr) {
   const int nprob = (int)probs.size();
   mrrr_tuning tune;
-  {
+  if (use) {
+    tune = *use;
+  } else {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune = g_tune;
   }
@@ -543,6 +546,38 @@ int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, dou
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// tuning cache of the batched form, keyed by the batch's size histogram
+// (problem counts per power-of-two size class, each count rounded to a power
+// of two)
+
+static std::mutex g_cache_mu;
+static std::map<uint64_t, mrrr_tuning> g_cache;
+
+static uint64_t size_key(int64_t batch, const int64_t* n_host) {
+  int64_t hist[64] = {0};
+  for (int64_t b = 0; b < batch; ++b) {
+    int c = 0;
+    for (int64_t v = n_host[b]; v > 1; v >>= 1) ++c;
+    hist[c]++;
+  }
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  for (int c = 0; c < 64; ++c) {
+    int q = 0;
+    for (int64_t v = hist[c]; v > 0; v >>= 1) ++q;
+    h = (h ^ (uint64_t)(c * 64 + q)) * 1099511628211ull;
+  }
+  return h;
+}
+
+static bool cache_lookup(uint64_t key, mrrr_tuning* t) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(key);
+  if (it == g_cache.end()) return false;
+  *t = it->second;
+  return true;
+}
+
 int mrrr_step_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host, const double* d,
                       const double* e, double* w, double* Z, const int64_t* zoff_host, mrrr_info* info,
                       void* stream) {
@@ -576,7 +611,9 @@ int mrrr_step_batched(int64_t batch, const int64_t* n_host, const int64_t* off_h
     p.kind = MRRR_ALL;
   }
   Report r;
-  int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r);
+  mrrr_tuning cached;
+  const bool have = cache_lookup(size_key(batch, n_host), &cached);
+  int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r, have ? &cached : nullptr);
   if (rc != 0) return rc;
   int st = 0;
   for (int64_t b = 0; b < batch; ++b) {
@@ -586,6 +623,86 @@ int mrrr_step_batched(int64_t batch, const int64_t* n_host, const int64_t* off_h
   if (!st) st = r.c.status;
   if (st) fail(st, "%s", mrrr_status_string(st));
   return st;
+}
+
+// coordinate search over the launch shapes: eigenvectors per wavefront,
+// eigenvalues per refinement wavefront, count-grid density; each candidate is
+// timed (host clock around a whole synchronised solve) on the caller's batch
+int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host, const double* d,
+                          const double* e, double* w, double* Z, const int64_t* zoff_host, mrrr_tuning* best,
+                          void* stream) {
+  if (batch < 1) return fail(-1, "batch < 1");
+  if (!n_host) return fail(-2, "n_host is NULL");
+  if (!off_host) return fail(-3, "off_host is NULL");
+  if (!d) return fail(-4, "d is NULL");
+  if (!e) return fail(-5, "e is NULL");
+  if (!w) return fail(-6, "w is NULL");
+  if (Z && !zoff_host) return fail(-8, "zoff_host is NULL");
+  int64_t tot = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    if (n_host[b] < 1 || n_host[b] > INT32_MAX / 8) return fail(-2, "n_host[%lld] out of range", (long long)b);
+    if (off_host[b] < 0) return fail(-3, "off_host[%lld] < 0", (long long)b);
+    tot += n_host[b];
+  }
+  if (tot > INT32_MAX / 2) return fail(-2, "total order too large");
+  int dev = 0;
+  Workspace* W = workspace_for_current_device(&dev);
+  if (!W) return fail(MRRR_ERR_NO_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(W->mu);
+  std::vector<Problem> tmpl(batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    Problem& p = tmpl[b];
+    memset(&p, 0, sizeof(p));
+    p.off = off_host[b];
+    p.n = n_host[b];
+    p.zoff = Z ? zoff_host[b] : 0;
+    p.ldz = n_host[b];
+    p.kind = MRRR_ALL;
+  }
+  auto run = [&](const mrrr_tuning& t, double* ms) -> int {
+    std::vector<Problem> probs = tmpl;
+    Report r;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r, &t);
+    const auto t1 = std::chrono::steady_clock::now();
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return rc;
+  };
+  mrrr_tuning cur;
+  {
+    std::lock_guard<std::mutex> lk2(g_tune_mu);
+    cur = g_tune;
+  }
+  if (cur.refine_wave_slots == 0) cur.refine_wave_slots = (tot <= 32768) ? 16 : (tot <= 131072 ? 32 : 64);
+  if (cur.vec_wave_slots == 0) cur.vec_wave_slots = 32;
+  double best_ms = 0.0;
+  int rc = run(cur, &best_ms);  // grows the workspace
+  if (rc != 0) return rc;
+  if ((rc = run(cur, &best_ms)) != 0) return rc;
+  const int vec_c[] = {32, 16, 8};
+  const int ref_c[] = {16, 32, 64};
+  const int grid_c[] = {2, 4, 8};
+  for (int param = 0; param < 3; ++param) {
+    const int* cand = param == 0 ? vec_c : (param == 1 ? ref_c : grid_c);
+    for (int k = 0; k < 3; ++k) {
+      mrrr_tuning t = cur;
+      int* field = param == 0 ? &t.vec_wave_slots : (param == 1 ? &t.refine_wave_slots : &t.grid_density);
+      if (*field == cand[k]) continue;
+      *field = cand[k];
+      double ms = 0.0;
+      if ((rc = run(t, &ms)) != 0) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        cur = t;
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk3(g_cache_mu);
+    g_cache[size_key(batch, n_host)] = cur;
+  }
+  if (best) *best = cur;
+  return 0;
 }
 
 int mrrr_get_tuning(mrrr_tuning* t) {

@@ -1012,8 +1012,9 @@ __global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N,
     }
     // the child's eigenvalue is the parent's minus sigma up to the effect of the
     // relative perturbations of the mixed stable transform (at most O(n eps)
-    // relative to the parent's eigenvalue): a generous pad, validated by counts
-    // only when the bracket is refined
+    // relative to the parent's eigenvalue): a generous pad.  Classification
+    // refines (validates by counts) every pair whose decision the pads could
+    // flip, so the unrefined brackets only decide clear cases.
     const double l0 = lo[s], h0 = hi[s];
     const double pad = 4.0 * (double)blk.n * kEps * (fabs(l0) + fabs(h0)) + 4.0 * kEps * fabs(nd.sigma);
     lo[s] = (l0 - nd.sigma) - pad;

@@ -276,6 +276,25 @@ def test_full_size_n20000(M, kind):
         assert np.abs(wn - lam).max() <= tol
 
 
+@pytest.mark.parametrize("kind", ["toeplitz", "geometric", "glued", "random"])
+def test_mid_size_n8000(M, kind):
+    # between the oracle-sized cases and the full size: trees of several levels
+    n = 8000
+    d, e = {"toeplitz": lambda: W.toeplitz(n), "geometric": lambda: W.geometric(n, 2103),
+            "glued": lambda: W.glued_wilkinson(n, 3101), "random": lambda: W.random_uniform(n, 2101)}[kind]()
+    w, Z, info = M.eigh_tridiagonal(torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda"),
+                                    return_info=True)
+    assert info["status"] == 0
+    r, o = gpu_metrics(d, e, w, Z)
+    assert r <= 10.0 and o <= 10.0
+    wn = w.cpu().numpy()
+    assert np.all(np.diff(wn) >= 0)
+    tol = eig_tol(d, e)
+    for j in np.unique(np.r_[1, n // 2, n, np.random.default_rng(1).integers(1, n + 1, 6)]):
+        lo, hi = oracle.bisect_T(d, e, int(j))
+        assert lo - tol <= wn[j - 1] <= hi + tol
+
+
 def test_full_size_c3_glued_subset(M):
     n = 60000
     d, e = W.glued_wilkinson(n, W.SEEDS["c3"])
@@ -328,6 +347,43 @@ def test_batched_c4_shape(M):
                                                       torch.tensor(e, device="cuda"), ns, return_info=True)
     wbn = wb.cpu().numpy()
     for b in range(0, 256, 37):
+        nb = int(ns[b])
+        p = probs[b]
+        Z = Zb[zoff[b]:zoff[b] + nb * nb].reshape(nb, nb).t()
+        r, o = gpu_metrics(p[0], p[1], wb[off[b]:off[b] + nb], Z)
+        assert r <= 10 and o <= 10
+        wo, Zo, st = oracle.mrrr(p[0], p[1])
+        assert np.abs(wbn[off[b]:off[b] + nb] - wo).max() <= eig_tol(p[0], p[1])
+
+
+def test_vector_wave_slots_do_not_change_results(M):
+    # each eigenvector's arithmetic is independent of how many share a wavefront
+    d, e = W.random_uniform(3000, 77)
+    old = M.get_tuning()
+    outs = []
+    try:
+        for slots in (32, 16, 8):
+            M.set_tuning(vec_wave_slots=slots)
+            w, Z, _ = gpu_solve(M, d, e)
+            outs.append((w, Z))
+    finally:
+        M.set_tuning(**old)
+    for w, Z in outs[1:]:
+        assert np.array_equal(w, outs[0][0]) and np.array_equal(Z, outs[0][1])
+
+
+def test_autotune_batched(M):
+    probs = batched_problems(64, 4202, nmax=600)
+    d, e, ns, off = W.pack(probs)
+    dt, et = torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda")
+    t = M.autotune_batched(dt, et, ns)
+    assert t["vec_wave_slots"] in (8, 16, 32)
+    assert t["refine_wave_slots"] in (16, 32, 64)
+    assert t["grid_density"] in (2, 4, 8)
+    # later batches of the same shape use the cached choice; results still meet the bar
+    wb, Zb, zoff = M.eigh_tridiagonal_batched(dt, et, ns)
+    wbn = wb.cpu().numpy()
+    for b in range(0, len(probs), 9):
         nb = int(ns[b])
         p = probs[b]
         Z = Zb[zoff[b]:zoff[b] + nb * nb].reshape(nb, nb).t()
