@@ -467,21 +467,24 @@ __device__ inline double next_point(const EigState& S, int k) {
   return S.lo + (S.hi - S.lo) * ((double)(k + 1) / (double)(L + 1));
 }
 
+// a count only moves a validated end inward, and never past the other
+// validated end: counts from rounded arithmetic need not be monotone in the
+// shift, and a bracket must not invert
 template <int L>
-__device__ inline void update_state(EigState& S, const double* p, const int* c, const double* g) {
+__device__ inline void update_state(EigState& S, const double* p, const int* c, const double* g, bool vonly) {
   double pmin = INFINITY, pmax = -INFINITY;
   for (int q = 0; q < L; ++q) {
     pmin = fmin(pmin, p[q]);
     pmax = fmax(pmax, p[q]);
     if (c[q] <= S.j - 1) {
-      if (S.clo < 0 || p[q] > S.lo) { S.lo = p[q]; S.clo = c[q]; S.glo = g[q]; }
+      if ((S.clo < 0 || p[q] > S.lo) && (S.chi < 0 || p[q] < S.hi)) { S.lo = p[q]; S.clo = c[q]; S.glo = g[q]; }
     } else {
-      if (S.chi < 0 || p[q] < S.hi) { S.hi = p[q]; S.chi = c[q]; S.ghi = g[q]; }
+      if ((S.chi < 0 || p[q] < S.hi) && (S.clo < 0 || p[q] > S.lo)) { S.hi = p[q]; S.chi = c[q]; S.ghi = g[q]; }
     }
   }
-  if (S.clo < 0) { S.lo = pmin - S.pad; S.pad *= 4.0; }
-  if (S.chi < 0) { S.hi = pmax + S.pad; S.pad *= 4.0; }
-  S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
+  if (S.clo < 0) { S.lo = fmin(pmin, S.hi) - S.pad; S.pad *= 4.0; }
+  if (S.chi < 0) { S.hi = fmax(pmax, S.lo) + S.pad; S.pad *= 4.0; }
+  S.done = (S.clo >= 0 && S.chi >= 0 && (vonly || bracket_converged(S.lo, S.hi))) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -526,9 +529,10 @@ __device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, d
                                          double* __restrict__ st, double* g_out) {
   double s = -tau, ds = -1.0, g = 0.0;
   int c = 0;
+  // no zero-pivot guard in this pass: a zero or tiny pivot ends in a
+  // non-finite s, answered by the guarded recount below
   staged_rows(Rd, n, st, [&](int, double D, double, double, double LLD) {
-    double dp = D + s;
-    dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+    const double dp = D + s;
     c += (dp < 0.0) ? 1 : 0;
     const double inv = rcp_nr1(dp);
     const double dsi = ds * inv;
@@ -537,7 +541,7 @@ __device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, d
     ds = fma(LLD * D, dsi * inv, -1.0);
     s = fma(s * inv, LLD, -tau);
   });
-  if (!(s == s)) {
+  if (!isfinite(s) || !isfinite(g)) {
     c = sturm_count(reinterpret_cast<const Rep*>(Rd), n, tau, pivmin);
     g = NAN;
   }
@@ -547,7 +551,7 @@ __device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, d
 
 template <int L>
 __device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __restrict__ R, int n, double pivmin,
-                                          int k, int gbase, double* __restrict__ st) {
+                                          int k, int gbase, double* __restrict__ st, bool vonly) {
   long long steps = 0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     const bool need = act && !S.done;
@@ -565,7 +569,7 @@ __device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __re
       cq[q] = __shfl(c, gbase + q, 64);
       gq[q] = __shfl(gv, gbase + q, 64);
     }
-    if (need) update_state<L>(S, pq, cq, gq);
+    if (need) update_state<L>(S, pq, cq, gq, vonly);
   }
   return steps;
 }
@@ -576,7 +580,7 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
                                                const int32_t* __restrict__ snode, const Rep* __restrict__ pool,
                                                double* __restrict__ lo_a, double* __restrict__ hi_a,
                                                int32_t* __restrict__ clo_a, int32_t* __restrict__ chi_a,
-                                               uint32_t* __restrict__ sflag, Counters* __restrict__ C) {
+                                               uint32_t* __restrict__ sflag, Counters* __restrict__ C, int vonly) {
   const int lane = threadIdx.x;
   const int k = lane % L, gbase = lane - k;
   const int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L;
@@ -596,16 +600,16 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
   S.ghi = NAN;
   S.j = (int)(ss - blk.row0) + 1;
   S.pad = fmax(fmax(S.hi - S.lo, 4.0 * kEps * fmax(fabs(S.lo), fabs(S.hi))), blk.pivmin);
-  S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
+  S.done = (S.clo >= 0 && S.chi >= 0 && (vonly || bracket_converged(S.lo, S.hi))) ? 1 : 0;
   const int64_t rep0 = __shfl(nd.rep, first_lane(am), 64);
   long long steps;
   if (__ballot(nd.rep != rep0) == 0) {
     __shared__ double st[2 * 4 * kSG];
     // per-lane copy of the (equal) pointer keeps the staged loads global
     steps = refine_sweeps<L>(S, act, pool + nd.rep, __builtin_amdgcn_readfirstlane(blk.n), blk.pivmin, k, gbase,
-                             st);
+                             st, vonly != 0);
   } else {
-    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase, nullptr);
+    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase, nullptr, vonly != 0);
   }
   if (act && k == 0) {
     lo_a[s] = S.lo;
@@ -613,7 +617,7 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
     clo_a[s] = S.clo;
     chi_a[s] = S.chi;
     uint32_t fl = sflag[s] & ~F_NEEDS_REFINE;
-    if (S.done) fl |= F_ACCURATE;
+    if (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) fl |= F_ACCURATE;
     sflag[s] = fl;
   }
   // each lane evaluated its own points: count all of them
@@ -1014,7 +1018,9 @@ __global__ void k_shift(const Block* __restrict__ B, const Node* __restrict__ N,
     // relative perturbations of the mixed stable transform (at most O(n eps)
     // relative to the parent's eigenvalue): a generous pad.  Classification
     // refines (validates by counts) every pair whose decision the pads could
-    // flip, so the unrefined brackets only decide clear cases.
+    // flip, so the unrefined brackets only decide clear cases -- and pairs
+    // near the gap threshold stay together, which keeps borderline
+    // eigenvalues off poorly conditioned representations.
     const double l0 = lo[s], h0 = hi[s];
     const double pad = 4.0 * (double)blk.n * kEps * (fabs(l0) + fabs(h0)) + 4.0 * kEps * fabs(nd.sigma);
     lo[s] = (l0 - nd.sigma) - pad;
@@ -1216,29 +1222,39 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     {
       // rows in two buffers of kHB: one is consumed while the other's loads
       // are in flight (prefetch distance kHB .. 2 kHB - 1 steps)
+      // Without a zero or overflowing pivot (the usual case) the guard and
+      // the special-case rule are no-ops, so the first pass runs without them
+      // (three dependent operations fewer per row); a lane that ends with a
+      // non-finite value makes the wavefront repeat the pass with both.
       auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
-      auto step = [&](int t, const Row3& rr) {
-        if (t < T && go && t < n - 1) {
-          const int row = role ? n - 2 - t : t;
-          const double b = role ? rr.LLD : rr.D;
-          const double f = role ? rr.D : rr.LLD;
-          double den = b + x;
-          den = (fabs(den) < pivmin) ? -pivmin : den;
-          const double rc = rcp_nr1(den);
-          const double xf = x * f;
-          const double q0 = xf * rc;
-          const double q = fma(rc, fma(-den, q0, xf), q0);
-          const double xn = ((role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : q - lam;
-          // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
-          const double w0 = rr.LD * rc;
-          const double w = fma(rc, fma(-den, w0, rr.LD), w0);
-          const int64_t o = (int64_t)row * kPairSlots + c;
-          X[o] = role ? xn : x;
-          Wr[o] = w;
-          x = xn;
-        }
-      };
-      pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
+      const double x0 = x;
+      for (int guarded = 0; guarded < 2; ++guarded) {
+        x = x0;
+        auto step = [&](int t, const Row3& rr) {
+          if (t < T && go && t < n - 1) {
+            const int row = role ? n - 2 - t : t;
+            const double b = role ? rr.LLD : rr.D;
+            const double f = role ? rr.D : rr.LLD;
+            double den = b + x;
+            if (guarded) den = (fabs(den) < pivmin) ? -pivmin : den;
+            const double rc = rcp_nr1(den);
+            const double xf = x * f;
+            const double q0 = xf * rc;
+            const double q = fma(rc, fma(-den, q0, xf), q0);
+            double xn = q - lam;
+            if (guarded) xn = ((role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : xn;
+            // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
+            const double w0 = rr.LD * rc;
+            const double w = fma(rc, fma(-den, w0, rr.LD), w0);
+            const int64_t o = (int64_t)row * kPairSlots + c;
+            X[o] = role ? xn : x;
+            Wr[o] = w;
+            x = xn;
+          }
+        };
+        pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
+        if (__ballot(go && !isfinite(x)) == 0) break;
+      }
     }
     if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
     __syncthreads();  // S and P complete and visible to the partner lane
@@ -1634,16 +1650,20 @@ void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t 
 
 void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
                    const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
-                   uint32_t* sflag, Counters* C, int lanes) {
+                   uint32_t* sflag, Counters* C, int lanes, bool validate_only) {
   // `lanes` lanes per eigenvalue: 64 / lanes eigenvalues per wavefront
   const unsigned g4 = (unsigned)((ntot + 15) / 16), g2 = (unsigned)((ntot + 31) / 32),
                  g1 = (unsigned)((ntot + 63) / 64);
+  const int v = validate_only ? 1 : 0;
   if (lanes >= 4)
-    hipLaunchKernelGGL(k_refine<4>, dim3(g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+    hipLaunchKernelGGL(k_refine<4>, dim3(g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
+                       v);
   else if (lanes == 2)
-    hipLaunchKernelGGL(k_refine<2>, dim3(g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+    hipLaunchKernelGGL(k_refine<2>, dim3(g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
+                       v);
   else
-    hipLaunchKernelGGL(k_refine<1>, dim3(g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C);
+    hipLaunchKernelGGL(k_refine<1>, dim3(g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
+                       v);
 }
 
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag) {

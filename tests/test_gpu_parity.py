@@ -312,6 +312,29 @@ def test_full_size_c3_glued_subset(M):
         assert lo - tol <= wn[j - il] <= hi + tol
 
 
+def test_full_size_c3_glued_full_spectrum(M):
+    # 2858 glued W21+ blocks, every eigenpair (Z is 28.8 GB)
+    n = 60000
+    d, e = W.glued_wilkinson(n, W.SEEDS["c3"])
+    dt = torch.tensor(d, device="cuda")
+    et = torch.tensor(e, device="cuda")
+    try:
+        w, Z, info = M.eigh_tridiagonal(dt, et, return_info=True)
+        assert info["status"] == 0 and w.numel() == n
+        r, o = gpu_metrics(d, e, w, Z)
+        assert r <= 10.0 and o <= 10.0
+        wn = w.cpu().numpy()
+        assert np.all(np.diff(wn) >= 0)
+        tol = eig_tol(d, e)
+        for j in [1, 2, n // 3, n // 2, 2 * n // 3, n - 1, n]:
+            lo, hi = oracle.bisect_T(d, e, j)
+            assert lo - tol <= wn[j - 1] <= hi + tol
+    finally:
+        del dt, et
+        torch.cuda.empty_cache()
+        M.release()
+
+
 # ----------------------------------------------------------------------------
 # batched form
 
