@@ -23,6 +23,7 @@ constexpr double kGrowthBound = 8.0;   // child accepted outright if max|D_c| <=
 constexpr double kPertScale = 4.0;     // root perturbation 4 eps u, u in [-1, 1)
 constexpr int kMaxRqi = 5;              // Rayleigh-quotient solves per singleton (one more to repeat the best)
 constexpr int kMaxSweeps = 200;        // refinement sweeps per eigenvalue (cap)
+constexpr int kSeg = 8;                 // eigenvector solves: rows per recomputed segment
 
 // slot flags
 constexpr uint32_t F_NEEDS_REFINE = 1u;   // bracket must be (re)validated/refined

@@ -353,7 +353,8 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                   dC, lanes);
     prof.end();
     // 8. eigenvectors of all singletons (eigenvectors per wavefront: tuning,
-    //    32 by default; four work vectors of rows x slots doubles per wavefront)
+    //    32 by default; two checkpoint arrays of ceil(rows / kSeg) x slots
+    //    doubles per wavefront)
     int vslots = tune.vec_wave_slots;
     if (vslots == 0) vslots = 32;
     const int64_t nch = (ntot + vslots - 1) / vslots;
@@ -369,7 +370,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     for (int64_t c = 0; c < nch; ++c)
       if (rows[c] > 0) {
         act.push_back((int32_t)c);
-        maxper = std::max<int64_t>(maxper, 4 * vslots * (int64_t)rows[c]);
+        maxper = std::max<int64_t>(maxper, 2 * vslots * (int64_t)((rows[c] + kSeg - 1) / kSeg));
       }
     const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
     ENS(chunks, sizeof(int32_t) * (act.size() + 1));
@@ -381,7 +382,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       int64_t used = 0;
       aoff.clear();
       while (i1 < act.size()) {
-        const int64_t need = 4 * vslots * (int64_t)rows[act[i1]];
+        const int64_t need = 2 * vslots * (int64_t)((rows[act[i1]] + kSeg - 1) / kSeg);
         if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
         aoff.push_back(used);
         used += need;

@@ -497,8 +497,12 @@ __device__ inline void update_state(EigState& S, const double* p, const int* c, 
 
 constexpr int kSG = 64;
 
-template <class Body>
-__device__ inline void staged_rows(const double* __restrict__ Rd, int n, double* __restrict__ st, Body&& body) {
+// as staged_rows, for the first nrow <= n rows, with group(g0) called at the
+// start of every group (before its rows) and body(i, j, D, L, LD, LLD) given
+// the row's position j = i - g0 inside its group
+template <class Group, class Body>
+__device__ inline void staged_rows_g(const double* __restrict__ Rd, int n, int nrow, double* __restrict__ st,
+                                     Group&& group, Body&& body) {
   const int lane = threadIdx.x & 63;
   const int64_t n4 = 4 * (int64_t)n;
   double q[4];
@@ -507,7 +511,7 @@ __device__ inline void staged_rows(const double* __restrict__ Rd, int n, double*
     const int64_t idx = lane + 64 * k;
     q[k] = (idx < n4) ? Rd[idx] : 0.0;
   }
-  for (int g0 = 0; g0 < n; g0 += kSG) {
+  for (int g0 = 0; g0 < nrow; g0 += kSG) {
     double* buf = st + ((g0 / kSG) & 1) * (4 * kSG);
 #pragma unroll
     for (int k = 0; k < 4; ++k) buf[lane + 64 * k] = q[k];
@@ -517,10 +521,44 @@ __device__ inline void staged_rows(const double* __restrict__ Rd, int n, double*
       const int64_t idx = (int64_t)(g0 + kSG) * 4 + lane + 64 * k;
       q[k] = (idx < n4) ? Rd[idx] : 0.0;
     }
-    const int m = min(kSG, n - g0);
+    group(g0);
+    const int m = min(kSG, nrow - g0);
 #pragma unroll 8
-    for (int j = 0; j < m; ++j) body(g0 + j, buf[4 * j], buf[4 * j + 1], buf[4 * j + 2], buf[4 * j + 3]);
+    for (int j = 0; j < m; ++j) body(g0 + j, j, buf[4 * j], buf[4 * j + 1], buf[4 * j + 2], buf[4 * j + 3]);
   }
+}
+
+template <class Body>
+__device__ inline void staged_rows(const double* __restrict__ Rd, int n, double* __restrict__ st, Body&& body) {
+  staged_rows_g(Rd, n, n, st, [](int) {},
+                [&](int i, int, double D, double L, double LD, double LLD) { body(i, D, L, LD, LLD); });
+}
+
+// Raw buffer resource over bytes [p, p + bytes): a buffer store whose offset
+// lies at or beyond `bytes` is discarded by the hardware range check, so a
+// wavefront can store from a few lanes without branching around the store.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kDropOff = 0x80000000u;  // beyond every resource used here
+
+// a value equal in every lane, made visibly wave-uniform (scalar registers)
+__device__ __forceinline__ long long uniform_ll(long long x) {
+  const unsigned long long u = (unsigned long long)x;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t off, double a, double b) {
+  const u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
+  const u32x4 v = {ua.x, ua.y, ub.x, ub.y};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t off, double a) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, a), r, (int)off, 0, 0);
 }
 
 // Sturm count plus log-derivative (as sturm_count_deriv) for a wavefront
@@ -889,39 +927,52 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
       base = -1;
     }
   }
-  base = __shfl(base, 0, 64);
+  base = uniform_ll(__shfl(base, 0, 64));
   bool valid = false;
   double sigma = 0.0;
   if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
-  const bool spec = base >= 0 && lane < 2;
-  double* Qs = reinterpret_cast<double*>(pool + (base >= 0 ? base : 0) + (lane & 1) * (int64_t)n);
-  // pass 1: growth of every candidate
+  // the two speculative regions, stored through buffer resources rebased at
+  // every group (each row's store lands in the owning lane's region only)
+  char* const reg0 = reinterpret_cast<char*>(pool + (base >= 0 ? base : 0));
+  char* const reg1 = reg0 + (int64_t)n * sizeof(Rep);
+  const bool own0 = base >= 0 && lane == 0, own1 = base >= 0 && lane == 1;
+  // pass 1: growth of every candidate (rows 0 .. n-2; the last row has no L)
   double sv = -sigma, gmax = 0.0;
   bool fin = true;
-  staged_rows(Rd, n, st, [&](int i, double D, double L, double LD, double) {
-    const double dp = D + sv;
+  __amdgpu_buffer_rsrc_t r0 = raw_rsrc(reg0, 0), r1 = raw_rsrc(reg1, 0);
+  staged_rows_g(
+      Rd, n, n - 1, st,
+      [&](int g0) {
+        r0 = raw_rsrc(reg0 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
+        r1 = raw_rsrc(reg1 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
+      },
+      [&](int, int j, double D, double L, double LD, double) {
+        const double dp = D + sv;
+        gmax = fmax(gmax, fabs(dp));
+        const double lp = LD * rcp_nr2(dp);
+        const double ld = lp * dp;
+        const double lld = ld * lp;
+        const uint32_t o0 = own0 ? (uint32_t)j * sizeof(Rep) : kDropOff;
+        const uint32_t o1 = own1 ? (uint32_t)j * sizeof(Rep) : kDropOff;
+        bstore2(r0, o0, dp, lp);
+        bstore2(r0, o0 + 16, ld, lld);
+        bstore2(r1, o1, dp, lp);
+        bstore2(r1, o1 + 16, ld, lld);
+        sv = fma(lp * L, sv, -sigma);
+        fin = fin && isfinite(dp) && isfinite(lp);
+      });
+  {
+    const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
     gmax = fmax(gmax, fabs(dp));
-    if (i == n - 1) {
-      fin = fin && isfinite(dp);
-      if (spec) {
-        Qs[(int64_t)i * 4] = dp;
-        Qs[(int64_t)i * 4 + 1] = 0.0;
-        Qs[(int64_t)i * 4 + 2] = 0.0;
-        Qs[(int64_t)i * 4 + 3] = 0.0;
-      }
-      return;
+    fin = fin && isfinite(dp);
+    if (own0 || own1) {
+      double* q = reinterpret_cast<double*>(own0 ? reg0 : reg1) + 4 * (int64_t)(n - 1);
+      q[0] = dp;
+      q[1] = 0.0;
+      q[2] = 0.0;
+      q[3] = 0.0;
     }
-    const double lp = LD * rcp_nr2(dp);
-    if (spec) {
-      const double ld = lp * dp;
-      Qs[(int64_t)i * 4] = dp;
-      Qs[(int64_t)i * 4 + 1] = lp;
-      Qs[(int64_t)i * 4 + 2] = ld;
-      Qs[(int64_t)i * 4 + 3] = ld * lp;
-    }
-    sv = fma(lp * L, sv, -sigma);
-    fin = fin && isfinite(dp) && isfinite(lp);
-  });
+  }
   const double growth = (valid && fin) ? gmax : INFINITY;
   double gr[kChildCand];
 #pragma unroll
@@ -942,7 +993,7 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
         pick = k;
       }
   }
-  const long long off = (pick < 0 || base < 0) ? -1 : base + (pick < 2 ? pick : 0) * (long long)n;
+  const long long off = uniform_ll((pick < 0 || base < 0) ? -1 : base + (pick < 2 ? pick : 0) * (long long)n);
   bool v;
   const double sg = (pick >= 0) ? child_sigma(cl, blk, lo, hi, pick, &v) : 0.0;
   if (lane == 0) {
@@ -977,20 +1028,24 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   if (off < 0 || pick < 2) return;
   // pass 2 (a farther candidate won): every lane repeats its transform (the
   // staging needs the whole wavefront); lanes 0..3 store field q of each row
-  double* Q = reinterpret_cast<double*>(pool + off);
+  char* const Q = reinterpret_cast<char*>(pool + off);
   sv = -sg;
-  staged_rows(Rd, n, st, [&](int i, double D, double L, double LD, double) {
-    const double dp = D + sv;
-    if (i == n - 1) {
-      if (lane < 4) Q[(int64_t)i * 4 + lane] = (lane == 0) ? dp : 0.0;
-      return;
-    }
-    const double lp = LD * rcp_nr2(dp);
-    const double ld = lp * dp;
-    const double val = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
-    if (lane < 4) Q[(int64_t)i * 4 + lane] = val;
-    sv = fma(lp * L, sv, -sg);
-  });
+  __amdgpu_buffer_rsrc_t rq = raw_rsrc(Q, 0);
+  staged_rows_g(
+      Rd, n, n - 1, st,
+      [&](int g0) { rq = raw_rsrc(Q + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep)); },
+      [&](int, int j, double D, double L, double LD, double) {
+        const double dp = D + sv;
+        const double lp = LD * rcp_nr2(dp);
+        const double ld = lp * dp;
+        const double val = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
+        bstore1(rq, lane < 4 ? (uint32_t)(j * 4 + lane) * 8u : kDropOff, val);
+        sv = fma(lp * L, sv, -sg);
+      });
+  if (lane < 4) {
+    const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
+    reinterpret_cast<double*>(Q)[4 * (int64_t)(n - 1) + lane] = (lane == 0) ? dp : 0.0;
+  }
 }
 
 // move the cluster's brackets into the child's frame (or, without a child,
@@ -1043,23 +1098,23 @@ __global__ void k_clear_active(int64_t ntot, uint32_t* __restrict__ sflag) {
 //    factorization of L D L^T - lam I, one solve per Rayleigh-quotient step.
 //    Two lanes serve one eigenvector, up to 32 consecutive slots per wavefront:
 //      lane 2c     top-down stationary transform
-//                  s_1 = -lam,  s_{i+1} = s_i LLD_i / (D_i + s_i) - lam        (s_i -> S)
+//                  s_1 = -lam,  s_{i+1} = s_i LLD_i / (D_i + s_i) - lam
 //      lane 2c+1   bottom-up progressive transform
-//                  p_n = D_n - lam,  p_i = p_{i+1} D_i / (LLD_i + p_{i+1}) - lam  (p_i -> P)
-//    run concurrently: both are x' = x f / (b + x) - lam with (b, f) chosen by
-//    the lane's role; each step also stores the quotient the solve needs,
-//    L+_i = LD_i / (D_i + s_i) or U-_i = L_i D_i / (LLD_i + p_{i+1}).  Then
-//      twist   gamma_k = s_k + p_k + lam, r = argmin |gamma_k| (ties: smallest k),
-//              each lane scanning one half of k
-//      solve   z_r = 1; lane 2c walks up, z_i = -L+_i z_{i+1}; lane 2c+1 walks
-//              down, z_{i+1} = -U-_i z_i (the dependency chain of a step is one
-//              multiply)
+//                  p_n = D_n - lam,  p_i = p_{i+1} D_i / (LLD_i + p_{i+1}) - lam
+//    Both are x' = x f / (b + x) - lam with (b, f) chosen by the lane's role;
+//    a step also gives the quotient the solve needs, L+_i = LD_i / (D_i + s_i)
+//    or U-_i = L_i D_i / (LLD_i + p_{i+1}).  Then
+//      twist   gamma_k = s_k + p_k + lam, r = argmin |gamma_k| (ties: smallest k)
+//      solve   z_r = 1; z_i = -L+_i z_{i+1} above the twist (lane 2c),
+//              z_{i+1} = -U-_i z_i below it (lane 2c+1)
 //      then    lam <- lam + gamma_r / ||z||^2 until the stopping rule holds.
-//    Work vectors per wavefront: S, P, W0 (L+, then z above the twist), W1 (U-,
-//    then z from the twist down), each [row][slots].  Every loop is software
-//    pipelined (pipelined()): loads run kHB .. 2 kHB - 1 steps ahead of use.
-
-constexpr int kZRows = 32;      // rows per LDS transpose tile
+//    Nothing of length n is stored per eigenvector: the transforms keep their
+//    variable at the first row of every segment of kSeg rows (checkpoints), and
+//    the twist search and the solve recompute one segment at a time from its
+//    checkpoint, in registers, with the same operations and therefore the same
+//    values.  After the last solve the vector is recomputed once more and
+//    written to Z already normalized.  A solve reads the representation about
+//    three times per lane and writes 2 n / kSeg doubles per lane pair.
 
 // angle accepted for a singleton's vector: eps * max(n / 8, 4 log2 n), a
 // small fraction of the O(n eps) orthogonality the method guarantees
@@ -1131,20 +1186,6 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   }
 }
 
-// t / den to about one ulp: reciprocal with one Newton step, then one
-// Newton correction of the quotient
-__device__ __forceinline__ double quot(double t, double den) {
-  const double r = rcp_nr1(den);
-  const double q0 = t * r;
-  const double res = fma(-den, q0, t);
-  return fma(r, res, q0);
-}
-
-__device__ __forceinline__ int clamp_row(int i, int n) { return min(max(i, 0), n - 1); }
-
-// compiler-only barrier: memory operations are not moved across it
-__device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
-
 // the three fields of a representation row the transforms use
 struct Row3 {
   double D, LD, LLD;
@@ -1157,201 +1198,304 @@ __device__ __forceinline__ Row3 load_row3(const Rep* __restrict__ R, int i) {
   return r;
 }
 
-constexpr int kHB = 8;  // steps per half of a double buffer
+// compiler-only barrier: memory operations are not moved across it
+__device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
 
-// software pipeline over steps t = 0 .. T - 1 (T wave-uniform): the loads of
-// one half of kHB steps are issued while the other half is consumed, so every
-// value arrives kHB .. 2 kHB - 1 steps after its load was issued.  load(t)
-// must be in bounds for any t >= 0; step(t, v) sees steps in order.
-template <class Ld, class St>
-__device__ __forceinline__ void pipelined(int T, Ld&& load, St&& step) {
-  using V = decltype(load(0));
-  V a[kHB], b[kHB];
-#pragma unroll
-  for (int k = 0; k < kHB; ++k) a[k] = load(k);
-  for (int t0 = 0; t0 < T; t0 += 2 * kHB) {
-#pragma unroll
-    for (int k = 0; k < kHB; ++k) b[k] = load(t0 + kHB + k);
+// One step of the unified transform: role 0 (stationary, top-down) b = D,
+// f = LLD; role 1 (progressive, bottom-up) b = LLD, f = D.  Returns
+// x' = x f / (b + x) - lam and sets w = LD / (b + x), both quotients to about
+// one ulp (reciprocal with one Newton step, then one Newton correction of the
+// quotient).  With `guard` (kMayGuard instantiations only) a pivot below
+// pivmin becomes -pivmin and a quotient whose reciprocal vanished gives f - lam.
+template <bool kMayGuard>
+__device__ __forceinline__ double xstep(int role, const Row3& rr, double x, double lam, double pivmin, bool guard,
+                                        double& w) {
+  const double b = role ? rr.LLD : rr.D;
+  const double f = role ? rr.D : rr.LLD;
+  double den = b + x;
+  if (kMayGuard) den = (guard && fabs(den) < pivmin) ? -pivmin : den;
+  const double rc = rcp_nr1(den);
+  const double xf = x * f;
+  const double q0 = xf * rc;
+  const double q = fma(rc, fma(-den, q0, xf), q0);
+  double xn = q - lam;
+  if (kMayGuard) xn = (guard && (role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : xn;
+  const double w0 = rr.LD * rc;
+  w = fma(rc, fma(-den, w0, rr.LD), w0);
+  return xn;
+}
+
+// rows of one segment plus up to two checkpoint values
+struct SegRows {
+  Row3 r[kSeg];
+  double ck0, ck1;
+};
+
+// software pipeline over segment iterations j = 0 .. J - 1 (J wave-uniform):
+// the rows of iteration j + 1 are in flight while iteration j computes.
+// load(j) must stay in bounds for every j >= 0.
+template <class Ld, class Bd>
+__device__ __forceinline__ void seg_pipelined(int J, Ld&& load, Bd&& body) {
+  SegRows a = load(0), b;
+  for (int j = 0; j < J; j += 2) {
+    b = load(j + 1);
     ring_fence();
-#pragma unroll
-    for (int k = 0; k < kHB; ++k) step(t0 + k, a[k]);
+    body(j, a);
     ring_fence();
-#pragma unroll
-    for (int k = 0; k < kHB; ++k) a[k] = load(t0 + 2 * kHB + k);
+    a = load(j + 2);
     ring_fence();
-#pragma unroll
-    for (int k = 0; k < kHB; ++k) step(t0 + kHB + k, b[k]);
+    if (j + 1 < J) body(j + 1, b);
     ring_fence();
   }
 }
 
-struct Pair2 {
-  double s, p;
-};
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
-// one Rayleigh-quotient iteration sequence for the eigenvector of lane pair c;
-// role 0 = top-down / upward lane, role 1 = bottom-up / downward lane.  Work
-// vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = L+_i then z above the
-// twist, W1 = U-_i then z from the twist down.  Returns the twist index of the
-// last solve (z is in W0 for rows < r and in W1 for rows >= r).
+// Segment k covers rows [k kSeg, (k + 1) kSeg).  A lane visits the rows of a
+// segment in its role's order: ascending (role 0), descending (role 1).
+__device__ __forceinline__ int seg_row(int role, int k, int u) {
+  return role ? k * kSeg + kSeg - 1 - u : k * kSeg + u;
+}
+
+// 1. the transforms of the lane's role over all rows, storing the checkpoints
+//    SC[k] = s at row k kSeg (role 0) and PC[k] = p at row k kSeg, k >= 1
+//    (role 1).  Returns the last value (s_n or p_1).
+template <int kPairSlots, bool kMayGuard>
+__device__ inline double transform_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
+                                        double lam, double x0, double* __restrict__ SC, double* __restrict__ PC,
+                                        int c) {
+  const int nseg = (n + kSeg - 1) / kSeg;
+  const int J = wave_max(nseg);
+  double x = x0;
+  seg_pipelined(
+      J,
+      [&](int j) {
+        SegRows v;
+        const int k = min(role ? nseg - 1 - j : j, nseg - 1);
+        const int kk = max(k, 0);
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(seg_row(role, kk, u), n - 1));
+        v.ck0 = v.ck1 = 0.0;
+        return v;
+      },
+      [&](int j, const SegRows& v) {
+        const bool on = go && j < nseg;
+        const int k = role ? nseg - 1 - j : j;
+        if (on && !role) SC[(int64_t)k * kPairSlots + c] = x;
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+          const int row = seg_row(role, k, u);
+          double w;
+          const double xn = xstep<kMayGuard>(role, v.r[u], x, lam, pivmin, true, w);
+          x = (on && row <= n - 2) ? xn : x;
+        }
+        if (on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
+      });
+  return x;
+}
+
+// 2. twist index: lane 2c searches the segments below the middle one, lane
+//    2c+1 the rest; per segment s is recomputed upward from SC, then p
+//    downward from PC (or from p_n) with gamma at every row.  Ties go to the
+//    smaller index.
+template <int kPairSlots, bool kMayGuard>
+__device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, double lam,
+                                  double xlast, const double* __restrict__ SC, const double* __restrict__ PC, int c,
+                                  double& gmin_out, int& r_out) {
+  const int nseg = (n + kSeg - 1) / kSeg;
+  const int hs = nseg >> 1;
+  const int cnt = role ? nseg - hs : hs;
+  const int J = wave_max(cnt);
+  double gbest = INFINITY;
+  int rbest = -1;
+  seg_pipelined(
+      J,
+      [&](int j) {
+        SegRows v;
+        const int k = min(role ? hs + j : j, nseg - 1);
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(k * kSeg + u, n - 1));
+        v.ck0 = SC[(int64_t)k * kPairSlots + c];
+        v.ck1 = PC[(int64_t)min(k + 1, nseg - 1) * kPairSlots + c];
+        return v;
+      },
+      [&](int j, const SegRows& v) {
+        const bool on = go && j < cnt;
+        const int k = role ? hs + j : j;
+        // s_i at the rows of the segment
+        double sv[kSeg];
+        double x = v.ck0;
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+          const int row = k * kSeg + u;
+          sv[u] = x;
+          double w;
+          const double xn = xstep<kMayGuard>(0, v.r[u], x, lam, pivmin, true, w);
+          x = (row <= n - 2) ? xn : x;
+        }
+        // p_i from the first row of the next segment (or p_n) downward
+        const int rs = min((k + 1) * kSeg, n - 1);
+        double xp = (rs == n - 1) ? xlast : v.ck1;
+        double gseg = INFINITY;
+        int rseg = -1;
+#pragma unroll
+        for (int u = kSeg - 1; u >= 0; --u) {
+          const int row = k * kSeg + u;
+          double w;
+          const double xpn = xstep<kMayGuard>(1, v.r[u], xp, lam, pivmin, true, w);
+          xp = (row < rs) ? xpn : xp;
+          const double g = sv[u] + xp + lam;
+          if (on && row <= rs && isfinite(g) && fabs(g) <= fabs(gseg)) {
+            gseg = g;
+            rseg = row;
+          }
+        }
+        if (fabs(gseg) < fabs(gbest)) {
+          gbest = gseg;
+          rbest = rseg;
+        }
+      });
+  // the partner's candidate; ties go to the smaller index (lane 2c's half)
+  const double go_g = __shfl_xor(gbest, 1, 64);
+  const int go_r = __shfl_xor(rbest, 1, 64);
+  const double gt = role ? go_g : gbest, gb = role ? gbest : go_g;
+  const int rt = role ? go_r : rbest, rb = role ? rbest : go_r;
+  const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
+  double gmin = take_b ? gb : gt;
+  int r = take_b ? rb : rt;
+  if (r < 0) {
+    r = 0;
+    gmin = 0.0;
+  }
+  gmin_out = gmin;
+  r_out = r;
+}
+
+// 3. the solve outward from the twist r, segment by segment: lane 2c from the
+//    segment of row r-1 up to the first, lane 2c+1 from the segment of row r
+//    down to the last.  A segment's quotients are recomputed from its
+//    checkpoint, then z walks through it; where a z is zero the row of
+//    L D L^T - lam I gives the next one from the one before.  Accumulates
+//    ||z||^2 and the signed entry of largest magnitude (ties: smaller row) of
+//    the lane's half; with kWrite, stores z * scale into Zc (z_r by the caller).
+template <int kPairSlots, bool kMayGuard, bool kWrite>
+__device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, bool guard,
+                                  double lam, double xlast, int r, const double* __restrict__ SC,
+                                  const double* __restrict__ PC, int c, double* __restrict__ Zc, double scale,
+                                  double& nrm_out, double& zbest_out) {
+  const int nseg = (n + kSeg - 1) / kSeg;
+  const bool has = go && (role ? r <= n - 2 : r >= 1);
+  const int k0 = role ? r / kSeg : (r - 1) / kSeg;
+  const int cnt = has ? (role ? (n - 2) / kSeg - k0 + 1 : k0 + 1) : 0;
+  const int J = wave_max(cnt);
+  double nrm = (go && role) ? 1.0 : 0.0;
+  double zbest = (go && role) ? 1.0 : 0.0;
+  double zc = 1.0, zp = 0.0;
+  const int dir = role ? 1 : -1;
+  seg_pipelined(
+      J,
+      [&](int j) {
+        SegRows v;
+        const int k = min(max(role ? k0 + j : k0 - j, 0), nseg - 1);
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(seg_row(role, k, u), n - 1));
+        v.ck0 = role ? PC[(int64_t)min(k + 1, nseg - 1) * kPairSlots + c] : SC[(int64_t)k * kPairSlots + c];
+        v.ck1 = 0.0;
+        return v;
+      },
+      [&](int j, const SegRows& v) {
+        const bool on = j < cnt;
+        const int k = role ? k0 + j : k0 - j;
+        const int rs = min((k + 1) * kSeg, n - 1);
+        double x = (role && rs == n - 1) ? xlast : v.ck0;
+        double wb[kSeg];
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+          const int row = seg_row(role, k, u);
+          const double xn = xstep<kMayGuard>(role, v.r[u], x, lam, pivmin, guard, wb[u]);
+          x = (role ? row < rs : row <= n - 2) ? xn : x;
+        }
+        // rows in solve order: descending (role 0), ascending (role 1)
+#pragma unroll
+        for (int u = kSeg - 1; u >= 0; --u) {
+          const int row = seg_row(role, k, u);
+          const bool act = on && (role ? (row >= r && row <= n - 2) : (row <= r - 1));
+          if (act) {
+            const bool first = role ? (row == r) : (row == r - 1);
+            double zn;
+            if (zc != 0.0 || first) {
+              zn = -wb[u] * zc;
+            } else if (zp != 0.0) {
+              const double ldi = R[row].LD;
+              const double ldn = R[row - dir].LD;
+              zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+            } else {
+              zn = 0.0;  // an underflowed tail stays zero
+            }
+            zn = isfinite(zn) ? zn : 0.0;
+            if (kWrite) Zc[role ? row + 1 : row] = zn * scale;
+            zp = zc;
+            zc = zn;
+            nrm += zn * zn;
+            if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
+          }
+        }
+      });
+  nrm_out = nrm;
+  zbest_out = zbest;
+}
+
+// Rayleigh-quotient iteration for the eigenvector of lane pair c (role 0 =
+// top-down / upward lane, role 1 = bottom-up / downward lane) over
+// checkpoints SC, PC ([segment][kPairSlots] each).  Returns the twist index of
+// the last solve, with its shift in lam_last and its guard flag in g_last.
 template <int kPairSlots>
-__device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, int n, int nmax, double pivmin,
-                               double* __restrict__ S, double* __restrict__ P, double* __restrict__ W0,
-                               double* __restrict__ W1, int c, VecState& V) {
+__device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, int n, double pivmin,
+                               double* __restrict__ SC, double* __restrict__ PC, int c, VecState& V,
+                               double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
   int rout = 0;
-  // wave-uniform trip counts
-  int T = n - 1;
-  for (int o = 32; o > 0; o >>= 1) T = max(T, __shfl_xor(T, o, 64));
-  double* const X = role ? P : S;    // this lane's transform variable
-  double* const Wr = role ? W1 : W0;  // this lane's quotients, then z
+  const double dn = R[n - 1].D;
   for (int it = 0; it <= kMaxRqi; ++it) {
     const bool go = solve && !conv;
     if (__ballot(go) == 0) break;
     const double lam = V.lam;
-    // 1. the two transforms, concurrently; each step also stores the quotient
-    //    the solve will need (L+_i on the top lane, U-_i on the bottom lane)
-    double x;
-    if (role) {
-      x = R[n - 1].D - lam;
-      if (go) P[(int64_t)(n - 1) * kPairSlots + c] = x;
-    } else {
-      x = -lam;
-    }
+    const double xlast = dn - lam;  // p_n
+    // 1. the two transforms, concurrently.  Without a zero or overflowing
+    //    pivot (the usual case) the guard and the special-case rule are
+    //    no-ops, so the first pass runs without them; a lane that ends with a
+    //    non-finite value makes the wavefront repeat the pass with both, and
+    //    the recomputations of this solve follow the pass that was kept.
+    const double x0 = role ? xlast : -lam;
+    bool guarded = false;
     {
-      // rows in two buffers of kHB: one is consumed while the other's loads
-      // are in flight (prefetch distance kHB .. 2 kHB - 1 steps)
-      // Without a zero or overflowing pivot (the usual case) the guard and
-      // the special-case rule are no-ops, so the first pass runs without them
-      // (three dependent operations fewer per row); a lane that ends with a
-      // non-finite value makes the wavefront repeat the pass with both.
-      auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
-      const double x0 = x;
-      for (int guarded = 0; guarded < 2; ++guarded) {
-        x = x0;
-        auto step = [&](int t, const Row3& rr) {
-          if (t < T && go && t < n - 1) {
-            const int row = role ? n - 2 - t : t;
-            const double b = role ? rr.LLD : rr.D;
-            const double f = role ? rr.D : rr.LLD;
-            double den = b + x;
-            if (guarded) den = (fabs(den) < pivmin) ? -pivmin : den;
-            const double rc = rcp_nr1(den);
-            const double xf = x * f;
-            const double q0 = xf * rc;
-            const double q = fma(rc, fma(-den, q0, xf), q0);
-            double xn = q - lam;
-            if (guarded) xn = ((role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : xn;
-            // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
-            const double w0 = rr.LD * rc;
-            const double w = fma(rc, fma(-den, w0, rr.LD), w0);
-            const int64_t o = (int64_t)row * kPairSlots + c;
-            X[o] = role ? xn : x;
-            Wr[o] = w;
-            x = xn;
-          }
-        };
-        pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
-        if (__ballot(go && !isfinite(x)) == 0) break;
+      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, x0, SC, PC, c);
+      if (__ballot(go && !isfinite(x)) != 0) {
+        guarded = true;
+        transform_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, x0, SC, PC, c);
       }
     }
-    if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
-    __syncthreads();  // S and P complete and visible to the partner lane
-    // 2. twist index: lane 2c scans k < h, lane 2c+1 scans k >= h
-    const int h = n >> 1;
-    double gmin = INFINITY;
-    int r = -1;
+    __syncthreads();  // checkpoints complete and visible to the partner lane
+    // 2. twist index
+    double gmin;
+    int r;
+    if (guarded)
+      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, gmin, r);
+    else
+      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, gmin, r);
+    // 3. solve: ||z||^2 and the largest entry
+    double nrm, zbest;
+    if (guarded)
+      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, true, lam, xlast, r, SC, PC, c, nullptr, 1.0, nrm,
+                                          zbest);
+    else
+      solve_pass<kPairSlots, false, false>(go, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, nullptr, 1.0,
+                                           nrm, zbest);
     {
-      const int kb = role ? h : 0;
-      const int kc = role ? n - h : h;
-      int T2 = kc;
-      for (int o = 32; o > 0; o >>= 1) T2 = max(T2, __shfl_xor(T2, o, 64));
-      pipelined(
-          T2,
-          [&](int t) {
-            const int64_t o = (int64_t)clamp_row(kb + t, n) * kPairSlots + c;
-            Pair2 v;
-            v.s = S[o];
-            v.p = P[o];
-            return v;
-          },
-          [&](int t, const Pair2& v) {
-            if (t < T2 && go && t < kc) {
-              const double g = v.s + v.p + lam;
-              if (isfinite(g) && fabs(g) < fabs(gmin)) {
-                gmin = g;
-                r = kb + t;
-              }
-            }
-          });
-      // the partner's candidate; ties go to the smaller index (the upper half)
-      const double go_g = __shfl_xor(gmin, 1, 64);
-      const int go_r = __shfl_xor(r, 1, 64);
-      const double gt = role ? go_g : gmin, gb = role ? gmin : go_g;
-      const int rt = role ? go_r : r, rb = role ? r : go_r;
-      const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
-      gmin = take_b ? gb : gt;
-      r = take_b ? rb : rt;
-      if (r < 0) {
-        r = 0;
-        gmin = 0.0;
-      }
-    }
-    // 3. solves outward from the twist: z_i = -L+_i z_{i+1} upward (lane 2c),
-    //    z_{i+1} = -U-_i z_i downward (lane 2c+1); where a z is zero the row
-    //    of L D L^T - lam I gives the next one from the one before.  Rows are
-    //    visited in a wave-uniform order per role (top lanes from the largest
-    //    twist index of the wave down, bottom lanes from the smallest up), each
-    //    lane active on its own side of its twist, so every access is one
-    //    coalesced row of the work vector.
-    double nrm = 0.0, zbest = 0.0;
-    {
-      if (go && role) {
-        nrm = 1.0;
-        zbest = 1.0;
-      }
-      int rmax = (go && !role) ? r : 0;        // top lanes: rows rmax-1 .. 0
-      int rmin = (go && role) ? r : INT_MAX;   // bottom lanes: rows rmin .. n-2
-      for (int o = 32; o > 0; o >>= 1) {
-        rmax = max(rmax, __shfl_xor(rmax, o, 64));
-        rmin = min(rmin, __shfl_xor(rmin, o, 64));
-      }
-      if (rmin == INT_MAX) rmin = 0;  // no lane iterating: nothing to visit
-      int nb = (go && role) ? n - 1 - rmin : 0;
-      for (int o = 32; o > 0; o >>= 1) nb = max(nb, __shfl_xor(nb, o, 64));
-      const int T3 = max(rmax, nb);
-      const int base = role ? rmin : rmax - 1;
-      const int dir = role ? 1 : -1;
-      double zc = 1.0, zp = 0.0;
-      pipelined(
-          T3, [&](int t) { return Wr[(int64_t)clamp_row(base + dir * t, n) * kPairSlots + c]; },
-          [&](int t, double w) {
-            const int row = base + dir * t;
-            const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
-            if (t < T3 && go && on) {
-              const bool first = role ? (row == r) : (row == r - 1);
-              double zn;
-              if (zc != 0.0 || first) {
-                zn = -w * zc;
-              } else if (zp != 0.0) {
-                const double ldi = R[row].LD;
-                const double ldn = R[row - dir].LD;
-                zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
-              } else {
-                zn = 0.0;  // an underflowed tail stays zero
-              }
-              zn = isfinite(zn) ? zn : 0.0;
-              const int zrow = role ? row + 1 : row;
-              Wr[(int64_t)zrow * kPairSlots + c] = zn;
-              zp = zc;
-              zc = zn;
-              nrm += zn * zn;
-              // largest magnitude, ties to the smaller row
-              if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
-            }
-          });
-      if (go && role) W1[(int64_t)r * kPairSlots + c] = 1.0;
       // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
       const double nrm_o = __shfl_xor(nrm, 1, 64);
       const double zb_o = __shfl_xor(zbest, 1, 64);
@@ -1359,9 +1503,11 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
       zbest = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
     }
-    __syncthreads();  // z complete before the next transform overwrites the work vectors
+    __syncthreads();  // checkpoints read before the next transform overwrites them
     if (go) {
       rout = r;
+      lam_last = lam;
+      g_last = guarded;
       rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
     }
   }
@@ -1377,7 +1523,6 @@ __global__ void __launch_bounds__(64) k_vectors(
     const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
     const double* __restrict__ sgap, const Rep* __restrict__ pool, const double* __restrict__ ds,
     double* __restrict__ scratch, double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
-  __shared__ double tile[kPairSlots][kZRows + 1];
   __shared__ int64_t s_col[kPairSlots];
   __shared__ int64_t s_zoff[kPairSlots];
   __shared__ int s_n[kPairSlots];
@@ -1390,7 +1535,7 @@ __global__ void __launch_bounds__(64) k_vectors(
   if (ci >= nchunks) return;
   const int64_t chunk = chunks[ci];
   const int64_t s = chunk * kPairSlots + c;
-  double* S = scratch + chunk_off[ci];
+  double* SC = scratch + chunk_off[ci];
   const bool lane_slot = c < kPairSlots;  // lanes beyond 2 * kPairSlots idle
   bool act = false;
   if (lane_slot && s < ntot) act = (sflag[s] & F_SINGLETON) && scol[s] >= 0;
@@ -1402,12 +1547,9 @@ __global__ void __launch_bounds__(64) k_vectors(
   const Block blk = B[sblk[ss]];
   const Node nd = N[snode[ss]];
   const int n = blk.n;
-  int nmax = act ? n : 0;
-  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-  double* Pv = S + (int64_t)nmax * kPairSlots;
-  double* W0 = Pv + (int64_t)nmax * kPairSlots;
-  double* W1 = W0 + (int64_t)nmax * kPairSlots;
-  const int cs = lane_slot ? c : 0;  // scratch column (idle lanes never store)
+  const int nmax = wave_max(act ? n : 0);
+  double* PC = SC + (int64_t)((nmax + kSeg - 1) / kSeg) * kPairSlots;
+  const int cs = lane_slot ? c : 0;  // checkpoint column (idle lanes never store)
   VecState V;
   V.lo = lo_a[ss];
   V.hi = hi_a[ss];
@@ -1423,17 +1565,18 @@ __global__ void __launch_bounds__(64) k_vectors(
   V.rq = 0;
   V.fallback = false;
   const bool solve = act && n > 1;
-  int r = 0;
-  if (act && n == 1 && role) W1[c] = 1.0;
-  r = pair_rqi<kPairSlots>(solve, role, pool + nd.rep, n, nmax, blk.pivmin, S, Pv, W0, W1, cs, V);
+  double lam_last = V.lam;
+  bool g_last = false;
+  const Rep* R = pool + nd.rep;
+  const int r = pair_rqi<kPairSlots>(solve, role, R, n, blk.pivmin, SC, PC, cs, V, lam_last, g_last);
   double scale = 1.0;
   if (solve) {
     scale = 1.0 / sqrt(V.nrm);
     if (V.zmaxv < 0.0) scale = -scale;
   }
+  const Problem pr = P[blk.prob];
   // eigenvalue (once per pair)
   if (act && !role) {
-    const Problem pr = P[blk.prob];
     const double wv = (n == 1) ? ds[s] / pr.scale : (nd.acc + V.lam_out) / pr.scale;
     w_out[pr.off + col] = wv;
     s_col[c] = col;
@@ -1448,33 +1591,12 @@ __global__ void __launch_bounds__(64) k_vectors(
   }
   __syncthreads();
   if (Z != nullptr) {
-    // z * scale into column-major Z through an LDS transpose: each pass stages
-    // 32 rows x 32 columns (lane 2c rows 0-15 of column c, lane 2c+1 rows
-    // 16-31), then every column gets one contiguous 256-byte segment
-    for (int r0 = 0; r0 < nmax; r0 += kZRows) {
-      double v[kZRows / 2];
-#pragma unroll
-      for (int k = 0; k < kZRows / 2; ++k) {
-        const int row = r0 + role * (kZRows / 2) + k;
-        const double* src = (row < r) ? W0 : W1;
-        v[k] = (row < nmax) ? src[(int64_t)row * kPairSlots + cs] : 0.0;
-      }
-      if (lane_slot) {
-#pragma unroll
-        for (int k = 0; k < kZRows / 2; ++k) {
-          const int row = r0 + role * (kZRows / 2) + k;
-          tile[c][role * (kZRows / 2) + k] = (act && row < n) ? v[k] * scale : 0.0;
-        }
-      }
-      __syncthreads();
-      const int rr = lane & (kZRows - 1);
-      for (int cg = 0; cg < kPairSlots; cg += 2) {
-        const int cl = cg + (lane >> 5);
-        const int i = r0 + rr;
-        if (s_col[cl] >= 0 && i < s_n[cl]) Z[s_zoff[cl] + s_lrow0[cl] + i] = tile[cl][rr];
-      }
-      __syncthreads();
-    }
+    // the last solve once more, z * scale straight into the lane's column
+    double* Zc = Z + (act ? pr.zoff + col * pr.ldz + blk.lrow0 : 0);
+    double nrm_d, zb_d;
+    solve_pass<kPairSlots, true, true>(solve, role, R, n, blk.pivmin, g_last, lam_last, R[n - 1].D - lam_last, r, SC,
+                                       PC, cs, Zc, scale, nrm_d, zb_d);
+    if (act && role) Zc[solve ? r : 0] = scale;  // z_r = 1 (n = 1: the unit vector)
     // rows of the problem outside the block are exact zeros
     for (int cl = 0; cl < kPairSlots; ++cl) {
       if (s_col[cl] < 0) continue;
@@ -1495,8 +1617,7 @@ __global__ void __launch_bounds__(64) k_vectors(
     if (V.fallback) atomicAdd(&C->fallbacks, 1ull);
   }
   {
-    int rqm = V.rq;
-    for (int o = 32; o > 0; o >>= 1) rqm = max(rqm, __shfl_xor(rqm, o, 64));
+    const int rqm = wave_max(V.rq);
     if (lane == 0) atomicAdd(&C->wave_solves, (unsigned long long)rqm);
   }
 }
