@@ -66,12 +66,12 @@ struct DevBuf {
 struct Workspace {
   std::mutex mu;
   DevBuf problems, poff, sprob, ds, es, flag, excl, tiles, total, bstart, sblk, blocks, goff, nodes, pool, gcnt, lo,
-      hi, clo, chi, snode, sflag, scol, val, runflag, runid, runs, clusters, counters, chunkrows, chunks, chunkoff,
+      hi, clo, chi, snode, sflag, scol, val, runflag, runid, runs, clusters, counters, vrid, cflag, cid, cstart,
       scratch, bad, perm, tmp, sgap;
   size_t total_bytes() const {
     const DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                            &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
-                           &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad,
+                           &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &bad,
                            &perm, &tmp, &sgap};
     size_t t = 0;
     for (auto* b : all) t += b->bytes;
@@ -80,7 +80,7 @@ struct Workspace {
   void release() {
     DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                      &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
-                     &runid, &runs, &clusters, &counters, &chunkrows, &chunks, &chunkoff, &scratch, &bad, &perm,
+                     &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &bad, &perm,
                      &tmp, &sgap};
     for (auto* b : all) {
       if (b->p) (void)hipFree(b->p);
@@ -352,54 +352,36 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                   P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
                   dC, lanes);
     prof.end();
-    // 8. eigenvectors of all singletons (eigenvectors per wavefront: tuning,
-    //    32 by default; two checkpoint arrays of ceil(rows / kSeg) x slots
-    //    doubles per wavefront)
+    // 8. eigenvectors of all singletons: one wavefront per chunk of up to
+    //    vec_wave_slots (32 by default) consecutive singletons of one node;
+    //    two checkpoint arrays of ceil(n / kSeg) x slots doubles per chunk
     int vslots = tune.vec_wave_slots;
     if (vslots == 0) vslots = 32;
-    const int64_t nch = (ntot + vslots - 1) / vslots;
-    ENS(chunkrows, sizeof(int32_t) * nch);
-    launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), vslots,
-                      P_<int32_t>(W.chunkrows));
-    std::vector<int32_t> rows(nch);
-    HIP_TRY(hipMemcpyAsync(rows.data(), W.chunkrows.p, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, st));
+    ENS(vrid, sizeof(int32_t) * ntot);
+    ENS(cflag, sizeof(int32_t) * ntot);
+    ENS(cid, sizeof(int32_t) * ntot);
+    ENS(cstart, sizeof(int64_t) * (ntot + 1));
+    launch_vec_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), P_<int32_t>(W.snode), vslots,
+                      P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int32_t>(W.tiles), P_<int32_t>(W.total),
+                      P_<int32_t>(W.vrid), P_<int64_t>(W.runs), P_<int32_t>(W.cflag), P_<int32_t>(W.cid),
+                      P_<int64_t>(W.cstart));
+    int32_t nchunks = 0;
+    HIP_TRY(hipMemcpyAsync(&nchunks, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int32_t> act;
-    std::vector<int64_t> aoff;
-    int64_t maxper = 0;
-    for (int64_t c = 0; c < nch; ++c)
-      if (rows[c] > 0) {
-        act.push_back((int32_t)c);
-        maxper = std::max<int64_t>(maxper, 2 * vslots * (int64_t)((rows[c] + kSeg - 1) / kSeg));
-      }
-    const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
-    ENS(chunks, sizeof(int32_t) * (act.size() + 1));
-    ENS(chunkoff, sizeof(int64_t) * (act.size() + 1));
-    size_t i0 = 0;
-    while (i0 < act.size()) {
-      // the largest run of chunks whose scratch fits the budget
-      size_t i1 = i0;
-      int64_t used = 0;
-      aoff.clear();
-      while (i1 < act.size()) {
-        const int64_t need = 2 * vslots * (int64_t)((rows[act[i1]] + kSeg - 1) / kSeg);
-        if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
-        aoff.push_back(used);
-        used += need;
-        ++i1;
-      }
-      ENS(scratch, sizeof(double) * (size_t)used);
-      HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data() + i0, sizeof(int32_t) * (i1 - i0), hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * (i1 - i0), hipMemcpyHostToDevice, st));
+    int64_t nmax_all = 1;
+    for (auto& p : probs) nmax_all = std::max<int64_t>(nmax_all, p.n);
+    const int64_t stride = 2 * (int64_t)vslots * ((nmax_all + kSeg - 1) / kSeg);
+    const size_t budget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
+    const int64_t cmax = std::max<int64_t>(1, (int64_t)(budget / (sizeof(double) * (size_t)stride)));
+    ENS(scratch, sizeof(double) * (size_t)(std::min<int64_t>(std::max(nchunks, 1), cmax) * stride));
+    for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
+      const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
       prof.begin(MRRR_K_VECTORS);
-      launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff), (int)(i1 - i0),
-                     ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol),
-                     P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
-                     P_<double>(W.scratch), w, Z, dC, vslots);
+      launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot, P_<int32_t>(W.vrid),
+                     P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol), P_<double>(W.lo),
+                     P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds), P_<double>(W.scratch), stride, w,
+                     Z, dC, vslots);
       prof.end();
-      // host vectors are reused by the next batch: wait for the copies
-      HIP_TRY(hipStreamSynchronize(st));
-      i0 = i1;
     }
   }
   // 9. ascending order within each problem

@@ -9,6 +9,8 @@
 //   clusters         k_child, k_shift L_c D_c L_c^T = L D L^T - sigma_c I (stationary qds)
 //   singletons       k_vectors        twisted factorization + Rayleigh correction,
 //                    z written to column-major Z through an LDS transpose
+#include <type_traits>
+
 #include "mrrr_dev.h"
 #include "mrrr_launch.h"
 
@@ -1186,32 +1188,19 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   }
 }
 
-// the three fields of a representation row the transforms use
-struct Row3 {
-  double D, LD, LLD;
-};
-__device__ __forceinline__ Row3 load_row3(const Rep* __restrict__ R, int i) {
-  Row3 r;
-  r.D = R[i].D;
-  r.LD = R[i].LD;
-  r.LLD = R[i].LLD;
-  return r;
-}
-
 // compiler-only barrier: memory operations are not moved across it
 __device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
 
-// One step of the unified transform: role 0 (stationary, top-down) b = D,
-// f = LLD; role 1 (progressive, bottom-up) b = LLD, f = D.  Returns
-// x' = x f / (b + x) - lam and sets w = LD / (b + x), both quotients to about
-// one ulp (reciprocal with one Newton step, then one Newton correction of the
+// One step of the unified transform x' = x f / (b + x) - lam: role 0
+// (stationary, top-down) b = D, f = LLD; role 1 (progressive, bottom-up)
+// b = LLD, f = D.  Also sets w = LD / (b + x); both quotients to about one ulp
+// (reciprocal with one Newton step, then one Newton correction of the
 // quotient).  With `guard` (kMayGuard instantiations only) a pivot below
-// pivmin becomes -pivmin and a quotient whose reciprocal vanished gives f - lam.
+// pivmin becomes -pivmin, and where gnum / (b + x) vanishes (gnum = D for
+// role 1, LD for role 0) the step gives f - lam.
 template <bool kMayGuard>
-__device__ __forceinline__ double xstep(int role, const Row3& rr, double x, double lam, double pivmin, bool guard,
-                                        double& w) {
-  const double b = role ? rr.LLD : rr.D;
-  const double f = role ? rr.D : rr.LLD;
+__device__ __forceinline__ double xstep_bf(double b, double f, double LD, double gnum, double x, double lam,
+                                           double pivmin, bool guard, double& w) {
   double den = b + x;
   if (kMayGuard) den = (guard && fabs(den) < pivmin) ? -pivmin : den;
   const double rc = rcp_nr1(den);
@@ -1219,80 +1208,155 @@ __device__ __forceinline__ double xstep(int role, const Row3& rr, double x, doub
   const double q0 = xf * rc;
   const double q = fma(rc, fma(-den, q0, xf), q0);
   double xn = q - lam;
-  if (kMayGuard) xn = (guard && (role ? rr.D : rr.LD) * rc == 0.0) ? f - lam : xn;
-  const double w0 = rr.LD * rc;
-  w = fma(rc, fma(-den, w0, rr.LD), w0);
+  if (kMayGuard) xn = (guard && gnum * rc == 0.0) ? f - lam : xn;
+  const double w0 = LD * rc;
+  w = fma(rc, fma(-den, w0, LD), w0);
   return xn;
-}
-
-// rows of one segment plus up to two checkpoint values
-struct SegRows {
-  Row3 r[kSeg];
-  double ck0, ck1;
-};
-
-// software pipeline over segment iterations j = 0 .. J - 1 (J wave-uniform):
-// the rows of iteration j + 1 are in flight while iteration j computes.
-// load(j) must stay in bounds for every j >= 0.
-template <class Ld, class Bd>
-__device__ __forceinline__ void seg_pipelined(int J, Ld&& load, Bd&& body) {
-  SegRows a = load(0), b;
-  for (int j = 0; j < J; j += 2) {
-    b = load(j + 1);
-    ring_fence();
-    body(j, a);
-    ring_fence();
-    a = load(j + 2);
-    ring_fence();
-    if (j + 1 < J) body(j + 1, b);
-    ring_fence();
-  }
 }
 
 __device__ __forceinline__ int wave_max(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
-
-// Segment k covers rows [k kSeg, (k + 1) kSeg).  A lane visits the rows of a
-// segment in its role's order: ascending (role 0), descending (role 1).
-__device__ __forceinline__ int seg_row(int role, int k, int u) {
-  return role ? k * kSeg + kSeg - 1 - u : k * kSeg + u;
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
 }
 
-// 1. the transforms of the lane's role over all rows, storing the checkpoints
+constexpr int kSB = 64;           // representation rows per staged group
+constexpr int kGS = kSB / kSeg;   // segments per staged group
+
+// Segment iterations j = 0 .. J - 1 (J wave-uniform) for a wavefront whose
+// lanes share one representation R of n rows.  Lanes of role q visit segment
+// k0 + dir * j, with k0 and dir equal across the role.  The rows of kGS
+// consecutive segments of each role are staged through LDS one group ahead
+// (lanes 0-31 load the role-0 rows, lanes 32-63 the role-1 rows, 64 bytes per
+// lane per group); kNck per-lane checkpoint values per segment, ck(k, which),
+// are loaded one group ahead as well and parked in LDS.  fn(j, k, rows, c0,
+// c1) runs per iteration, rows pointing at the LDS copy of segment k (row u:
+// rows[4u .. 4u+3] = D, L, LD, LLD).  With kRoleOrder the copy is in the
+// order of the lane's role instead: role-1 lanes see the segment's rows
+// descending and each row as (LLD, L, LD, D), so that field 0 is b and field
+// 3 is f of the unified step for either role.  lds: kStageLds doubles.  Rows
+// outside [0, n) are clamped; every lane must call.
+constexpr int kStageLds = 2 * 2 * kSB * 4 + 2 * kGS * 64;
+
+template <int kNck, class Ck>
+__device__ __forceinline__ void stage_load(const double* __restrict__ Rd, int n, int b, int li, int k0, int dir, int g,
+                                           Ck& ck, double2& q0, double2& q1, double2& q2, double2& q3,
+                                           double (&c0)[kGS], double (&c1)[kGS]) {
+  const double2* s0 = reinterpret_cast<const double2*>(Rd + 4 * (int64_t)min(max(b + li, 0), n - 1));
+  const double2* s1 = reinterpret_cast<const double2*>(Rd + 4 * (int64_t)min(max(b + li + 1, 0), n - 1));
+  q0 = s0[0];
+  q1 = s0[1];
+  q2 = s1[0];
+  q3 = s1[1];
+#pragma unroll
+  for (int m = 0; m < kGS; ++m) {
+    const int k = k0 + dir * (g * kGS + m);
+    if (kNck > 0) c0[m] = ck(k, 0);
+    if (kNck > 1) c1[m] = ck(k, 1);
+  }
+}
+
+__device__ __forceinline__ int stage_first_seg(int k0, int dir, int g) {
+  return dir > 0 ? k0 + g * kGS : k0 - g * kGS - (kGS - 1);
+}
+
+template <int kNck, bool kRoleOrder, class Ck, class Fn>
+__device__ inline void staged_segments(const Rep* __restrict__ R, int n, int J, int k0, int dir,
+                                       double* __restrict__ lds, Ck&& ck, Fn&& fn) {
+  const int lane = threadIdx.x & 63;
+  const int role = lane & 1;
+  const int lrole = lane >> 5;
+  const int k0l = __shfl(k0, lrole, 64);  // lane 0 has role 0, lane 1 role 1
+  const int dirl = __shfl(dir, lrole, 64);
+  const int li = (lane & 31) * 2;
+  J = __builtin_amdgcn_readfirstlane(J);
+  const int ng = (J + kGS - 1) / kGS;
+  const double* Rd = reinterpret_cast<const double*>(R);
+  double* cks = lds + 2 * 2 * kSB * 4;  // [which][m][lane]
+  // LDS positions of this lane's two rows (reversed inside the segment and
+  // with D and LLD swapped for role-1 streams with kRoleOrder)
+  const bool rev = kRoleOrder && lrole == 1;
+  const int p0 = rev ? (li & ~(kSeg - 1)) + kSeg - 1 - (li & (kSeg - 1)) : li;
+  const int p1 = rev ? p0 - 1 : li + 1;
+  double2 q0, q1, q2, q3;
+  double c0[kGS], c1[kGS];
+#pragma unroll
+  for (int m = 0; m < kGS; ++m) c0[m] = c1[m] = 0.0;
+  stage_load<kNck>(Rd, n, stage_first_seg(k0l, dirl, 0) * kSeg, li, k0, dir, 0, ck, q0, q1, q2, q3, c0, c1);
+  for (int g = 0; g < ng; ++g) {
+    double* buf = lds + (g & 1) * (2 * kSB * 4);
+    double2* d0 = reinterpret_cast<double2*>(buf + lrole * kSB * 4 + p0 * 4);
+    double2* d1 = reinterpret_cast<double2*>(buf + lrole * kSB * 4 + p1 * 4);
+    if (rev) {
+      d0[0] = make_double2(q1.y, q0.y);
+      d0[1] = make_double2(q1.x, q0.x);
+      d1[0] = make_double2(q3.y, q2.y);
+      d1[1] = make_double2(q3.x, q2.x);
+    } else {
+      d0[0] = q0;
+      d0[1] = q1;
+      d1[0] = q2;
+      d1[1] = q3;
+    }
+#pragma unroll
+    for (int m = 0; m < kGS; ++m) {
+      if (kNck > 0) cks[m * 64 + lane] = c0[m];
+      if (kNck > 1) cks[(kGS + m) * 64 + lane] = c1[m];
+    }
+    __syncthreads();
+    if (g + 1 < ng)
+      stage_load<kNck>(Rd, n, stage_first_seg(k0l, dirl, g + 1) * kSeg, li, k0, dir, g + 1, ck, q0, q1, q2, q3, c0,
+                       c1);
+    const int b = stage_first_seg(k0, dir, g) * kSeg;
+    const double* mine = buf + role * kSB * 4;
+#pragma unroll 1
+    for (int m = 0; m < kGS; ++m) {
+      const int j = g * kGS + m;
+      if (j < J) {
+        const int k = k0 + dir * j;
+        const double v0 = (kNck > 0) ? cks[m * 64 + lane] : 0.0;
+        const double v1 = (kNck > 1) ? cks[(kGS + m) * 64 + lane] : 0.0;
+        fn(j, k, mine + (k * kSeg - b) * 4, v0, v1);
+      }
+    }
+  }
+}
+
+// 1. the transform of the lane's role over all rows, storing the checkpoints
 //    SC[k] = s at row k kSeg (role 0) and PC[k] = p at row k kSeg, k >= 1
 //    (role 1).  Returns the last value (s_n or p_1).
 template <int kPairSlots, bool kMayGuard>
 __device__ inline double transform_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
                                         double lam, double x0, double* __restrict__ SC, double* __restrict__ PC,
-                                        int c) {
+                                        int c, double* __restrict__ lds) {
   const int nseg = (n + kSeg - 1) / kSeg;
-  const int J = wave_max(nseg);
   double x = x0;
-  seg_pipelined(
-      J,
-      [&](int j) {
-        SegRows v;
-        const int k = min(role ? nseg - 1 - j : j, nseg - 1);
-        const int kk = max(k, 0);
+  staged_segments<0, true>(
+      R, n, nseg, role ? nseg - 1 : 0, role ? -1 : 1, lds, [](int, int) { return 0.0; },
+      [&](int, int k, const double* rows, double, double) {
+        if (go && !role) SC[(int64_t)k * kPairSlots + c] = x;
+        if (__ballot(k == nseg - 1) == 0) {
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(seg_row(role, kk, u), n - 1));
-        v.ck0 = v.ck1 = 0.0;
-        return v;
-      },
-      [&](int j, const SegRows& v) {
-        const bool on = go && j < nseg;
-        const int k = role ? nseg - 1 - j : j;
-        if (on && !role) SC[(int64_t)k * kPairSlots + c] = x;
+          for (int u = 0; u < kSeg; ++u) {
+            const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
+            double w;
+            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, true, w);
+          }
+        } else {
+          // the last segment: no step at row n-1 and beyond
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
-          const int row = seg_row(role, k, u);
-          double w;
-          const double xn = xstep<kMayGuard>(role, v.r[u], x, lam, pivmin, true, w);
-          x = (on && row <= n - 2) ? xn : x;
+          for (int u = 0; u < kSeg; ++u) {
+            const int o = role ? kSeg - 1 - u : u;
+            const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
+            double w;
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, true, w);
+            x = (k * kSeg + o <= n - 2) ? xn : x;
+          }
         }
-        if (on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
+        if (go && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
       });
   return x;
 }
@@ -1304,59 +1368,61 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
 template <int kPairSlots, bool kMayGuard>
 __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, double lam,
                                   double xlast, const double* __restrict__ SC, const double* __restrict__ PC, int c,
-                                  double& gmin_out, int& r_out) {
+                                  double* __restrict__ lds, double& gmin_out, int& r_out) {
   const int nseg = (n + kSeg - 1) / kSeg;
   const int hs = nseg >> 1;
   const int cnt = role ? nseg - hs : hs;
-  const int J = wave_max(cnt);
   double gbest = INFINITY;
   int rbest = -1;
-  seg_pipelined(
-      J,
-      [&](int j) {
-        SegRows v;
-        const int k = min(role ? hs + j : j, nseg - 1);
-#pragma unroll
-        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(k * kSeg + u, n - 1));
-        v.ck0 = SC[(int64_t)k * kPairSlots + c];
-        v.ck1 = PC[(int64_t)min(k + 1, nseg - 1) * kPairSlots + c];
-        return v;
+  staged_segments<2, false>(
+      R, n, nseg - hs, role ? hs : 0, 1, lds,
+      [&](int k, int which) {
+        const int kk = min(which ? k + 1 : k, nseg - 1);
+        return (which ? PC : SC)[(int64_t)kk * kPairSlots + c];
       },
-      [&](int j, const SegRows& v) {
+      [&](int j, int k, const double* rows, double c0, double c1) {
         const bool on = go && j < cnt;
-        const int k = role ? hs + j : j;
-        // s_i at the rows of the segment
-        double sv[kSeg];
-        double x = v.ck0;
+        // kEdge: the last segment (no step at row n-1 and beyond) is in play
+        auto seg = [&](auto E) {
+          constexpr bool kEdge = decltype(E)::value;
+          // s_i at the rows of the segment
+          double sv[kSeg];
+          double x = c0;
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
-          const int row = k * kSeg + u;
-          sv[u] = x;
-          double w;
-          const double xn = xstep<kMayGuard>(0, v.r[u], x, lam, pivmin, true, w);
-          x = (row <= n - 2) ? xn : x;
-        }
-        // p_i from the first row of the next segment (or p_n) downward
-        const int rs = min((k + 1) * kSeg, n - 1);
-        double xp = (rs == n - 1) ? xlast : v.ck1;
-        double gseg = INFINITY;
-        int rseg = -1;
-#pragma unroll
-        for (int u = kSeg - 1; u >= 0; --u) {
-          const int row = k * kSeg + u;
-          double w;
-          const double xpn = xstep<kMayGuard>(1, v.r[u], xp, lam, pivmin, true, w);
-          xp = (row < rs) ? xpn : xp;
-          const double g = sv[u] + xp + lam;
-          if (on && row <= rs && isfinite(g) && fabs(g) <= fabs(gseg)) {
-            gseg = g;
-            rseg = row;
+          for (int u = 0; u < kSeg; ++u) {
+            sv[u] = x;
+            double w;
+            const double LD = rows[4 * u + 2];
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, LD, x, lam, pivmin, true, w);
+            x = (!kEdge || k * kSeg + u <= n - 2) ? xn : x;
           }
-        }
-        if (fabs(gseg) < fabs(gbest)) {
-          gbest = gseg;
-          rbest = rseg;
-        }
+          // p_i from the first row of the next segment (or p_n) downward
+          const int rs = min((k + 1) * kSeg, n - 1);
+          double xp = (kEdge && rs == n - 1) ? xlast : c1;
+          double gseg = INFINITY;
+          int rseg = -1;
+#pragma unroll
+          for (int u = kSeg - 1; u >= 0; --u) {
+            const int row = k * kSeg + u;
+            double w;
+            const double D = rows[4 * u];
+            const double xpn =
+                xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], D, xp, lam, pivmin, true, w);
+            xp = (!kEdge || row < rs) ? xpn : xp;
+            const double g = sv[u] + xp + lam;
+            const bool take = (!kEdge || row <= rs) && isfinite(g) && fabs(g) <= fabs(gseg);
+            gseg = take ? g : gseg;
+            rseg = take ? row : rseg;
+          }
+          if (on && fabs(gseg) < fabs(gbest)) {
+            gbest = gseg;
+            rbest = rseg;
+          }
+        };
+        if (__ballot(k >= nseg - 1) != 0)
+          seg(std::true_type{});
+        else
+          seg(std::false_type{});
       });
   // the partner's candidate; ties go to the smaller index (lane 2c's half)
   const double go_g = __shfl_xor(gbest, 1, 64);
@@ -1374,68 +1440,81 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
   r_out = r;
 }
 
-// 3. the solve outward from the twist r, segment by segment: lane 2c from the
-//    segment of row r-1 up to the first, lane 2c+1 from the segment of row r
-//    down to the last.  A segment's quotients are recomputed from its
-//    checkpoint, then z walks through it; where a z is zero the row of
-//    L D L^T - lam I gives the next one from the one before.  Accumulates
-//    ||z||^2 and the signed entry of largest magnitude (ties: smaller row) of
-//    the lane's half; with kWrite, stores z * scale into Zc (z_r by the caller).
+// 3. the solve outward from the twist r: lane 2c from row r-1 up to row 0,
+//    lane 2c+1 from row r down to row n-1, segment by segment in one order per
+//    role (role 0 from the highest segment any of its lanes needs, role 1 from
+//    the lowest), each lane working from its own twist on.  A segment's
+//    quotients are recomputed from its checkpoint, then z walks through it;
+//    where a z is zero the row of L D L^T - lam I gives the next one from the
+//    one before.  Accumulates ||z||^2 and the signed entry of largest
+//    magnitude (ties: smaller row) of the lane's half; with kWrite, stores
+//    z * scale into Zc (z_r by the caller).
 template <int kPairSlots, bool kMayGuard, bool kWrite>
 __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, bool guard,
                                   double lam, double xlast, int r, const double* __restrict__ SC,
-                                  const double* __restrict__ PC, int c, double* __restrict__ Zc, double scale,
-                                  double& nrm_out, double& zbest_out) {
+                                  const double* __restrict__ PC, int c, double* __restrict__ lds,
+                                  double* __restrict__ Zc, double scale, double& nrm_out, double& zbest_out) {
   const int nseg = (n + kSeg - 1) / kSeg;
+  const int klast = (n - 2) / kSeg;  // segment of row n-2
   const bool has = go && (role ? r <= n - 2 : r >= 1);
-  const int k0 = role ? r / kSeg : (r - 1) / kSeg;
-  const int cnt = has ? (role ? (n - 2) / kSeg - k0 + 1 : k0 + 1) : 0;
-  const int J = wave_max(cnt);
+  const int kown = role ? r / kSeg : (r - 1) / kSeg;
+  const int kT = wave_max((has && !role) ? kown : -1);
+  const int kB = wave_min((has && role) ? kown : INT_MAX);
+  const int JT = kT + 1;
+  const int JB = (kB == INT_MAX) ? 0 : klast - kB + 1;
+  const int J = max(JT, JB);
   double nrm = (go && role) ? 1.0 : 0.0;
   double zbest = (go && role) ? 1.0 : 0.0;
   double zc = 1.0, zp = 0.0;
   const int dir = role ? 1 : -1;
-  seg_pipelined(
-      J,
-      [&](int j) {
-        SegRows v;
-        const int k = min(max(role ? k0 + j : k0 - j, 0), nseg - 1);
-#pragma unroll
-        for (int u = 0; u < kSeg; ++u) v.r[u] = load_row3(R, min(seg_row(role, k, u), n - 1));
-        v.ck0 = role ? PC[(int64_t)min(k + 1, nseg - 1) * kPairSlots + c] : SC[(int64_t)k * kPairSlots + c];
-        v.ck1 = 0.0;
-        return v;
+  staged_segments<1, true>(
+      R, n, J, role ? (kB == INT_MAX ? 0 : kB) : max(kT, 0), dir, lds,
+      [&](int k, int) {
+        const int kk = min(max(role ? k + 1 : k, 0), nseg - 1);
+        return (role ? PC : SC)[(int64_t)kk * kPairSlots + c];
       },
-      [&](int j, const SegRows& v) {
-        const bool on = j < cnt;
-        const int k = role ? k0 + j : k0 - j;
+      [&](int, int k, const double* rows, double c0, double) {
+        const bool seg_on = has && (role ? (k >= kown && k <= klast) : (k <= kown && k >= 0));
         const int rs = min((k + 1) * kSeg, n - 1);
-        double x = (role && rs == n - 1) ? xlast : v.ck0;
+        double x = (role && rs == n - 1) ? xlast : c0;
         double wb[kSeg];
+        auto quotients = [&](auto E) {
+          constexpr bool kEdge = decltype(E)::value;
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
-          const int row = seg_row(role, k, u);
-          const double xn = xstep<kMayGuard>(role, v.r[u], x, lam, pivmin, guard, wb[u]);
-          x = (role ? row < rs : row <= n - 2) ? xn : x;
-        }
+          for (int u = 0; u < kSeg; ++u) {
+            const int o = role ? kSeg - 1 - u : u;
+            const int row = k * kSeg + o;
+            const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, guard, wb[u]);
+            x = (!kEdge || (role ? row < rs : row <= n - 2)) ? xn : x;
+          }
+        };
+        if (__ballot(k >= nseg - 1) != 0)
+          quotients(std::true_type{});
+        else
+          quotients(std::false_type{});
         // rows in solve order: descending (role 0), ascending (role 1)
 #pragma unroll
         for (int u = kSeg - 1; u >= 0; --u) {
-          const int row = seg_row(role, k, u);
-          const bool act = on && (role ? (row >= r && row <= n - 2) : (row <= r - 1));
-          if (act) {
-            const bool first = role ? (row == r) : (row == r - 1);
-            double zn;
-            if (zc != 0.0 || first) {
-              zn = -wb[u] * zc;
-            } else if (zp != 0.0) {
-              const double ldi = R[row].LD;
-              const double ldn = R[row - dir].LD;
-              zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
-            } else {
-              zn = 0.0;  // an underflowed tail stays zero
+          const int o = role ? kSeg - 1 - u : u;
+          const int row = k * kSeg + o;
+          const bool act = seg_on && (role ? (row >= r && row <= n - 2) : (row <= r - 1));
+          const bool first = role ? (row == r) : (row == r - 1);
+          double zn = -wb[u] * zc;
+          const bool slow = act && !(zc != 0.0 || first);
+          if (__ballot(slow) != 0) {
+            if (slow) {
+              if (zp != 0.0) {
+                const double ldi = R[row].LD;
+                const double ldn = R[row - dir].LD;
+                zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+              } else {
+                zn = 0.0;  // an underflowed tail stays zero
+              }
             }
-            zn = isfinite(zn) ? zn : 0.0;
+          }
+          zn = isfinite(zn) ? zn : 0.0;
+          if (act) {
             if (kWrite) Zc[role ? row + 1 : row] = zn * scale;
             zp = zc;
             zc = zn;
@@ -1454,8 +1533,8 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
 // the last solve, with its shift in lam_last and its guard flag in g_last.
 template <int kPairSlots>
 __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, int n, double pivmin,
-                               double* __restrict__ SC, double* __restrict__ PC, int c, VecState& V,
-                               double& lam_last, bool& g_last) {
+                               double* __restrict__ SC, double* __restrict__ PC, int c, double* __restrict__ lds,
+                               VecState& V, double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
   int rout = 0;
@@ -1473,10 +1552,10 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     const double x0 = role ? xlast : -lam;
     bool guarded = false;
     {
-      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, x0, SC, PC, c);
+      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, x0, SC, PC, c, lds);
       if (__ballot(go && !isfinite(x)) != 0) {
         guarded = true;
-        transform_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, x0, SC, PC, c);
+        transform_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, x0, SC, PC, c, lds);
       }
     }
     __syncthreads();  // checkpoints complete and visible to the partner lane
@@ -1484,17 +1563,17 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     double gmin;
     int r;
     if (guarded)
-      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, gmin, r);
+      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, lds, gmin, r);
     else
-      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, gmin, r);
+      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, lds, gmin, r);
     // 3. solve: ||z||^2 and the largest entry
     double nrm, zbest;
     if (guarded)
-      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, true, lam, xlast, r, SC, PC, c, nullptr, 1.0, nrm,
-                                          zbest);
+      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, true, lam, xlast, r, SC, PC, c, lds, nullptr, 1.0,
+                                          nrm, zbest);
     else
-      solve_pass<kPairSlots, false, false>(go, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, nullptr, 1.0,
-                                           nrm, zbest);
+      solve_pass<kPairSlots, false, false>(go, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, lds, nullptr,
+                                           1.0, nrm, zbest);
     {
       // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
       const double nrm_o = __shfl_xor(nrm, 1, 64);
@@ -1515,14 +1594,19 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
   return rout;
 }
 
+// One wavefront per chunk: up to kPairSlots consecutive singletons of one
+// node (cstart[ci] is the chunk's first slot; rid: run of equal-node
+// singletons per slot, -1 elsewhere), so every lane works on the same
+// representation.  Checkpoints of chunk ci at scratch + ci * stride.
 template <int kPairSlots>
-__global__ void __launch_bounds__(64) k_vectors(
+__global__ void __launch_bounds__(64, 2) k_vectors(
     const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
-    const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
-    const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
-    const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
-    const double* __restrict__ sgap, const Rep* __restrict__ pool, const double* __restrict__ ds,
-    double* __restrict__ scratch, double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
+    const int64_t* __restrict__ cstart, int nchunks, int64_t ntot, const int32_t* __restrict__ rid,
+    const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const int64_t* __restrict__ scol,
+    const double* __restrict__ lo_a, const double* __restrict__ hi_a, const double* __restrict__ sgap,
+    const Rep* __restrict__ pool, const double* __restrict__ ds, double* __restrict__ scratch, int64_t stride,
+    double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
+  __shared__ double lds[kStageLds];
   __shared__ int64_t s_col[kPairSlots];
   __shared__ int64_t s_zoff[kPairSlots];
   __shared__ int s_n[kPairSlots];
@@ -1533,22 +1617,19 @@ __global__ void __launch_bounds__(64) k_vectors(
   const int role = lane & 1;
   const int ci = blockIdx.x;
   if (ci >= nchunks) return;
-  const int64_t chunk = chunks[ci];
-  const int64_t s = chunk * kPairSlots + c;
-  double* SC = scratch + chunk_off[ci];
+  const int64_t first = cstart[ci];
+  const int64_t s = first + c;
   const bool lane_slot = c < kPairSlots;  // lanes beyond 2 * kPairSlots idle
-  bool act = false;
-  if (lane_slot && s < ntot) act = (sflag[s] & F_SINGLETON) && scol[s] >= 0;
-  const uint64_t am = __ballot(act);
-  if (am == 0) return;
-  const int64_t sf = __shfl(s, first_lane(am), 64);
-  const int64_t ss = act ? s : sf;  // idle lanes shadow a valid slot
+  const int run = rid[first];
+  const bool act = lane_slot && s < ntot && rid[s] == run;
+  const int64_t ss = act ? s : first;  // idle lanes shadow the chunk's first slot
   const int64_t col = act ? scol[s] : -1;
-  const Block blk = B[sblk[ss]];
-  const Node nd = N[snode[ss]];
-  const int n = blk.n;
-  const int nmax = wave_max(act ? n : 0);
-  double* PC = SC + (int64_t)((nmax + kSeg - 1) / kSeg) * kPairSlots;
+  // one node per chunk: block, node and representation are the same in every lane
+  const Block blk = B[sblk[first]];
+  const Node nd = N[snode[first]];
+  const int n = __builtin_amdgcn_readfirstlane(blk.n);
+  double* SC = scratch + (int64_t)ci * stride;
+  double* PC = SC + (int64_t)((n + kSeg - 1) / kSeg) * kPairSlots;
   const int cs = lane_slot ? c : 0;  // checkpoint column (idle lanes never store)
   VecState V;
   V.lo = lo_a[ss];
@@ -1567,8 +1648,9 @@ __global__ void __launch_bounds__(64) k_vectors(
   const bool solve = act && n > 1;
   double lam_last = V.lam;
   bool g_last = false;
-  const Rep* R = pool + nd.rep;
-  const int r = pair_rqi<kPairSlots>(solve, role, R, n, blk.pivmin, SC, PC, cs, V, lam_last, g_last);
+  const Rep* R = pool + uniform_ll(nd.rep);
+  const double pivmin = __longlong_as_double(uniform_ll(__double_as_longlong(blk.pivmin)));
+  const int r = pair_rqi<kPairSlots>(solve, role, R, n, pivmin, SC, PC, cs, lds, V, lam_last, g_last);
   double scale = 1.0;
   if (solve) {
     scale = 1.0 / sqrt(V.nrm);
@@ -1594,8 +1676,9 @@ __global__ void __launch_bounds__(64) k_vectors(
     // the last solve once more, z * scale straight into the lane's column
     double* Zc = Z + (act ? pr.zoff + col * pr.ldz + blk.lrow0 : 0);
     double nrm_d, zb_d;
-    solve_pass<kPairSlots, true, true>(solve, role, R, n, blk.pivmin, g_last, lam_last, R[n - 1].D - lam_last, r, SC,
-                                       PC, cs, Zc, scale, nrm_d, zb_d);
+    if (n > 1)
+      solve_pass<kPairSlots, true, true>(solve, role, R, n, pivmin, g_last, lam_last, R[n - 1].D - lam_last, r, SC,
+                                         PC, cs, lds, Zc, scale, nrm_d, zb_d);
     if (act && role) Zc[solve ? r : 0] = scale;  // z_r = 1 (n = 1: the unit vector)
     // rows of the problem outside the block are exact zeros
     for (int cl = 0; cl < kPairSlots; ++cl) {
@@ -1622,16 +1705,47 @@ __global__ void __launch_bounds__(64) k_vectors(
   }
 }
 
-// scratch rows each chunk of `slots` slots needs (0: no singleton to compute)
-__global__ void k_chunk_rows(const Block* __restrict__ B, int64_t ntot, const int32_t* __restrict__ sblk,
-                             const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol, int slots,
-                             int32_t* __restrict__ rows) {
-  const int64_t s = (int64_t)blockIdx.x * slots + (threadIdx.x & (slots - 1));
-  int v = 0;
-  if ((int)threadIdx.x < slots && s < ntot && (sflag[s] & F_SINGLETON) && scol[s] >= 0) v = B[sblk[s]].n;
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  if (threadIdx.x == 0) rows[blockIdx.x] = v;
+// chunks for k_vectors: runs of consecutive singleton slots (with an output
+// column) of one node, cut into pieces of at most `slots`
+__device__ __forceinline__ bool vec_slot(const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                                        int64_t s) {
+  return (sflag[s] & F_SINGLETON) && scol[s] >= 0;
 }
+
+__global__ void k_vec_runs(int64_t ntot, const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                           const int32_t* __restrict__ snode, int32_t* __restrict__ runflag) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  int f = 0;
+  if (vec_slot(sflag, scol, s)) f = (s == 0 || !vec_slot(sflag, scol, s - 1) || snode[s - 1] != snode[s]) ? 1 : 0;
+  runflag[s] = f;
+}
+
+__global__ void k_vec_rid(int64_t ntot, const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                          const int32_t* __restrict__ runflag, const int32_t* __restrict__ runid,
+                          int32_t* __restrict__ rid, int64_t* __restrict__ rstart) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const bool v = vec_slot(sflag, scol, s);
+  rid[s] = v ? runid[s] + runflag[s] - 1 : -1;
+  if (runflag[s]) rstart[runid[s]] = s;
+}
+
+__global__ void k_vec_cflags(int64_t ntot, const int32_t* __restrict__ rid, const int64_t* __restrict__ rstart,
+                             int slots, int32_t* __restrict__ cflag) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int q = rid[s];
+  cflag[s] = (q >= 0 && (s - rstart[q]) % slots == 0) ? 1 : 0;
+}
+
+__global__ void k_vec_cstart(int64_t ntot, const int32_t* __restrict__ cflag, const int32_t* __restrict__ cid,
+                             int64_t* __restrict__ cstart) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  if (cflag[s]) cstart[cid[s]] = s;
+}
+
 
 // ---------------------------------------------------------------------------
 // 9. output order: eigenvalues ascending within each problem (swaps are only
@@ -1835,21 +1949,26 @@ void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag) {
   hipLaunchKernelGGL(k_clear_active, GRID1(ntot, 256), 0, st, ntot, sflag);
 }
 
-void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
-                       const int64_t* scol, int slots, int32_t* rows) {
-  const int64_t nch = (ntot + slots - 1) / slots;
-  hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)nch), dim3(64), 0, st, B, ntot, sblk, sflag, scol, slots, rows);
+void launch_vec_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, const int32_t* snode,
+                       int slots, int32_t* runflag, int32_t* runid, int32_t* tiles, int32_t* total, int32_t* rid,
+                       int64_t* rstart, int32_t* cflag, int32_t* cid, int64_t* cstart) {
+  if (ntot == 0) return;
+  hipLaunchKernelGGL(k_vec_runs, GRID1(ntot, 256), 0, st, ntot, sflag, scol, snode, runflag);
+  launch_scan(st, runflag, runid, tiles, ntot, total);
+  hipLaunchKernelGGL(k_vec_rid, GRID1(ntot, 256), 0, st, ntot, sflag, scol, runflag, runid, rid, rstart);
+  hipLaunchKernelGGL(k_vec_cflags, GRID1(ntot, 256), 0, st, ntot, rid, rstart, slots, cflag);
+  launch_scan(st, cflag, cid, tiles, ntot, total);
+  hipLaunchKernelGGL(k_vec_cstart, GRID1(ntot, 256), 0, st, ntot, cflag, cid, cstart);
 }
 
-void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
-                    const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
-                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const double* sgap,
-                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C,
-                    int slots) {
+void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int64_t* cstart,
+                    int nchunks, int64_t ntot, const int32_t* rid, const int32_t* sblk, const int32_t* snode,
+                    const int64_t* scol, const double* lo, const double* hi, const double* sgap, const Rep* pool,
+                    const double* ds, double* scratch, int64_t stride, double* w, double* Z, Counters* C, int slots) {
   if (nchunks == 0) return;
-#define MRRR_VEC(SL)                                                                                             \
-  hipLaunchKernelGGL(k_vectors<SL>, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, sblk, \
-                     snode, sflag, scol, lo, hi, sgap, pool, ds, scratch, w, Z, C)
+#define MRRR_VEC(SL)                                                                                               \
+  hipLaunchKernelGGL(k_vectors<SL>, dim3(nchunks), dim3(64), 0, st, P, B, N, cstart, nchunks, ntot, rid, sblk, snode, \
+                     scol, lo, hi, sgap, pool, ds, scratch, stride, w, Z, C)
   if (slots == 8)
     MRRR_VEC(8);
   else if (slots == 16)

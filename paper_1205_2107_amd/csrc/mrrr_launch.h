@@ -36,12 +36,13 @@ void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, 
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
                   int32_t* snode, uint32_t* sflag, double* sgap);
 void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag);
-void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
-                       const int64_t* scol, int slots, int32_t* rows);
-void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
-                    const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk, const int32_t* snode,
-                    const uint32_t* sflag, const int64_t* scol, const double* lo, const double* hi, const double* sgap,
-                    const Rep* pool, const double* ds, double* scratch, double* w, double* Z, Counters* C, int slots);
+void launch_vec_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, const int32_t* snode,
+                       int slots, int32_t* runflag, int32_t* runid, int32_t* tiles, int32_t* total, int32_t* rid,
+                       int64_t* rstart, int32_t* cflag, int32_t* cid, int64_t* cstart);
+void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int64_t* cstart,
+                    int nchunks, int64_t ntot, const int32_t* rid, const int32_t* sblk, const int32_t* snode,
+                    const int64_t* scol, const double* lo, const double* hi, const double* sgap, const Rep* pool,
+                    const double* ds, double* scratch, int64_t stride, double* w, double* Z, Counters* C, int slots);
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C);
 void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t* bad, double* w, int64_t* perm,
                      double* tmp, double* Z);
