@@ -345,26 +345,35 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       if (level > kMaxDepth + 2) break;
     }
     rep->nodes = node_base - nblk;
-    // singletons of child nodes: validated, full-accuracy brackets in their leaf's frame
+    // singletons of child nodes: validated, full-accuracy brackets in their
+    // leaf's frame; each wavefront takes eigenvalues of one node (chunks of
+    // equal-node slots) so that it reads one representation through LDS
     launch_mark_leaf(st, ntot, P_<int64_t>(W.scol), P_<uint32_t>(W.sflag));
+    ENS(vrid, sizeof(int32_t) * ntot);
+    ENS(cflag, sizeof(int32_t) * ntot);
+    ENS(cid, sizeof(int32_t) * ntot);
+    ENS(cstart, sizeof(int64_t) * (ntot + 1));
+    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_NEEDS_REFINE, false,
+                       P_<int32_t>(W.snode), 64 / lanes, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
+                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
+                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
+    int32_t nrchunks = 0;
+    HIP_TRY(hipMemcpyAsync(&nrchunks, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     prof.begin(MRRR_K_REFINE);
     launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
                   P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
-                  dC, lanes);
+                  dC, lanes, false, P_<int64_t>(W.cstart), P_<int32_t>(W.vrid), nrchunks);
     prof.end();
     // 8. eigenvectors of all singletons: one wavefront per chunk of up to
     //    vec_wave_slots (32 by default) consecutive singletons of one node;
     //    two checkpoint arrays of ceil(n / kSeg) x slots doubles per chunk
     int vslots = tune.vec_wave_slots;
     if (vslots == 0) vslots = 32;
-    ENS(vrid, sizeof(int32_t) * ntot);
-    ENS(cflag, sizeof(int32_t) * ntot);
-    ENS(cid, sizeof(int32_t) * ntot);
-    ENS(cstart, sizeof(int64_t) * (ntot + 1));
-    launch_vec_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), P_<int32_t>(W.snode), vslots,
-                      P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int32_t>(W.tiles), P_<int32_t>(W.total),
-                      P_<int32_t>(W.vrid), P_<int64_t>(W.runs), P_<int32_t>(W.cflag), P_<int32_t>(W.cid),
-                      P_<int64_t>(W.cstart));
+    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_SINGLETON, true,
+                       P_<int32_t>(W.snode), vslots, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
+                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
+                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
     int32_t nchunks = 0;
     HIP_TRY(hipMemcpyAsync(&nchunks, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -620,11 +620,24 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
                                                const int32_t* __restrict__ snode, const Rep* __restrict__ pool,
                                                double* __restrict__ lo_a, double* __restrict__ hi_a,
                                                int32_t* __restrict__ clo_a, int32_t* __restrict__ chi_a,
-                                               uint32_t* __restrict__ sflag, Counters* __restrict__ C, int vonly) {
+                                               uint32_t* __restrict__ sflag, Counters* __restrict__ C, int vonly,
+                                               const int64_t* __restrict__ cstart, const int32_t* __restrict__ rid,
+                                               int nchunks) {
   const int lane = threadIdx.x;
   const int k = lane % L, gbase = lane - k;
-  const int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L;
-  const bool act = (s < ntot) && (sflag[s] & F_NEEDS_REFINE);
+  // eigenvalues of the wavefront: 64 / L consecutive slots, or (cstart) the
+  // slots of one chunk of equal-node slots needing refinement
+  int64_t s;
+  bool act;
+  if (cstart != nullptr) {
+    if ((int)blockIdx.x >= nchunks) return;
+    const int64_t first = cstart[blockIdx.x];
+    s = first + lane / L;
+    act = s < ntot && rid[s] == rid[first];
+  } else {
+    s = (int64_t)blockIdx.x * (64 / L) + lane / L;
+    act = (s < ntot) && (sflag[s] & F_NEEDS_REFINE);
+  }
   const uint64_t am = __ballot(act);
   if (am == 0) return;
   const int64_t sf = __shfl(s, first_lane(am), 64);
@@ -1193,14 +1206,16 @@ __device__ __forceinline__ void ring_fence() { asm volatile("" ::: "memory"); }
 
 // One step of the unified transform x' = x f / (b + x) - lam: role 0
 // (stationary, top-down) b = D, f = LLD; role 1 (progressive, bottom-up)
-// b = LLD, f = D.  Also sets w = LD / (b + x); both quotients to about one ulp
+// b = LLD, f = D.  Also sets w = LD / (b + x); quotients to about one ulp
 // (reciprocal with one Newton step, then one Newton correction of the
-// quotient).  With `guard` (kMayGuard instantiations only) a pivot below
-// pivmin becomes -pivmin, and where gnum / (b + x) vanishes (gnum = D for
-// role 1, LD for role 0) the step gives f - lam.
+// quotient).  The fast form divides the product x f, which overflows once a
+// near-zero pivot has made x huge; the guarded form (`guard`, kMayGuard
+// instantiations only) takes the ratio first, x (f / (b + x)), as the qds
+// transforms do, replaces a pivot below pivmin by -pivmin, and gives f - lam
+// where the ratio vanishes (b + x infinite).
 template <bool kMayGuard>
-__device__ __forceinline__ double xstep_bf(double b, double f, double LD, double gnum, double x, double lam,
-                                           double pivmin, bool guard, double& w) {
+__device__ __forceinline__ double xstep_bf(double b, double f, double LD, double x, double lam, double pivmin,
+                                           bool guard, double& w) {
   double den = b + x;
   if (kMayGuard) den = (guard && fabs(den) < pivmin) ? -pivmin : den;
   const double rc = rcp_nr1(den);
@@ -1208,7 +1223,12 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
   const double q0 = xf * rc;
   const double q = fma(rc, fma(-den, q0, xf), q0);
   double xn = q - lam;
-  if (kMayGuard) xn = (guard && gnum * rc == 0.0) ? f - lam : xn;
+  if (kMayGuard) {
+    const double t0 = f * rc;
+    const double t = fma(rc, fma(-den, t0, f), t0);
+    const double xs = (t == 0.0) ? f - lam : x * t - lam;
+    xn = guard ? xs : xn;
+  }
   const double w0 = LD * rc;
   w = fma(rc, fma(-den, w0, LD), w0);
   return xn;
@@ -1343,7 +1363,7 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
           for (int u = 0; u < kSeg; ++u) {
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
-            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, true, w);
+            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, true, w);
           }
         } else {
           // the last segment: no step at row n-1 and beyond
@@ -1352,7 +1372,7 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
             const int o = role ? kSeg - 1 - u : u;
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, true, w);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, true, w);
             x = (k * kSeg + o <= n - 2) ? xn : x;
           }
         }
@@ -1393,7 +1413,7 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
             sv[u] = x;
             double w;
             const double LD = rows[4 * u + 2];
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, LD, x, lam, pivmin, true, w);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, x, lam, pivmin, true, w);
             x = (!kEdge || k * kSeg + u <= n - 2) ? xn : x;
           }
           // p_i from the first row of the next segment (or p_n) downward
@@ -1407,7 +1427,7 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
             double w;
             const double D = rows[4 * u];
             const double xpn =
-                xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], D, xp, lam, pivmin, true, w);
+                xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], xp, lam, pivmin, true, w);
             xp = (!kEdge || row < rs) ? xpn : xp;
             const double g = sv[u] + xp + lam;
             const bool take = (!kEdge || row <= rs) && isfinite(g) && fabs(g) <= fabs(gseg);
@@ -1485,7 +1505,7 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
             const int o = role ? kSeg - 1 - u : u;
             const int row = k * kSeg + o;
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, role ? f : LD, x, lam, pivmin, guard, wb[u]);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, wb[u]);
             x = (!kEdge || (role ? row < rs : row <= n - 2)) ? xn : x;
           }
         };
@@ -1705,28 +1725,31 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   }
 }
 
-// chunks for k_vectors: runs of consecutive singleton slots (with an output
-// column) of one node, cut into pieces of at most `slots`
-__device__ __forceinline__ bool vec_slot(const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
-                                        int64_t s) {
-  return (sflag[s] & F_SINGLETON) && scol[s] >= 0;
+// chunks of slots of one node: runs of consecutive slots that have every
+// flag of `need` (and, with need_col, an output column) and the same node,
+// cut into pieces of at most `slots`
+__device__ __forceinline__ bool chunk_slot(const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
+                                          uint32_t need, bool need_col, int64_t s) {
+  return (sflag[s] & need) == need && (!need_col || scol[s] >= 0);
 }
 
 __global__ void k_vec_runs(int64_t ntot, const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
-                           const int32_t* __restrict__ snode, int32_t* __restrict__ runflag) {
+                           uint32_t need, int need_col, const int32_t* __restrict__ snode,
+                           int32_t* __restrict__ runflag) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ntot) return;
   int f = 0;
-  if (vec_slot(sflag, scol, s)) f = (s == 0 || !vec_slot(sflag, scol, s - 1) || snode[s - 1] != snode[s]) ? 1 : 0;
+  if (chunk_slot(sflag, scol, need, need_col, s))
+    f = (s == 0 || !chunk_slot(sflag, scol, need, need_col, s - 1) || snode[s - 1] != snode[s]) ? 1 : 0;
   runflag[s] = f;
 }
 
 __global__ void k_vec_rid(int64_t ntot, const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol,
-                          const int32_t* __restrict__ runflag, const int32_t* __restrict__ runid,
-                          int32_t* __restrict__ rid, int64_t* __restrict__ rstart) {
+                          uint32_t need, int need_col, const int32_t* __restrict__ runflag,
+                          const int32_t* __restrict__ runid, int32_t* __restrict__ rid, int64_t* __restrict__ rstart) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ntot) return;
-  const bool v = vec_slot(sflag, scol, s);
+  const bool v = chunk_slot(sflag, scol, need, need_col, s);
   rid[s] = v ? runid[s] + runflag[s] - 1 : -1;
   if (runflag[s]) rstart[runid[s]] = s;
 }
@@ -1885,20 +1908,23 @@ void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t 
 
 void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
                    const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
-                   uint32_t* sflag, Counters* C, int lanes, bool validate_only) {
+                   uint32_t* sflag, Counters* C, int lanes, bool validate_only, const int64_t* cstart,
+                   const int32_t* rid, int nchunks) {
   // `lanes` lanes per eigenvalue: 64 / lanes eigenvalues per wavefront
   const unsigned g4 = (unsigned)((ntot + 15) / 16), g2 = (unsigned)((ntot + 31) / 32),
                  g1 = (unsigned)((ntot + 63) / 64);
   const int v = validate_only ? 1 : 0;
+  const bool ch = cstart != nullptr;
+  if (ch && nchunks == 0) return;
   if (lanes >= 4)
-    hipLaunchKernelGGL(k_refine<4>, dim3(g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
-                       v);
+    hipLaunchKernelGGL(k_refine<4>, dim3(ch ? (unsigned)nchunks : g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
   else if (lanes == 2)
-    hipLaunchKernelGGL(k_refine<2>, dim3(g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
-                       v);
+    hipLaunchKernelGGL(k_refine<2>, dim3(ch ? (unsigned)nchunks : g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
   else
-    hipLaunchKernelGGL(k_refine<1>, dim3(g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi, sflag, C,
-                       v);
+    hipLaunchKernelGGL(k_refine<1>, dim3(ch ? (unsigned)nchunks : g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
 }
 
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag) {
@@ -1949,13 +1975,15 @@ void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag) {
   hipLaunchKernelGGL(k_clear_active, GRID1(ntot, 256), 0, st, ntot, sflag);
 }
 
-void launch_vec_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, const int32_t* snode,
-                       int slots, int32_t* runflag, int32_t* runid, int32_t* tiles, int32_t* total, int32_t* rid,
-                       int64_t* rstart, int32_t* cflag, int32_t* cid, int64_t* cstart) {
+void launch_node_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, uint32_t need,
+                        bool need_col, const int32_t* snode, int slots, int32_t* runflag, int32_t* runid,
+                        int32_t* tiles, int32_t* total, int32_t* rid, int64_t* rstart, int32_t* cflag, int32_t* cid,
+                        int64_t* cstart) {
   if (ntot == 0) return;
-  hipLaunchKernelGGL(k_vec_runs, GRID1(ntot, 256), 0, st, ntot, sflag, scol, snode, runflag);
+  const int nc = need_col ? 1 : 0;
+  hipLaunchKernelGGL(k_vec_runs, GRID1(ntot, 256), 0, st, ntot, sflag, scol, need, nc, snode, runflag);
   launch_scan(st, runflag, runid, tiles, ntot, total);
-  hipLaunchKernelGGL(k_vec_rid, GRID1(ntot, 256), 0, st, ntot, sflag, scol, runflag, runid, rid, rstart);
+  hipLaunchKernelGGL(k_vec_rid, GRID1(ntot, 256), 0, st, ntot, sflag, scol, need, nc, runflag, runid, rid, rstart);
   hipLaunchKernelGGL(k_vec_cflags, GRID1(ntot, 256), 0, st, ntot, rid, rstart, slots, cflag);
   launch_scan(st, cflag, cid, tiles, ntot, total);
   hipLaunchKernelGGL(k_vec_cstart, GRID1(ntot, 256), 0, st, ntot, cflag, cid, cstart);

@@ -18,7 +18,8 @@ void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t 
                    uint32_t* sflag, Counters* C);
 void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
                    const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
-                   uint32_t* sflag, Counters* C, int lanes, bool validate_only = false);
+                   uint32_t* sflag, Counters* C, int lanes, bool validate_only = false,
+                   const int64_t* cstart = nullptr, const int32_t* rid = nullptr, int nchunks = 0);
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag);
 void launch_columns(hipStream_t st, const Problem* P, Block* B, int nblk, const Node* N, int64_t ntot,
                     const int32_t* sblk, const double* lo, const double* hi, double* val, int64_t* scol, bool multi);
@@ -36,9 +37,10 @@ void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, 
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
                   int32_t* snode, uint32_t* sflag, double* sgap);
 void launch_clear_active(hipStream_t st, int64_t ntot, uint32_t* sflag);
-void launch_vec_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, const int32_t* snode,
-                       int slots, int32_t* runflag, int32_t* runid, int32_t* tiles, int32_t* total, int32_t* rid,
-                       int64_t* rstart, int32_t* cflag, int32_t* cid, int64_t* cstart);
+void launch_node_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, const int64_t* scol, uint32_t need,
+                        bool need_col, const int32_t* snode, int slots, int32_t* runflag, int32_t* runid,
+                        int32_t* tiles, int32_t* total, int32_t* rid, int64_t* rstart, int32_t* cflag, int32_t* cid,
+                        int64_t* cstart);
 void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int64_t* cstart,
                     int nchunks, int64_t ntot, const int32_t* rid, const int32_t* sblk, const int32_t* snode,
                     const int64_t* scol, const double* lo, const double* hi, const double* sgap, const Rep* pool,
