@@ -24,6 +24,8 @@ constexpr double kPertScale = 4.0;     // root perturbation 4 eps u, u in [-1, 1
 constexpr int kMaxRqi = 5;              // Rayleigh-quotient solves per singleton (one more to repeat the best)
 constexpr int kMaxSweeps = 200;        // refinement sweeps per eigenvalue (cap)
 constexpr int kSeg = 8;                 // eigenvector solves: rows per recomputed segment
+constexpr int kCkptMinRun = 16;          // checkpointing eigenvector kernel: equal-node run length ...
+constexpr int kCkptMinN = 4096;          // ... and block order from which it is used
 
 // slot flags
 constexpr uint32_t F_NEEDS_REFINE = 1u;   // bracket must be (re)validated/refined
@@ -32,6 +34,7 @@ constexpr uint32_t F_ACTIVE = 4u;         // slot belongs to a node of the curre
 constexpr uint32_t F_RUNSTART = 8u;       // first index of a run (classification)
 constexpr uint32_t F_DONE = 16u;          // eigenvector written
 constexpr uint32_t F_ACCURATE = 32u;      // bracket validated and at full relative accuracy
+constexpr uint32_t F_CKPT = 64u;          // eigenvector by the checkpointing kernel (long runs, large blocks)
 
 struct Rep {
   double D, L, LD, LLD;

@@ -67,12 +67,16 @@ struct Workspace {
   std::mutex mu;
   DevBuf problems, poff, sprob, ds, es, flag, excl, tiles, total, bstart, sblk, blocks, goff, nodes, pool, gcnt, lo,
       hi, clo, chi, snode, sflag, scol, val, runflag, runid, runs, clusters, counters, vrid, cflag, cid, cstart,
-      scratch, bad, perm, tmp, sgap;
+      scratch, ckscratch, chunkrows, chunks, chunkoff, bad, perm, tmp, sgap;
+  // second stream (default priority) for the checkpointing eigenvector kernel,
+  // which runs beside the stored-vector kernel; fork and join events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t total_bytes() const {
     const DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                            &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
-                           &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &bad,
-                           &perm, &tmp, &sgap};
+                           &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &ckscratch,
+                           &chunkrows, &chunks, &chunkoff, &bad, &perm, &tmp, &sgap};
     size_t t = 0;
     for (auto* b : all) t += b->bytes;
     return t;
@@ -80,13 +84,18 @@ struct Workspace {
   void release() {
     DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                      &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
-                     &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &bad, &perm,
-                     &tmp, &sgap};
+                     &runid, &runs, &clusters, &counters, &vrid, &cflag, &cid, &cstart, &scratch, &ckscratch,
+                     &chunkrows, &chunks, &chunkoff, &bad, &perm, &tmp, &sgap};
     for (auto* b : all) {
       if (b->p) (void)hipFree(b->p);
       b->p = nullptr;
       b->bytes = 0;
     }
+    if (aux) (void)hipStreamDestroy(aux);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    aux = nullptr;
+    ev_fork = ev_join = nullptr;
   }
 };
 
@@ -365,12 +374,26 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                   P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
                   dC, lanes, false, P_<int64_t>(W.cstart), P_<int32_t>(W.vrid), nrchunks);
     prof.end();
-    // 8. eigenvectors of all singletons: one wavefront per chunk of up to
-    //    vec_wave_slots (32 by default) consecutive singletons of one node;
-    //    two checkpoint arrays of ceil(n / kSeg) x slots doubles per chunk
+    // 8. eigenvectors of all singletons.  Long runs of singletons of one node
+    //    in large blocks go to the checkpointing kernel (one node per
+    //    wavefront, representation staged through LDS, nothing of length n
+    //    stored per eigenvector); the rest to the stored-vector kernel (32
+    //    consecutive slots per wavefront, four work vectors in memory).  Both
+    //    compute the same values.  Eigenvectors per wavefront: tuning, 32 by
+    //    default.
     int vslots = tune.vec_wave_slots;
     if (vslots == 0) vslots = 32;
+    ENS(vrid, sizeof(int32_t) * ntot);
+    ENS(cflag, sizeof(int32_t) * ntot);
+    ENS(cid, sizeof(int32_t) * ntot);
+    ENS(cstart, sizeof(int64_t) * (ntot + 1));
     launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_SINGLETON, true,
+                       P_<int32_t>(W.snode), vslots, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
+                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
+                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
+    launch_mark_ckpt(st, ntot, dB, P_<int32_t>(W.sblk), P_<int32_t>(W.vrid), P_<int64_t>(W.runs), kCkptMinRun,
+                     kCkptMinN, P_<uint32_t>(W.sflag));
+    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_SINGLETON | F_CKPT, true,
                        P_<int32_t>(W.snode), vslots, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
                        P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
                        P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
@@ -380,18 +403,74 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     int64_t nmax_all = 1;
     for (auto& p : probs) nmax_all = std::max<int64_t>(nmax_all, p.n);
     const int64_t stride = 2 * (int64_t)vslots * ((nmax_all + kSeg - 1) / kSeg);
-    const size_t budget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
-    const int64_t cmax = std::max<int64_t>(1, (int64_t)(budget / (sizeof(double) * (size_t)stride)));
-    ENS(scratch, sizeof(double) * (size_t)(std::min<int64_t>(std::max(nchunks, 1), cmax) * stride));
-    for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
-      const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
-      prof.begin(MRRR_K_VECTORS);
-      launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot, P_<int32_t>(W.vrid),
-                     P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol), P_<double>(W.lo),
-                     P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds), P_<double>(W.scratch), stride, w,
-                     Z, dC, vslots);
-      prof.end();
+    // the whole eigenvector phase is timed as one launch on the caller's stream
+    prof.begin(MRRR_K_VECTORS);
+    bool forked = false;
+    if (nchunks > 0) {
+      const size_t budget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
+      const int64_t cmax = std::max<int64_t>(1, (int64_t)(budget / (sizeof(double) * (size_t)stride)));
+      ENS(ckscratch, sizeof(double) * (size_t)(std::min<int64_t>(nchunks, cmax) * stride));
+      if (!W.aux) HIP_TRY(hipStreamCreateWithFlags(&W.aux, hipStreamNonBlocking));
+      if (!W.ev_fork) HIP_TRY(hipEventCreateWithFlags(&W.ev_fork, hipEventDisableTiming));
+      if (!W.ev_join) HIP_TRY(hipEventCreateWithFlags(&W.ev_join, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(W.ev_fork, st));
+      HIP_TRY(hipStreamWaitEvent(W.aux, W.ev_fork, 0));
+      forked = true;
+      for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
+        const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
+        launch_vectors(W.aux, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot,
+                       P_<int32_t>(W.vrid), P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol),
+                       P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
+                       P_<double>(W.ckscratch), stride, w, Z, dC, vslots);
+      }
+      HIP_TRY(hipEventRecord(W.ev_join, W.aux));
     }
+    // the stored-vector kernel for the remaining singletons
+    const int64_t nch = (ntot + vslots - 1) / vslots;
+    ENS(chunkrows, sizeof(int32_t) * nch);
+    launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), vslots,
+                      P_<int32_t>(W.chunkrows));
+    std::vector<int32_t> rows(nch);
+    HIP_TRY(hipMemcpyAsync(rows.data(), W.chunkrows.p, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> act;
+    std::vector<int64_t> aoff;
+    int64_t maxper = 0;
+    for (int64_t c = 0; c < nch; ++c)
+      if (rows[c] > 0) {
+        act.push_back((int32_t)c);
+        maxper = std::max<int64_t>(maxper, 4 * vslots * (int64_t)rows[c]);
+      }
+    const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
+    ENS(chunks, sizeof(int32_t) * (act.size() + 1));
+    ENS(chunkoff, sizeof(int64_t) * (act.size() + 1));
+    size_t i0 = 0;
+    while (i0 < act.size()) {
+      // the largest run of chunks whose scratch fits the budget
+      size_t i1 = i0;
+      int64_t used = 0;
+      aoff.clear();
+      while (i1 < act.size()) {
+        const int64_t need = 4 * vslots * (int64_t)rows[act[i1]];
+        if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
+        aoff.push_back(used);
+        used += need;
+        ++i1;
+      }
+      ENS(scratch, sizeof(double) * (size_t)used);
+      HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data() + i0, sizeof(int32_t) * (i1 - i0), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * (i1 - i0), hipMemcpyHostToDevice, st));
+      launch_vectors_stored(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff),
+                            (int)(i1 - i0), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag),
+                            P_<int64_t>(W.scol), P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool,
+                            P_<double>(W.ds), P_<double>(W.scratch), w, Z, dC, vslots);
+      // the host vectors are read by the copies: wait for them (the other
+      // stream keeps running)
+      HIP_TRY(hipStreamSynchronize(st));
+      i0 = i1;
+    }
+    if (forked) HIP_TRY(hipStreamWaitEvent(st, W.ev_join, 0));
+    prof.end();
   }
   // 9. ascending order within each problem
   ENS(bad, sizeof(int32_t) * nprob);

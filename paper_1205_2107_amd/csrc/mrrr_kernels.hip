@@ -896,6 +896,7 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
 
 constexpr int kChildLevels = 8;
 constexpr int kChildCand = 2 * kChildLevels;
+constexpr int kChildMaskedFrom = 1024;  // clusters per launch from which k_child stores masked
 
 __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const double* __restrict__ lo,
                                      const double* __restrict__ hi, int cand, bool* valid) {
@@ -919,6 +920,12 @@ __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const 
   return side ? h0 + delta : l0 - delta;
 }
 
+// kMasked: rows are stored by the owning lanes under an execution mask (few
+// store lanes per instruction: cheaper when many wavefronts share the chip);
+// otherwise every lane issues buffer stores that the range check drops except
+// for the owner, which keeps the loop branch-free (faster for a lone
+// wavefront, whose LDS reads then batch across rows)
+template <bool kMasked>
 __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
                                               int node_base, const Cluster* __restrict__ clusters,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
@@ -961,18 +968,28 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
         r0 = raw_rsrc(reg0 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
         r1 = raw_rsrc(reg1 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
       },
-      [&](int, int j, double D, double L, double LD, double) {
+      [&](int i, int j, double D, double L, double LD, double) {
         const double dp = D + sv;
         gmax = fmax(gmax, fabs(dp));
         const double lp = LD * rcp_nr2(dp);
         const double ld = lp * dp;
         const double lld = ld * lp;
-        const uint32_t o0 = own0 ? (uint32_t)j * sizeof(Rep) : kDropOff;
-        const uint32_t o1 = own1 ? (uint32_t)j * sizeof(Rep) : kDropOff;
-        bstore2(r0, o0, dp, lp);
-        bstore2(r0, o0 + 16, ld, lld);
-        bstore2(r1, o1, dp, lp);
-        bstore2(r1, o1 + 16, ld, lld);
+        if (kMasked) {
+          if (own0 || own1) {
+            double* q = reinterpret_cast<double*>(own0 ? reg0 : reg1) + 4 * (int64_t)i;
+            q[0] = dp;
+            q[1] = lp;
+            q[2] = ld;
+            q[3] = lld;
+          }
+        } else {
+          const uint32_t o0 = own0 ? (uint32_t)j * sizeof(Rep) : kDropOff;
+          const uint32_t o1 = own1 ? (uint32_t)j * sizeof(Rep) : kDropOff;
+          bstore2(r0, o0, dp, lp);
+          bstore2(r0, o0 + 16, ld, lld);
+          bstore2(r1, o1, dp, lp);
+          bstore2(r1, o1 + 16, ld, lld);
+        }
         sv = fma(lp * L, sv, -sigma);
         fin = fin && isfinite(dp) && isfinite(lp);
       });
@@ -1049,12 +1066,16 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   staged_rows_g(
       Rd, n, n - 1, st,
       [&](int g0) { rq = raw_rsrc(Q + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep)); },
-      [&](int, int j, double D, double L, double LD, double) {
+      [&](int i, int j, double D, double L, double LD, double) {
         const double dp = D + sv;
         const double lp = LD * rcp_nr2(dp);
         const double ld = lp * dp;
         const double val = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
-        bstore1(rq, lane < 4 ? (uint32_t)(j * 4 + lane) * 8u : kDropOff, val);
+        if (kMasked) {
+          if (lane < 4) reinterpret_cast<double*>(Q)[4 * (int64_t)i + lane] = val;
+        } else {
+          bstore1(rq, lane < 4 ? (uint32_t)(j * 4 + lane) * 8u : kDropOff, val);
+        }
         sv = fma(lp * L, sv, -sg);
       });
   if (lane < 4) {
@@ -1350,8 +1371,8 @@ __device__ inline void staged_segments(const Rep* __restrict__ R, int n, int J, 
 //    (role 1).  Returns the last value (s_n or p_1).
 template <int kPairSlots, bool kMayGuard>
 __device__ inline double transform_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
-                                        double lam, double x0, double* __restrict__ SC, double* __restrict__ PC,
-                                        int c, double* __restrict__ lds) {
+                                        bool guard, double lam, double x0, double* __restrict__ SC,
+                                        double* __restrict__ PC, int c, double* __restrict__ lds) {
   const int nseg = (n + kSeg - 1) / kSeg;
   double x = x0;
   staged_segments<0, true>(
@@ -1363,7 +1384,7 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
           for (int u = 0; u < kSeg; ++u) {
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
-            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, true, w);
+            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
           }
         } else {
           // the last segment: no step at row n-1 and beyond
@@ -1372,7 +1393,7 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
             const int o = role ? kSeg - 1 - u : u;
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, true, w);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
             x = (k * kSeg + o <= n - 2) ? xn : x;
           }
         }
@@ -1386,9 +1407,10 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
 //    downward from PC (or from p_n) with gamma at every row.  Ties go to the
 //    smaller index.
 template <int kPairSlots, bool kMayGuard>
-__device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, double lam,
-                                  double xlast, const double* __restrict__ SC, const double* __restrict__ PC, int c,
-                                  double* __restrict__ lds, double& gmin_out, int& r_out) {
+__device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, bool guard,
+                                  double lam, double xlast, const double* __restrict__ SC,
+                                  const double* __restrict__ PC, int c, double* __restrict__ lds, double& gmin_out,
+                                  int& r_out) {
   const int nseg = (n + kSeg - 1) / kSeg;
   const int hs = nseg >> 1;
   const int cnt = role ? nseg - hs : hs;
@@ -1413,7 +1435,7 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
             sv[u] = x;
             double w;
             const double LD = rows[4 * u + 2];
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, x, lam, pivmin, true, w);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, x, lam, pivmin, guard, w);
             x = (!kEdge || k * kSeg + u <= n - 2) ? xn : x;
           }
           // p_i from the first row of the next segment (or p_n) downward
@@ -1427,7 +1449,7 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
             double w;
             const double D = rows[4 * u];
             const double xpn =
-                xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], xp, lam, pivmin, true, w);
+                xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], xp, lam, pivmin, guard, w);
             xp = (!kEdge || row < rs) ? xpn : xp;
             const double g = sv[u] + xp + lam;
             const bool take = (!kEdge || row <= rs) && isfinite(g) && fabs(g) <= fabs(gseg);
@@ -1570,26 +1592,27 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     //    non-finite value makes the wavefront repeat the pass with both, and
     //    the recomputations of this solve follow the pass that was kept.
     const double x0 = role ? xlast : -lam;
-    bool guarded = false;
+    bool any_guard = false, gl = false;  // the lane's transform needed the guarded form
     {
-      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, x0, SC, PC, c, lds);
-      if (__ballot(go && !isfinite(x)) != 0) {
-        guarded = true;
-        transform_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, x0, SC, PC, c, lds);
-      }
+      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, SC, PC, c, lds);
+      gl = go && !isfinite(x);
+      // the pair's two lanes share the guard: the checkpoints of both are recomputed
+      gl = gl || __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
+      any_guard = __ballot(gl) != 0;
+      if (any_guard) transform_pass<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, SC, PC, c, lds);
     }
     __syncthreads();  // checkpoints complete and visible to the partner lane
     // 2. twist index
     double gmin;
     int r;
-    if (guarded)
-      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, lds, gmin, r);
+    if (any_guard)
+      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, xlast, SC, PC, c, lds, gmin, r);
     else
-      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, lam, xlast, SC, PC, c, lds, gmin, r);
+      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, false, lam, xlast, SC, PC, c, lds, gmin, r);
     // 3. solve: ||z||^2 and the largest entry
     double nrm, zbest;
-    if (guarded)
-      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, true, lam, xlast, r, SC, PC, c, lds, nullptr, 1.0,
+    if (any_guard)
+      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, gl, lam, xlast, r, SC, PC, c, lds, nullptr, 1.0,
                                           nrm, zbest);
     else
       solve_pass<kPairSlots, false, false>(go, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, lds, nullptr,
@@ -1606,7 +1629,7 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     if (go) {
       rout = r;
       lam_last = lam;
-      g_last = guarded;
+      g_last = gl;
       rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
     }
   }
@@ -1723,6 +1746,396 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
     const int rqm = wave_max(V.rq);
     if (lane == 0) atomicAdd(&C->wave_solves, (unsigned long long)rqm);
   }
+}
+
+// ---- stored work vectors: the variant for small blocks and small nodes ----
+// Work vectors per wavefront: S, P, W0 (L+, then z above the twist), W1 (U-,
+// then z from the twist down), each [row][slots], written by the transforms
+// and read back by the twist scan, the solve and the Z write.  For blocks
+// whose work vectors stay in the caches this costs less than recomputing
+// segments, and a wavefront may mix nodes (32 consecutive slots).
+
+constexpr int kZRows = 32;      // rows per LDS transpose tile
+
+__device__ __forceinline__ int clamp_row(int i, int n) { return min(max(i, 0), n - 1); }
+
+// the three fields of a representation row the transforms use
+struct Row3 {
+  double D, LD, LLD;
+};
+__device__ __forceinline__ Row3 load_row3(const Rep* __restrict__ R, int i) {
+  Row3 r;
+  r.D = R[i].D;
+  r.LD = R[i].LD;
+  r.LLD = R[i].LLD;
+  return r;
+}
+
+constexpr int kHB = 8;  // steps per half of a double buffer
+
+// software pipeline over steps t = 0 .. T - 1 (T wave-uniform): the loads of
+// one half of kHB steps are issued while the other half is consumed, so every
+// value arrives kHB .. 2 kHB - 1 steps after its load was issued.  load(t)
+// must be in bounds for any t >= 0; step(t, v) sees steps in order.
+template <class Ld, class St>
+__device__ __forceinline__ void pipelined(int T, Ld&& load, St&& step) {
+  using V = decltype(load(0));
+  V a[kHB], b[kHB];
+#pragma unroll
+  for (int k = 0; k < kHB; ++k) a[k] = load(k);
+  for (int t0 = 0; t0 < T; t0 += 2 * kHB) {
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) b[k] = load(t0 + kHB + k);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) step(t0 + k, a[k]);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) a[k] = load(t0 + 2 * kHB + k);
+    ring_fence();
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) step(t0 + kHB + k, b[k]);
+    ring_fence();
+  }
+}
+
+struct Pair2 {
+  double s, p;
+};
+
+// one Rayleigh-quotient iteration sequence for the eigenvector of lane pair c;
+// role 0 = top-down / upward lane, role 1 = bottom-up / downward lane.  Work
+// vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = L+_i then z above the
+// twist, W1 = U-_i then z from the twist down.  Returns the twist index of the
+// last solve (z is in W0 for rows < r and in W1 for rows >= r).
+template <int kPairSlots>
+__device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restrict__ R, int n, int nmax, double pivmin,
+                               double* __restrict__ S, double* __restrict__ P, double* __restrict__ W0,
+                               double* __restrict__ W1, int c, VecState& V) {
+  bool conv = !solve;
+  bool last = false;
+  int rout = 0;
+  // wave-uniform trip counts
+  int T = n - 1;
+  for (int o = 32; o > 0; o >>= 1) T = max(T, __shfl_xor(T, o, 64));
+  double* const X = role ? P : S;    // this lane's transform variable
+  double* const Wr = role ? W1 : W0;  // this lane's quotients, then z
+  for (int it = 0; it <= kMaxRqi; ++it) {
+    const bool go = solve && !conv;
+    if (__ballot(go) == 0) break;
+    const double lam = V.lam;
+    // 1. the two transforms, concurrently; each step also stores the quotient
+    //    the solve will need (L+_i on the top lane, U-_i on the bottom lane)
+    double x;
+    if (role) {
+      x = R[n - 1].D - lam;
+      if (go) P[(int64_t)(n - 1) * kPairSlots + c] = x;
+    } else {
+      x = -lam;
+    }
+    {
+      // rows in two buffers of kHB: one is consumed while the other's loads
+      // are in flight (prefetch distance kHB .. 2 kHB - 1 steps)
+      // The first pass runs the fast form of the step; a lane that ends
+      // with a non-finite value (a zero or overflowing pivot) repeats its
+      // transform in the guarded form, the other lanes repeat theirs
+      // unchanged, so each eigenvector's values do not depend on its
+      // wavefront.
+      auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
+      const double x0 = x;
+      auto pass = [&](auto G, bool gl) {
+        constexpr bool kG = decltype(G)::value;
+        x = x0;
+        auto step = [&](int t, const Row3& rr) {
+          if (t < T && go && t < n - 1) {
+            const int row = role ? n - 2 - t : t;
+            const double b = role ? rr.LLD : rr.D;
+            const double f = role ? rr.D : rr.LLD;
+            // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
+            double w;
+            const double xn = xstep_bf<kG>(b, f, rr.LD, x, lam, pivmin, gl, w);
+            const int64_t o = (int64_t)row * kPairSlots + c;
+            X[o] = role ? xn : x;
+            Wr[o] = w;
+            x = xn;
+          }
+        };
+        pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
+      };
+      pass(std::false_type{}, false);
+      bool gl = go && !isfinite(x);
+      gl = gl || __shfl_xor(gl ? 1 : 0, 1, 64) != 0;  // both transforms of a pair in one form
+      if (__ballot(gl) != 0) pass(std::true_type{}, gl);
+    }
+    if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
+    __syncthreads();  // S and P complete and visible to the partner lane
+    // 2. twist index: lane 2c scans k < h, lane 2c+1 scans k >= h
+    const int h = n >> 1;
+    double gmin = INFINITY;
+    int r = -1;
+    {
+      const int kb = role ? h : 0;
+      const int kc = role ? n - h : h;
+      int T2 = kc;
+      for (int o = 32; o > 0; o >>= 1) T2 = max(T2, __shfl_xor(T2, o, 64));
+      pipelined(
+          T2,
+          [&](int t) {
+            const int64_t o = (int64_t)clamp_row(kb + t, n) * kPairSlots + c;
+            Pair2 v;
+            v.s = S[o];
+            v.p = P[o];
+            return v;
+          },
+          [&](int t, const Pair2& v) {
+            if (t < T2 && go && t < kc) {
+              const double g = v.s + v.p + lam;
+              if (isfinite(g) && fabs(g) < fabs(gmin)) {
+                gmin = g;
+                r = kb + t;
+              }
+            }
+          });
+      // the partner's candidate; ties go to the smaller index (the upper half)
+      const double go_g = __shfl_xor(gmin, 1, 64);
+      const int go_r = __shfl_xor(r, 1, 64);
+      const double gt = role ? go_g : gmin, gb = role ? gmin : go_g;
+      const int rt = role ? go_r : r, rb = role ? r : go_r;
+      const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
+      gmin = take_b ? gb : gt;
+      r = take_b ? rb : rt;
+      if (r < 0) {
+        r = 0;
+        gmin = 0.0;
+      }
+    }
+    // 3. solves outward from the twist: z_i = -L+_i z_{i+1} upward (lane 2c),
+    //    z_{i+1} = -U-_i z_i downward (lane 2c+1); where a z is zero the row
+    //    of L D L^T - lam I gives the next one from the one before.  Rows are
+    //    visited in a wave-uniform order per role (top lanes from the largest
+    //    twist index of the wave down, bottom lanes from the smallest up), each
+    //    lane active on its own side of its twist, so every access is one
+    //    coalesced row of the work vector.
+    double nrm = 0.0, zbest = 0.0;
+    {
+      if (go && role) {
+        nrm = 1.0;
+        zbest = 1.0;
+      }
+      int rmax = (go && !role) ? r : 0;        // top lanes: rows rmax-1 .. 0
+      int rmin = (go && role) ? r : INT_MAX;   // bottom lanes: rows rmin .. n-2
+      for (int o = 32; o > 0; o >>= 1) {
+        rmax = max(rmax, __shfl_xor(rmax, o, 64));
+        rmin = min(rmin, __shfl_xor(rmin, o, 64));
+      }
+      if (rmin == INT_MAX) rmin = 0;  // no lane iterating: nothing to visit
+      int nb = (go && role) ? n - 1 - rmin : 0;
+      for (int o = 32; o > 0; o >>= 1) nb = max(nb, __shfl_xor(nb, o, 64));
+      const int T3 = max(rmax, nb);
+      const int base = role ? rmin : rmax - 1;
+      const int dir = role ? 1 : -1;
+      double zc = 1.0, zp = 0.0;
+      pipelined(
+          T3, [&](int t) { return Wr[(int64_t)clamp_row(base + dir * t, n) * kPairSlots + c]; },
+          [&](int t, double w) {
+            const int row = base + dir * t;
+            const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
+            if (t < T3 && go && on) {
+              const bool first = role ? (row == r) : (row == r - 1);
+              double zn;
+              if (zc != 0.0 || first) {
+                zn = -w * zc;
+              } else if (zp != 0.0) {
+                const double ldi = R[row].LD;
+                const double ldn = R[row - dir].LD;
+                zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+              } else {
+                zn = 0.0;  // an underflowed tail stays zero
+              }
+              zn = isfinite(zn) ? zn : 0.0;
+              const int zrow = role ? row + 1 : row;
+              Wr[(int64_t)zrow * kPairSlots + c] = zn;
+              zp = zc;
+              zc = zn;
+              nrm += zn * zn;
+              // largest magnitude, ties to the smaller row
+              if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
+            }
+          });
+      if (go && role) W1[(int64_t)r * kPairSlots + c] = 1.0;
+      // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
+      const double nrm_o = __shfl_xor(nrm, 1, 64);
+      const double zb_o = __shfl_xor(zbest, 1, 64);
+      nrm += nrm_o;
+      const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
+      zbest = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+    }
+    __syncthreads();  // z complete before the next transform overwrites the work vectors
+    if (go) {
+      rout = r;
+      rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
+    }
+  }
+  if (solve && !conv) V.lam_out = V.lam;
+  return rout;
+}
+
+template <int kPairSlots>
+__global__ void __launch_bounds__(64) k_vectors_stored(
+    const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
+    const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
+    const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
+    const int64_t* __restrict__ scol, const double* __restrict__ lo_a, const double* __restrict__ hi_a,
+    const double* __restrict__ sgap, const Rep* __restrict__ pool, const double* __restrict__ ds,
+    double* __restrict__ scratch, double* __restrict__ w_out, double* __restrict__ Z, Counters* __restrict__ C) {
+  __shared__ double tile[kPairSlots][kZRows + 1];
+  __shared__ int64_t s_col[kPairSlots];
+  __shared__ int64_t s_zoff[kPairSlots];
+  __shared__ int s_n[kPairSlots];
+  __shared__ int64_t s_lrow0[kPairSlots];
+  __shared__ int64_t s_pn[kPairSlots];
+  const int lane = threadIdx.x;
+  const int c = lane >> 1;
+  const int role = lane & 1;
+  const int ci = blockIdx.x;
+  if (ci >= nchunks) return;
+  const int64_t chunk = chunks[ci];
+  const int64_t s = chunk * kPairSlots + c;
+  double* S = scratch + chunk_off[ci];
+  const bool lane_slot = c < kPairSlots;  // lanes beyond 2 * kPairSlots idle
+  bool act = false;
+  if (lane_slot && s < ntot) act = (sflag[s] & (F_SINGLETON | F_CKPT)) == F_SINGLETON && scol[s] >= 0;
+  const uint64_t am = __ballot(act);
+  if (am == 0) return;
+  const int64_t sf = __shfl(s, first_lane(am), 64);
+  const int64_t ss = act ? s : sf;  // idle lanes shadow a valid slot
+  const int64_t col = act ? scol[s] : -1;
+  const Block blk = B[sblk[ss]];
+  const Node nd = N[snode[ss]];
+  const int n = blk.n;
+  int nmax = act ? n : 0;
+  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+  double* Pv = S + (int64_t)nmax * kPairSlots;
+  double* W0 = Pv + (int64_t)nmax * kPairSlots;
+  double* W1 = W0 + (int64_t)nmax * kPairSlots;
+  const int cs = lane_slot ? c : 0;  // scratch column (idle lanes never store)
+  VecState V;
+  V.lo = lo_a[ss];
+  V.hi = hi_a[ss];
+  V.gap = sgap[ss];
+  V.resid = INFINITY;
+  V.stall = 0;
+  V.lam = 0.5 * (V.lo + V.hi);
+  V.best = V.lam;
+  V.lam_out = V.lam;
+  V.nrm = 1.0;
+  V.zmaxv = 1.0;
+  V.qsteps = 0;
+  V.rq = 0;
+  V.fallback = false;
+  const bool solve = act && n > 1;
+  int r = 0;
+  if (act && n == 1 && role) W1[c] = 1.0;
+  r = pair_rqi_stored<kPairSlots>(solve, role, pool + nd.rep, n, nmax, blk.pivmin, S, Pv, W0, W1, cs, V);
+  double scale = 1.0;
+  if (solve) {
+    scale = 1.0 / sqrt(V.nrm);
+    if (V.zmaxv < 0.0) scale = -scale;
+  }
+  // eigenvalue (once per pair)
+  if (act && !role) {
+    const Problem pr = P[blk.prob];
+    const double wv = (n == 1) ? ds[s] / pr.scale : (nd.acc + V.lam_out) / pr.scale;
+    w_out[pr.off + col] = wv;
+    s_col[c] = col;
+    s_zoff[c] = pr.zoff + col * pr.ldz;
+    s_n[c] = n;
+    s_lrow0[c] = blk.lrow0;
+    s_pn[c] = pr.n;
+  } else if (!role && lane_slot) {
+    s_col[c] = -1;
+    s_n[c] = 0;
+    s_pn[c] = 0;
+  }
+  __syncthreads();
+  if (Z != nullptr) {
+    // z * scale into column-major Z through an LDS transpose: each pass stages
+    // 32 rows x 32 columns (lane 2c rows 0-15 of column c, lane 2c+1 rows
+    // 16-31), then every column gets one contiguous 256-byte segment
+    for (int r0 = 0; r0 < nmax; r0 += kZRows) {
+      double v[kZRows / 2];
+#pragma unroll
+      for (int k = 0; k < kZRows / 2; ++k) {
+        const int row = r0 + role * (kZRows / 2) + k;
+        const double* src = (row < r) ? W0 : W1;
+        v[k] = (row < nmax) ? src[(int64_t)row * kPairSlots + cs] : 0.0;
+      }
+      if (lane_slot) {
+#pragma unroll
+        for (int k = 0; k < kZRows / 2; ++k) {
+          const int row = r0 + role * (kZRows / 2) + k;
+          tile[c][role * (kZRows / 2) + k] = (act && row < n) ? v[k] * scale : 0.0;
+        }
+      }
+      __syncthreads();
+      const int rr = lane & (kZRows - 1);
+      for (int cg = 0; cg < kPairSlots; cg += 2) {
+        const int cl = cg + (lane >> 5);
+        const int i = r0 + rr;
+        if (s_col[cl] >= 0 && i < s_n[cl]) Z[s_zoff[cl] + s_lrow0[cl] + i] = tile[cl][rr];
+      }
+      __syncthreads();
+    }
+    // rows of the problem outside the block are exact zeros
+    for (int cl = 0; cl < kPairSlots; ++cl) {
+      if (s_col[cl] < 0) continue;
+      const int64_t pn = s_pn[cl];
+      const int64_t r0 = s_lrow0[cl];
+      const int64_t r1 = r0 + s_n[cl];
+      if (r0 == 0 && r1 == pn) continue;
+      for (int64_t i = lane; i < pn; i += 64)
+        if (i < r0 || i >= r1) Z[s_zoff[cl] + i] = 0.0;
+    }
+  }
+  if (act && !role) {
+    atomicAdd(&C->qds_steps, (unsigned long long)V.qsteps);
+    atomicAdd(&C->vec_rows, (unsigned long long)(V.qsteps / 4));
+    if (Z != nullptr) atomicAdd(&C->z_entries, (unsigned long long)s_pn[c]);
+    atomicAdd(&C->rqi, (unsigned long long)V.rq);
+    atomicAdd(&C->singletons, 1ull);
+    if (V.fallback) atomicAdd(&C->fallbacks, 1ull);
+  }
+  {
+    int rqm = V.rq;
+    for (int o = 32; o > 0; o >>= 1) rqm = max(rqm, __shfl_xor(rqm, o, 64));
+    if (lane == 0) atomicAdd(&C->wave_solves, (unsigned long long)rqm);
+  }
+}
+
+// scratch rows each chunk of `slots` consecutive slots needs for the stored
+// variant (0: no singleton of that variant to compute)
+__global__ void k_chunk_rows(const Block* __restrict__ B, int64_t ntot, const int32_t* __restrict__ sblk,
+                             const uint32_t* __restrict__ sflag, const int64_t* __restrict__ scol, int slots,
+                             int32_t* __restrict__ rows) {
+  const int64_t s = (int64_t)blockIdx.x * slots + (threadIdx.x & (slots - 1));
+  int v = 0;
+  if ((int)threadIdx.x < slots && s < ntot && (sflag[s] & (F_SINGLETON | F_CKPT)) == F_SINGLETON && scol[s] >= 0)
+    v = B[sblk[s]].n;
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if (threadIdx.x == 0) rows[blockIdx.x] = v;
+}
+
+// singletons in runs of at least min_run equal-node slots of blocks of order
+// min_n or more go to the checkpointing kernel (rid, rstart: equal-node runs)
+__global__ void k_mark_ckpt(int64_t ntot, const Block* __restrict__ B, const int32_t* __restrict__ sblk,
+                            const int32_t* __restrict__ rid, const int64_t* __restrict__ rstart, int min_run,
+                            int min_n, uint32_t* __restrict__ sflag) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntot) return;
+  const int q = rid[s];
+  if (q < 0) return;
+  const int64_t t = rstart[q] + min_run - 1;
+  if (t < ntot && rid[t] == q && B[sblk[s]].n >= min_n) sflag[s] |= F_CKPT;
 }
 
 // chunks of slots of one node: runs of consecutive slots that have every
@@ -1960,8 +2373,14 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C) {
-  hipLaunchKernelGGL(k_child, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo,
-                     hi, pool, pool_cap, C);
+  // a lone or few wavefronts are latency-bound (branch-free stores), a full
+  // chip is issue-bound (masked stores)
+  if (nclusters >= kChildMaskedFrom)
+    hipLaunchKernelGGL(k_child<true>, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo, hi,
+                       pool, pool_cap, C);
+  else
+    hipLaunchKernelGGL(k_child<false>, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo,
+                       hi, pool, pool_cap, C);
 }
 
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
@@ -2004,6 +2423,37 @@ void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node
   else
     MRRR_VEC(32);
 #undef MRRR_VEC
+}
+
+void launch_vectors_stored(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
+                           const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk,
+                           const int32_t* snode, const uint32_t* sflag, const int64_t* scol, const double* lo,
+                           const double* hi, const double* sgap, const Rep* pool, const double* ds, double* scratch,
+                           double* w, double* Z, Counters* C, int slots) {
+  if (nchunks == 0) return;
+#define MRRR_VEC(SL)                                                                                              \
+  hipLaunchKernelGGL(k_vectors_stored<SL>, dim3(nchunks), dim3(64), 0, st, P, B, N, chunks, chunk_off, nchunks, ntot, \
+                     sblk, snode, sflag, scol, lo, hi, sgap, pool, ds, scratch, w, Z, C)
+  if (slots == 8)
+    MRRR_VEC(8);
+  else if (slots == 16)
+    MRRR_VEC(16);
+  else
+    MRRR_VEC(32);
+#undef MRRR_VEC
+}
+
+void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
+                       const int64_t* scol, int slots, int32_t* rows) {
+  const int64_t nch = (ntot + slots - 1) / slots;
+  if (nch == 0) return;
+  hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)nch), dim3(64), 0, st, B, ntot, sblk, sflag, scol, slots, rows);
+}
+
+void launch_mark_ckpt(hipStream_t st, int64_t ntot, const Block* B, const int32_t* sblk, const int32_t* rid,
+                      const int64_t* rstart, int min_run, int min_n, uint32_t* sflag) {
+  if (ntot == 0) return;
+  hipLaunchKernelGGL(k_mark_ckpt, GRID1(ntot, 256), 0, st, ntot, B, sblk, rid, rstart, min_run, min_n, sflag);
 }
 
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C) {

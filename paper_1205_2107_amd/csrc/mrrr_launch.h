@@ -45,6 +45,15 @@ void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node
                     int nchunks, int64_t ntot, const int32_t* rid, const int32_t* sblk, const int32_t* snode,
                     const int64_t* scol, const double* lo, const double* hi, const double* sgap, const Rep* pool,
                     const double* ds, double* scratch, int64_t stride, double* w, double* Z, Counters* C, int slots);
+void launch_vectors_stored(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int32_t* chunks,
+                           const int64_t* chunk_off, int nchunks, int64_t ntot, const int32_t* sblk,
+                           const int32_t* snode, const uint32_t* sflag, const int64_t* scol, const double* lo,
+                           const double* hi, const double* sgap, const Rep* pool, const double* ds, double* scratch,
+                           double* w, double* Z, Counters* C, int slots);
+void launch_chunk_rows(hipStream_t st, const Block* B, int64_t ntot, const int32_t* sblk, const uint32_t* sflag,
+                       const int64_t* scol, int slots, int32_t* rows);
+void launch_mark_ckpt(hipStream_t st, int64_t ntot, const Block* B, const int32_t* sblk, const int32_t* rid,
+                      const int64_t* rstart, int min_run, int min_n, uint32_t* sflag);
 void launch_check_sorted(hipStream_t st, const Problem* P, int nprob, const double* w, int32_t* bad, Counters* C);
 void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t* bad, double* w, int64_t* perm,
                      double* tmp, double* Z);
