@@ -61,7 +61,14 @@ def cpu_baseline(n):
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1205_2107_amd", "csrc", "mrrr_kernels.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_vectors_traffic_n20000.md")
+# kernel symbol per profiled category (the traffic summary under profiles/ is
+# named for the symbol and the workload)
+KERNEL_SYMBOL = {"grid": "k_grid", "refine": "k_refine", "child": "k_child", "vectors": "k_vectors_stored",
+                 "vectors_ckpt": "k_vectors"}
+
+
+def traffic_summary(kernel):
+    return os.path.join(ROOT, "profiles", f"{KERNEL_SYMBOL.get(kernel, kernel)}_traffic_n20000.md")
 
 
 def kernel_source_sha():
@@ -73,10 +80,11 @@ def kernel_source_sha():
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed PMC summary, or None
     when there is none or the kernel source changed since it was taken."""
-    if kernel != "vectors" or not os.path.exists(TRAFFIC_SUMMARY):
+    path = traffic_summary(kernel)
+    if not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
@@ -91,12 +99,13 @@ def measured_traffic(kernel):
 
 def roofline(prof):
     """dominant kernel by event time; ALU-bound kernels against the FP64 vector
-    peak, the eigenvector kernel against HBM bandwidth"""
+    peak, the eigenvector kernels (whose algorithmic bytes are the Z entries
+    they write) against HBM bandwidth"""
     name = max(prof, key=lambda k: prof[k]["ms"])
     p = prof[name]
-    out = {"kernel": name, "launches": p["launches"], "avg_ms": p["ms"] / max(p["launches"], 1),
-           "traffic": measured_traffic(name)}
-    if name == "vectors":
+    out = {"kernel": name, "symbol": KERNEL_SYMBOL.get(name, name), "launches": p["launches"],
+           "avg_ms": p["ms"] / max(p["launches"], 1), "traffic": measured_traffic(name)}
+    if name in ("vectors", "vectors_ckpt"):
         ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS})

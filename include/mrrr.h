@@ -169,21 +169,28 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
                           void* stream);
 
 /* Kernel timing.  While enabled, the solve entry points record HIP events on
- * the caller's stream around every launch of their main kernels and accumulate
- * the elapsed times and the algorithmic work of those launches:
+ * the stream each of their main kernels runs on (the caller's stream, or for
+ * MRRR_K_VECTORS_CKPT the library's second stream, joined to the caller's)
+ * around every launch and accumulate the elapsed times and the algorithmic
+ * work of those launches:
  *   MRRR_K_GRID     Sturm-count grid        work = 4 flops per row step
  *   MRRR_K_REFINE   bisection/Newton        work = 4 flops per row step
  *   MRRR_K_CHILD    child representations   work = 5 flops per row step
- *   MRRR_K_VECTORS  twisted factorizations  work = 15 flops per row per
- *                   iteration; bytes = 8 per eigenvector entry written
+ *   MRRR_K_VECTORS  twisted factorizations, stored-work-vector kernel:
+ *                   work = 15 flops per row per iteration; bytes = 8 per
+ *                   eigenvector entry written
  *   MRRR_K_BACKWARD both backward GEMMs     work = 2 n^3 flops each
+ *   MRRR_K_VECTORS_CKPT  twisted factorizations, checkpointing kernel (long
+ *                   runs of one node's singletons in large blocks); work and
+ *                   bytes counted as for MRRR_K_VECTORS
  * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
 #define MRRR_K_GRID 0
 #define MRRR_K_REFINE 1
 #define MRRR_K_CHILD 2
 #define MRRR_K_VECTORS 3
 #define MRRR_K_BACKWARD 4
-#define MRRR_K_COUNT 5
+#define MRRR_K_VECTORS_CKPT 5
+#define MRRR_K_COUNT 6
 
 typedef struct {
   int64_t launches;

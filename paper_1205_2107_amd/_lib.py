@@ -14,7 +14,7 @@ COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singl
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string")
-KERNELS = ("grid", "refine", "child", "vectors", "backward")
+KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt")
 
 
 class MrrrRange(ctypes.Structure):

@@ -113,6 +113,8 @@ struct Counters {
   int32_t ambiguous;               // classifications that need refined brackets
   int32_t pad2;
   unsigned long long wave_solves;  // twisted-factorization rounds summed over wavefronts
+  unsigned long long ckpt_vec_rows;   // vec_rows of the checkpointing eigenvector kernel
+  unsigned long long ckpt_z_entries;  // z_entries of the checkpointing eigenvector kernel
 };
 
 // ---------------------------------------------------------------------------

@@ -403,29 +403,10 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     int64_t nmax_all = 1;
     for (auto& p : probs) nmax_all = std::max<int64_t>(nmax_all, p.n);
     const int64_t stride = 2 * (int64_t)vslots * ((nmax_all + kSeg - 1) / kSeg);
-    // the whole eigenvector phase is timed as one launch on the caller's stream
-    prof.begin(MRRR_K_VECTORS);
-    bool forked = false;
-    if (nchunks > 0) {
-      const size_t budget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
-      const int64_t cmax = std::max<int64_t>(1, (int64_t)(budget / (sizeof(double) * (size_t)stride)));
-      ENS(ckscratch, sizeof(double) * (size_t)(std::min<int64_t>(nchunks, cmax) * stride));
-      if (!W.aux) HIP_TRY(hipStreamCreateWithFlags(&W.aux, hipStreamNonBlocking));
-      if (!W.ev_fork) HIP_TRY(hipEventCreateWithFlags(&W.ev_fork, hipEventDisableTiming));
-      if (!W.ev_join) HIP_TRY(hipEventCreateWithFlags(&W.ev_join, hipEventDisableTiming));
-      HIP_TRY(hipEventRecord(W.ev_fork, st));
-      HIP_TRY(hipStreamWaitEvent(W.aux, W.ev_fork, 0));
-      forked = true;
-      for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
-        const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
-        launch_vectors(W.aux, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot,
-                       P_<int32_t>(W.vrid), P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol),
-                       P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
-                       P_<double>(W.ckscratch), stride, w, Z, dC, vslots);
-      }
-      HIP_TRY(hipEventRecord(W.ev_join, W.aux));
-    }
-    // the stored-vector kernel for the remaining singletons
+    // the stored-vector kernel's chunks (32 consecutive slots, scratch sized
+    // by their largest block), planned and uploaded before either kernel
+    // starts: a transfer queued while the checkpointing kernel fills the chip
+    // would wait for free compute units
     const int64_t nch = (ntot + vslots - 1) / vslots;
     ENS(chunkrows, sizeof(int32_t) * nch);
     launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), vslots,
@@ -434,43 +415,70 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     HIP_TRY(hipMemcpyAsync(rows.data(), W.chunkrows.p, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<int32_t> act;
-    std::vector<int64_t> aoff;
     int64_t maxper = 0;
     for (int64_t c = 0; c < nch; ++c)
       if (rows[c] > 0) {
         act.push_back((int32_t)c);
         maxper = std::max<int64_t>(maxper, 4 * vslots * (int64_t)rows[c]);
       }
+    // batches of chunks whose scratch fits the budget; offsets relative to
+    // the scratch base, which every batch reuses
     const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
+    std::vector<int64_t> aoff(act.size());
+    std::vector<size_t> bstart_h{0};
+    int64_t used = 0, used_max = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      const int64_t need = 4 * vslots * (int64_t)rows[act[i]];
+      if ((size_t)(used + need) * sizeof(double) > budget && i > bstart_h.back()) {
+        bstart_h.push_back(i);
+        used = 0;
+      }
+      aoff[i] = used;
+      used += need;
+      used_max = std::max(used_max, used);
+    }
+    bstart_h.push_back(act.size());
     ENS(chunks, sizeof(int32_t) * (act.size() + 1));
     ENS(chunkoff, sizeof(int64_t) * (act.size() + 1));
-    size_t i0 = 0;
-    while (i0 < act.size()) {
-      // the largest run of chunks whose scratch fits the budget
-      size_t i1 = i0;
-      int64_t used = 0;
-      aoff.clear();
-      while (i1 < act.size()) {
-        const int64_t need = 4 * vslots * (int64_t)rows[act[i1]];
-        if ((size_t)(used + need) * sizeof(double) > budget && i1 > i0) break;
-        aoff.push_back(used);
-        used += need;
-        ++i1;
+    if (!act.empty()) {
+      ENS(scratch, sizeof(double) * (size_t)used_max);
+      HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data(), sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * act.size(), hipMemcpyHostToDevice, st));
+    }
+    const size_t ckbudget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
+    const int64_t cmax = std::max<int64_t>(1, (int64_t)(ckbudget / (sizeof(double) * (size_t)stride)));
+    if (nchunks > 0) ENS(ckscratch, sizeof(double) * (size_t)(std::min<int64_t>(nchunks, cmax) * stride));
+    HIP_TRY(hipStreamSynchronize(st));  // the uploads have read the host vectors
+    bool forked = false;
+    if (nchunks > 0) {
+      if (!W.aux) HIP_TRY(hipStreamCreateWithFlags(&W.aux, hipStreamNonBlocking));
+      if (!W.ev_fork) HIP_TRY(hipEventCreateWithFlags(&W.ev_fork, hipEventDisableTiming));
+      if (!W.ev_join) HIP_TRY(hipEventCreateWithFlags(&W.ev_join, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(W.ev_fork, st));
+      HIP_TRY(hipStreamWaitEvent(W.aux, W.ev_fork, 0));
+      forked = true;
+      prof.begin_on(MRRR_K_VECTORS_CKPT, W.aux);
+      for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
+        const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
+        launch_vectors(W.aux, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot,
+                       P_<int32_t>(W.vrid), P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol),
+                       P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds),
+                       P_<double>(W.ckscratch), stride, w, Z, dC, vslots);
       }
-      ENS(scratch, sizeof(double) * (size_t)used);
-      HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data() + i0, sizeof(int32_t) * (i1 - i0), hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * (i1 - i0), hipMemcpyHostToDevice, st));
-      launch_vectors_stored(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks), P_<int64_t>(W.chunkoff),
+      prof.end_on(W.aux);
+      HIP_TRY(hipEventRecord(W.ev_join, W.aux));
+    }
+    for (size_t bi = 0; bi + 1 < bstart_h.size(); ++bi) {
+      const size_t i0 = bstart_h[bi], i1 = bstart_h[bi + 1];
+      if (i1 == i0) continue;
+      prof.begin(MRRR_K_VECTORS);
+      launch_vectors_stored(st, dP, dB, P_<Node>(W.nodes), P_<int32_t>(W.chunks) + i0, P_<int64_t>(W.chunkoff) + i0,
                             (int)(i1 - i0), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<uint32_t>(W.sflag),
                             P_<int64_t>(W.scol), P_<double>(W.lo), P_<double>(W.hi), P_<double>(W.sgap), dpool,
                             P_<double>(W.ds), P_<double>(W.scratch), w, Z, dC, vslots);
-      // the host vectors are read by the copies: wait for them (the other
-      // stream keeps running)
-      HIP_TRY(hipStreamSynchronize(st));
-      i0 = i1;
+      prof.end();
     }
     if (forked) HIP_TRY(hipStreamWaitEvent(st, W.ev_join, 0));
-    prof.end();
   }
   // 9. ascending order within each problem
   ENS(bad, sizeof(int32_t) * nprob);
@@ -539,10 +547,13 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     }
   }
   if (prof.on) {
+    const double vr = (double)(hc.vec_rows - hc.ckpt_vec_rows), ze = (double)(hc.z_entries - hc.ckpt_z_entries);
     const double work[MRRR_K_COUNT] = {grid_work, 4.0 * (double)hc.sturm_steps, 5.0 * (double)hc.child_steps,
-                                       15.0 * (double)hc.vec_rows, 0.0};
-    const double bytes[MRRR_K_COUNT] = {0.0, 0.0, 32.0 * (double)hc.child_steps, 8.0 * (double)hc.z_entries, 0.0};
-    for (int k = 0; k < MRRR_K_BACKWARD; ++k) {
+                                       15.0 * vr, 0.0, 15.0 * (double)hc.ckpt_vec_rows};
+    const double bytes[MRRR_K_COUNT] = {0.0, 0.0, 32.0 * (double)hc.child_steps, 8.0 * ze, 0.0,
+                                        8.0 * (double)hc.ckpt_z_entries};
+    for (int k = 0; k < MRRR_K_COUNT; ++k) {
+      if (k == MRRR_K_BACKWARD) continue;
       double ms;
       int64_t l;
       prof.total(k, &ms, &l);

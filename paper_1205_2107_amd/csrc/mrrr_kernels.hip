@@ -1737,7 +1737,11 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   if (act && !role) {
     atomicAdd(&C->qds_steps, (unsigned long long)V.qsteps);
     atomicAdd(&C->vec_rows, (unsigned long long)(V.qsteps / 4));
-    if (Z != nullptr) atomicAdd(&C->z_entries, (unsigned long long)s_pn[c]);
+    atomicAdd(&C->ckpt_vec_rows, (unsigned long long)(V.qsteps / 4));
+    if (Z != nullptr) {
+      atomicAdd(&C->z_entries, (unsigned long long)s_pn[c]);
+      atomicAdd(&C->ckpt_z_entries, (unsigned long long)s_pn[c]);
+    }
     atomicAdd(&C->rqi, (unsigned long long)V.rq);
     atomicAdd(&C->singletons, 1ull);
     if (V.fallback) atomicAdd(&C->fallbacks, 1ull);

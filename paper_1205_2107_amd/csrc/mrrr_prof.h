@@ -36,6 +36,19 @@ struct ProfEvents {
     (void)hipEventRecord(cur.b, st);
     recs.push_back(cur);
   }
+  // the same around launches on another stream s
+  void begin_on(int kind, hipStream_t s) {
+    hipStream_t keep = st;
+    st = s;
+    begin(kind);
+    st = keep;
+  }
+  void end_on(hipStream_t s) {
+    hipStream_t keep = st;
+    st = s;
+    end();
+    st = keep;
+  }
   // total milliseconds and launches of one kind
   void total(int kind, double* ms, int64_t* launches) {
     *ms = 0.0;
