@@ -290,6 +290,8 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   } else {
     // 6-7. representation tree, level by level
     int node_base = nblk;
+    int64_t nmax_prob = 1;
+    for (auto& p : probs) nmax_prob = std::max<int64_t>(nmax_prob, p.n);
     int max_clusters = (int)std::min<int64_t>(ntot / 2 + 1, INT32_MAX / 2);
     ENS(clusters, sizeof(Cluster) * (size_t)max_clusters);
     for (int level = 0;; ++level) {
@@ -326,9 +328,12 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       rep->levels = level + 1;
       const int ncl = std::min(hc.nclusters, max_clusters);
       if (ncl == 0) break;
-      // capacity for the new nodes and two child-sized regions per cluster
+      // capacity for the new nodes and the speculative child regions of every
+      // cluster (two with masked stores, four in the branch-free form)
       if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
-      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + 2 * (size_t)hc.cluster_rows;
+      const bool masked = ncl >= kChildMaskedFrom || nmax_prob >= kChildFewMaxN;
+      const size_t spec = masked ? kChildSpecMany : kChildSpecFew;
+      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + spec * (size_t)hc.cluster_rows;
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
         if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
         dpool = P_<Rep>(W.pool);
@@ -342,7 +347,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       }
       prof.begin(MRRR_K_CHILD);
       launch_child(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<double>(W.lo),
-                   P_<double>(W.hi), dpool, pool_cap, dC);
+                   P_<double>(W.hi), dpool, pool_cap, dC, masked);
       prof.end();
       launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
                    P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),

@@ -896,7 +896,6 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
 
 constexpr int kChildLevels = 8;
 constexpr int kChildCand = 2 * kChildLevels;
-constexpr int kChildMaskedFrom = 1024;  // clusters per launch from which k_child stores masked
 
 __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const double* __restrict__ lo,
                                      const double* __restrict__ hi, int cand, bool* valid) {
@@ -920,11 +919,15 @@ __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const 
   return side ? h0 + delta : l0 - delta;
 }
 
-// kMasked: rows are stored by the owning lanes under an execution mask (few
-// store lanes per instruction: cheaper when many wavefronts share the chip);
-// otherwise every lane issues buffer stores that the range check drops except
-// for the owner, which keeps the loop branch-free (faster for a lone
-// wavefront, whose LDS reads then batch across rows)
+// kMasked: the two closest candidates store their rows, each by its owning
+// lane under an execution mask (few store lanes per instruction: cheaper when
+// many wavefronts share the chip).  Otherwise the four closest candidates
+// (levels 0 and 1 at both ends) store theirs through one buffer resource
+// whose range check drops the other lanes' stores, which keeps the loop
+// branch-free (faster for a lone wavefront, whose LDS reads then batch across
+// rows) and saves the second pass when a level-1 candidate wins; that form
+// needs 3 n rows of 32 bytes to stay below 2^31 bytes (the host picks the
+// masked form for blocks of 2^24 rows or more).
 template <bool kMasked>
 __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
                                               int node_base, const Cluster* __restrict__ clusters,
@@ -939,12 +942,13 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   const Block blk = B[par.blk];
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
   const double* Rd = reinterpret_cast<const double*>(pool + par.rep);
-  // two child-sized regions: the closest candidates at the left and right end
-  // (lanes 0, 1) store their rows while pass 1 runs; usually one of them wins
+  // child-sized regions for the closest candidates (lanes 0 .. kSpec-1), which
+  // store their rows while pass 1 runs; usually one of them wins
+  constexpr int kSpec = kMasked ? kChildSpecMany : kChildSpecFew;
   long long base = -1;
   if (lane == 0) {
-    base = (long long)atomicAdd(&C->pool_used, 2ull * (unsigned long long)n);
-    if ((unsigned long long)base + 2ull * (unsigned long long)n > pool_cap) {
+    base = (long long)atomicAdd(&C->pool_used, (unsigned long long)kSpec * (unsigned long long)n);
+    if ((unsigned long long)base + (unsigned long long)kSpec * (unsigned long long)n > pool_cap) {
       set_status(C, 3);
       base = -1;
     }
@@ -953,21 +957,21 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   bool valid = false;
   double sigma = 0.0;
   if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
-  // the two speculative regions, stored through buffer resources rebased at
-  // every group (each row's store lands in the owning lane's region only)
+  // the speculative regions: region k holds candidate k's rows; without the
+  // mask one buffer resource, rebased at every group, spans all of them
   char* const reg0 = reinterpret_cast<char*>(pool + (base >= 0 ? base : 0));
   char* const reg1 = reg0 + (int64_t)n * sizeof(Rep);
   const bool own0 = base >= 0 && lane == 0, own1 = base >= 0 && lane == 1;
+  const bool own = base >= 0 && lane < kSpec;
+  const uint32_t regoff = (uint32_t)(lane < kSpec ? lane : 0) * (uint32_t)n * (uint32_t)sizeof(Rep);
+  const int span = (kSpec - 1) * n * (int)sizeof(Rep) + kSG * (int)sizeof(Rep);
   // pass 1: growth of every candidate (rows 0 .. n-2; the last row has no L)
   double sv = -sigma, gmax = 0.0;
   bool fin = true;
-  __amdgpu_buffer_rsrc_t r0 = raw_rsrc(reg0, 0), r1 = raw_rsrc(reg1, 0);
+  __amdgpu_buffer_rsrc_t r0 = raw_rsrc(reg0, 0);
   staged_rows_g(
       Rd, n, n - 1, st,
-      [&](int g0) {
-        r0 = raw_rsrc(reg0 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
-        r1 = raw_rsrc(reg1 + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep));
-      },
+      [&](int g0) { r0 = raw_rsrc(reg0 + (int64_t)g0 * sizeof(Rep), kMasked ? 0 : span); },
       [&](int i, int j, double D, double L, double LD, double) {
         const double dp = D + sv;
         gmax = fmax(gmax, fabs(dp));
@@ -983,12 +987,9 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
             q[3] = lld;
           }
         } else {
-          const uint32_t o0 = own0 ? (uint32_t)j * sizeof(Rep) : kDropOff;
-          const uint32_t o1 = own1 ? (uint32_t)j * sizeof(Rep) : kDropOff;
-          bstore2(r0, o0, dp, lp);
-          bstore2(r0, o0 + 16, ld, lld);
-          bstore2(r1, o1, dp, lp);
-          bstore2(r1, o1 + 16, ld, lld);
+          const uint32_t o = own ? regoff + (uint32_t)j * sizeof(Rep) : kDropOff;
+          bstore2(r0, o, dp, lp);
+          bstore2(r0, o + 16, ld, lld);
         }
         sv = fma(lp * L, sv, -sigma);
         fin = fin && isfinite(dp) && isfinite(lp);
@@ -997,8 +998,8 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
     const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
     gmax = fmax(gmax, fabs(dp));
     fin = fin && isfinite(dp);
-    if (own0 || own1) {
-      double* q = reinterpret_cast<double*>(own0 ? reg0 : reg1) + 4 * (int64_t)(n - 1);
+    if (own) {
+      double* q = reinterpret_cast<double*>(reg0 + (int64_t)lane * n * sizeof(Rep)) + 4 * (int64_t)(n - 1);
       q[0] = dp;
       q[1] = 0.0;
       q[2] = 0.0;
@@ -1025,7 +1026,8 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
         pick = k;
       }
   }
-  const long long off = uniform_ll((pick < 0 || base < 0) ? -1 : base + (pick < 2 ? pick : 0) * (long long)n);
+  const long long off =
+      uniform_ll((pick < 0 || base < 0) ? -1 : base + (pick < kSpec ? pick : 0) * (long long)n);
   bool v;
   const double sg = (pick >= 0) ? child_sigma(cl, blk, lo, hi, pick, &v) : 0.0;
   if (lane == 0) {
@@ -1057,7 +1059,7 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
     }
     N[node_base + c] = nd;
   }
-  if (off < 0 || pick < 2) return;
+  if (off < 0 || pick < kSpec) return;
   // pass 2 (a farther candidate won): every lane repeats its transform (the
   // staging needs the whole wavefront); lanes 0..3 store field q of each row
   char* const Q = reinterpret_cast<char*>(pool + off);
@@ -2376,10 +2378,11 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
 }
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
-                  const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C) {
+                  const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
+                  bool masked) {
   // a lone or few wavefronts are latency-bound (branch-free stores), a full
   // chip is issue-bound (masked stores)
-  if (nclusters >= kChildMaskedFrom)
+  if (masked)
     hipLaunchKernelGGL(k_child<true>, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo, hi,
                        pool, pool_cap, C);
   else

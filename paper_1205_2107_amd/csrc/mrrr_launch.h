@@ -32,7 +32,8 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
                      const int64_t* scol, uint32_t* sflag, double* sgap, Cluster* clusters, int max_clusters,
                      Counters* C);
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
-                  const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C);
+                  const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
+                  bool masked);
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
                   int32_t* snode, uint32_t* sflag, double* sgap);
