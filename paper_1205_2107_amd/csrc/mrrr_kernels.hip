@@ -1987,7 +1987,7 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
 }
 
 template <int kPairSlots>
-__global__ void __launch_bounds__(64) k_vectors_stored(
+__global__ void __launch_bounds__(64, 2) k_vectors_stored(
     const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
     const int32_t* __restrict__ chunks, const int64_t* __restrict__ chunk_off, int nchunks, int64_t ntot,
     const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const uint32_t* __restrict__ sflag,
