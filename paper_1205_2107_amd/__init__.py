@@ -242,10 +242,10 @@ def get_tuning():
     t = MrrrTuning()
     _lib.check(_lib.load().mrrr_get_tuning(ctypes.byref(t)))
     return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
-            "vec_wave_slots": t.vec_wave_slots}
+            "vec_wave_slots": t.vec_wave_slots, "vec_ckpt_min_run": t.vec_ckpt_min_run}
 
 
-def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None):
+def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, vec_ckpt_min_run=None):
     t = MrrrTuning()
     lib = _lib.load()
     _lib.check(lib.mrrr_get_tuning(ctypes.byref(t)))
@@ -255,6 +255,8 @@ def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None):
         t.refine_wave_slots = int(refine_wave_slots)
     if vec_wave_slots is not None:
         t.vec_wave_slots = int(vec_wave_slots)
+    if vec_ckpt_min_run is not None:
+        t.vec_ckpt_min_run = int(vec_ckpt_min_run)
     if lib.mrrr_set_tuning(ctypes.byref(t)) != 0:
         raise ValueError("tuning value out of range")
 

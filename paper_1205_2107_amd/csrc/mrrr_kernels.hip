@@ -1249,7 +1249,8 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
   if (kMayGuard) {
     const double t0 = f * rc;
     const double t = fma(rc, fma(-den, t0, f), t0);
-    const double xs = (t == 0.0) ? f - lam : x * t - lam;
+    // one rounding in every inlining context (no contraction left to the compiler)
+    const double xs = (t == 0.0) ? f - lam : fma(x, t, -lam);
     xn = guard ? xs : xn;
   }
   const double w0 = LD * rc;
@@ -1599,7 +1600,10 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, SC, PC, c, lds);
       gl = go && !isfinite(x);
       // the pair's two lanes share the guard: the checkpoints of both are recomputed
-      gl = gl || __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
+      // every lane reads its partner's flag: a cross-lane read under the
+      // short circuit would run with the flagged lanes switched off
+      const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
+      gl = gl || gp;
       any_guard = __ballot(gl) != 0;
       if (any_guard) transform_pass<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, SC, PC, c, lds);
     }
@@ -1870,7 +1874,11 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
       };
       pass(std::false_type{}, false);
       bool gl = go && !isfinite(x);
-      gl = gl || __shfl_xor(gl ? 1 : 0, 1, 64) != 0;  // both transforms of a pair in one form
+      // both transforms of a pair in one form; every lane reads its partner's
+      // flag (a cross-lane read under the short circuit would run with the
+      // flagged lanes switched off)
+      const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
+      gl = gl || gp;
       if (__ballot(gl) != 0) pass(std::true_type{}, gl);
     }
     if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;

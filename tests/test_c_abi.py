@@ -64,3 +64,9 @@ def test_tuning_roundtrip():
     assert lib.mrrr_set_tuning(ctypes.byref(t)) == -1
     t.grid_density = old
     assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0
+    for bad in (-2, (1 << 30) + 1):
+        t.vec_ckpt_min_run = bad
+        assert lib.mrrr_set_tuning(ctypes.byref(t)) == -1
+    for ok in (-1, 1, 0):
+        t.vec_ckpt_min_run = ok
+        assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0

@@ -404,6 +404,34 @@ def test_vector_wave_slots_do_not_change_results(M):
         assert np.array_equal(w, outs[0][0]) and np.array_equal(Z, outs[0][1])
 
 
+def test_checkpointing_and_stored_vector_kernels_agree(M):
+    # the checkpointing eigenvector kernel recomputes s and p from checkpoints
+    # and must reproduce the stored-vector kernel bit for bit, also where a
+    # lane pair falls back to the guarded transform (the 1-2-1 matrix has
+    # eigenvalues shared with leading submatrices: exact zero pivots)
+    cases = [W.toeplitz(8000), W.glued_wilkinson(8000, 1), W.random_uniform(8000, 2001)]
+    old = M.get_tuning()
+    try:
+        for d, e in cases:
+            M.set_tuning(vec_ckpt_min_run=0)
+            M.profile(True)
+            w0, Z0, _ = gpu_solve(M, d, e)
+            ran = M.profile_read()["vectors_ckpt"]["launches"]
+            M.profile(False)
+            assert ran > 0, "the checkpointing kernel did not run"
+            M.set_tuning(vec_ckpt_min_run=-1)
+            M.profile(True)
+            w1, Z1, _ = gpu_solve(M, d, e)
+            ran = M.profile_read()["vectors_ckpt"]["launches"]
+            M.profile(False)
+            assert ran == 0
+            assert np.array_equal(w0, w1)
+            bad = np.nonzero(np.any(Z0 != Z1, axis=0))[0]
+            assert bad.size == 0, f"columns differ: {bad[:10]}"
+    finally:
+        M.set_tuning(**old)
+
+
 def test_autotune_batched(M):
     probs = batched_problems(64, 4202, nmax=600)
     d, e, ns, off = W.pack(probs)
