@@ -1369,25 +1369,38 @@ __device__ inline void staged_segments(const Rep* __restrict__ R, int n, int J, 
   }
 }
 
-// 1. the transform of the lane's role over all rows, storing the checkpoints
-//    SC[k] = s at row k kSeg (role 0) and PC[k] = p at row k kSeg, k >= 1
-//    (role 1).  Returns the last value (s_n or p_1).
+// 1-2. the two transforms and the twist index in one pass.  First half: lane
+//    2c runs the stationary transform over the segments above the middle one
+//    (hs = nseg / 2 segments), lane 2c+1 the progressive transform over the
+//    others, each storing its checkpoints (SC[k] = s at row k kSeg; PC[k] =
+//    p at row k kSeg, k >= 1).  Second half: each lane continues its
+//    transform into the other half, segment by segment, and recomputes there
+//    the partner's variable from the partner's checkpoints of the first half,
+//    so gamma_k = s_k + p_k + lam is formed on the way; the smallest |gamma|
+//    wins, ties to the smaller index.  Returns the lane's last transform value
+//    (s_n or p_1) for the finiteness test.
 template <int kPairSlots, bool kMayGuard>
-__device__ inline double transform_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
-                                        bool guard, double lam, double x0, double* __restrict__ SC,
-                                        double* __restrict__ PC, int c, double* __restrict__ lds) {
+__device__ inline double transform_twist(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
+                                         bool guard, double lam, double x0, double xlast, double* __restrict__ SC,
+                                         double* __restrict__ PC, int c, double* __restrict__ lds, double& gmin_out,
+                                         int& r_out) {
   const int nseg = (n + kSeg - 1) / kSeg;
+  const int hs = nseg >> 1;
+  const int cnt1 = role ? nseg - hs : hs;  // first-half segments of the lane
   double x = x0;
+  // first half: the lane's own transform, rows in its role's order
   staged_segments<0, true>(
-      R, n, nseg, role ? nseg - 1 : 0, role ? -1 : 1, lds, [](int, int) { return 0.0; },
-      [&](int, int k, const double* rows, double, double) {
-        if (go && !role) SC[(int64_t)k * kPairSlots + c] = x;
+      R, n, nseg - hs, role ? nseg - 1 : 0, role ? -1 : 1, lds, [](int, int) { return 0.0; },
+      [&](int j, int k, const double* rows, double, double) {
+        const bool on = j < cnt1;
+        if (go && on && !role) SC[(int64_t)k * kPairSlots + c] = x;
         if (__ballot(k == nseg - 1) == 0) {
 #pragma unroll
           for (int u = 0; u < kSeg; ++u) {
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
-            x = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
+            x = on ? xn : x;
           }
         } else {
           // the last segment: no step at row n-1 and beyond
@@ -1397,53 +1410,45 @@ __device__ inline double transform_pass(bool go, int role, const Rep* __restrict
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
             const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
-            x = (k * kSeg + o <= n - 2) ? xn : x;
+            x = (on && k * kSeg + o <= n - 2) ? xn : x;
           }
         }
-        if (go && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
+        if (go && on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
       });
-  return x;
-}
-
-// 2. twist index: lane 2c searches the segments below the middle one, lane
-//    2c+1 the rest; per segment s is recomputed upward from SC, then p
-//    downward from PC (or from p_n) with gamma at every row.  Ties go to the
-//    smaller index.
-template <int kPairSlots, bool kMayGuard>
-__device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, bool guard,
-                                  double lam, double xlast, const double* __restrict__ SC,
-                                  const double* __restrict__ PC, int c, double* __restrict__ lds, double& gmin_out,
-                                  int& r_out) {
-  const int nseg = (n + kSeg - 1) / kSeg;
-  const int hs = nseg >> 1;
-  const int cnt = role ? nseg - hs : hs;
+  __syncthreads();  // first-half checkpoints complete and visible to the partner lane
+  // second half: lane 2c over segments hs .. nseg-1 (ascending), lane 2c+1
+  // over hs-1 .. 0 (descending); both walk a segment's rows upward for s and
+  // downward for p
+  const int cnt2 = role ? hs : nseg - hs;
   double gbest = INFINITY;
   int rbest = -1;
-  staged_segments<2, false>(
-      R, n, nseg - hs, role ? hs : 0, 1, lds,
-      [&](int k, int which) {
-        const int kk = min(which ? k + 1 : k, nseg - 1);
-        return (which ? PC : SC)[(int64_t)kk * kPairSlots + c];
+  staged_segments<1, false>(
+      R, n, nseg - hs, role ? hs - 1 : hs, role ? -1 : 1, lds,
+      [&](int k, int) {
+        const int kk = min(max(role ? k : k + 1, 0), nseg - 1);
+        return (role ? SC : PC)[(int64_t)kk * kPairSlots + c];
       },
-      [&](int j, int k, const double* rows, double c0, double c1) {
-        const bool on = go && j < cnt;
-        // kEdge: the last segment (no step at row n-1 and beyond) is in play
+      [&](int j, int k, const double* rows, double ck, double) {
+        const bool on = j < cnt2;
+        if (go && on && !role) SC[(int64_t)k * kPairSlots + c] = x;
         auto seg = [&](auto E) {
           constexpr bool kEdge = decltype(E)::value;
-          // s_i at the rows of the segment
+          // s_i at the rows of the segment: lane 2c continues its transform,
+          // lane 2c+1 recomputes from the partner's checkpoint
           double sv[kSeg];
-          double x = c0;
+          double xs = role ? ck : x;
 #pragma unroll
           for (int u = 0; u < kSeg; ++u) {
-            sv[u] = x;
+            sv[u] = xs;
             double w;
             const double LD = rows[4 * u + 2];
-            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, x, lam, pivmin, guard, w);
-            x = (!kEdge || k * kSeg + u <= n - 2) ? xn : x;
+            const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, xs, lam, pivmin, guard, w);
+            xs = (!kEdge || k * kSeg + u <= n - 2) ? xn : xs;
           }
-          // p_i from the first row of the next segment (or p_n) downward
+          // p_i downward from the first row of the next segment (or p_n): lane
+          // 2c+1 continues its transform, lane 2c recomputes from a checkpoint
           const int rs = min((k + 1) * kSeg, n - 1);
-          double xp = (kEdge && rs == n - 1) ? xlast : c1;
+          double xp = role ? x : ((kEdge && rs == n - 1) ? xlast : ck);
           double gseg = INFINITY;
           int rseg = -1;
 #pragma unroll
@@ -1459,21 +1464,28 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
             gseg = take ? g : gseg;
             rseg = take ? row : rseg;
           }
-          if (on && fabs(gseg) < fabs(gbest)) {
-            gbest = gseg;
-            rbest = rseg;
+          if (on) {
+            // segments come in ascending order on lane 2c and descending on
+            // lane 2c+1: ties go to the smaller index either way
+            const bool better = role ? fabs(gseg) <= fabs(gbest) && rseg >= 0 : fabs(gseg) < fabs(gbest);
+            if (better) {
+              gbest = gseg;
+              rbest = rseg;
+            }
+            x = role ? xp : xs;
           }
         };
         if (__ballot(k >= nseg - 1) != 0)
           seg(std::true_type{});
         else
           seg(std::false_type{});
+        if (go && on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
       });
-  // the partner's candidate; ties go to the smaller index (lane 2c's half)
+  // the partner's candidate; lane 2c+1 searched the smaller indices
   const double go_g = __shfl_xor(gbest, 1, 64);
   const int go_r = __shfl_xor(rbest, 1, 64);
-  const double gt = role ? go_g : gbest, gb = role ? gbest : go_g;
-  const int rt = role ? go_r : rbest, rb = role ? rbest : go_r;
+  const double gt = role ? gbest : go_g, gb = role ? go_g : gbest;  // gt: lane 2c+1 (rows below the middle)
+  const int rt = role ? rbest : go_r, rb = role ? go_r : rbest;
   const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
   double gmin = take_b ? gb : gt;
   int r = take_b ? rb : rt;
@@ -1483,6 +1495,7 @@ __device__ inline void twist_pass(bool go, int role, const Rep* __restrict__ R, 
   }
   gmin_out = gmin;
   r_out = r;
+  return x;
 }
 
 // 3. the solve outward from the twist r: lane 2c from row r-1 up to row 0,
@@ -1596,8 +1609,11 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     //    the recomputations of this solve follow the pass that was kept.
     const double x0 = role ? xlast : -lam;
     bool any_guard = false, gl = false;  // the lane's transform needed the guarded form
+    double gmin;
+    int r;
     {
-      const double x = transform_pass<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, SC, PC, c, lds);
+      const double x = transform_twist<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, xlast, SC, PC, c,
+                                                          lds, gmin, r);
       gl = go && !isfinite(x);
       // the pair's two lanes share the guard: the checkpoints of both are recomputed
       // every lane reads its partner's flag: a cross-lane read under the
@@ -1605,16 +1621,12 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
       const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
       gl = gl || gp;
       any_guard = __ballot(gl) != 0;
-      if (any_guard) transform_pass<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, SC, PC, c, lds);
+      if (any_guard) {
+        __syncthreads();  // the first pass's checkpoints are read before they are rewritten
+        transform_twist<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, xlast, SC, PC, c, lds, gmin, r);
+      }
     }
     __syncthreads();  // checkpoints complete and visible to the partner lane
-    // 2. twist index
-    double gmin;
-    int r;
-    if (any_guard)
-      twist_pass<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, xlast, SC, PC, c, lds, gmin, r);
-    else
-      twist_pass<kPairSlots, false>(go, role, R, n, pivmin, false, lam, xlast, SC, PC, c, lds, gmin, r);
     // 3. solve: ||z||^2 and the largest entry
     double nrm, zbest;
     if (any_guard)
