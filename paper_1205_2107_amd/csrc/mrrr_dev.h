@@ -28,6 +28,9 @@ constexpr int kChildMaskedFrom = 1024;   // child builds: clusters per launch fr
 constexpr int kChildSpecMany = 2;        // speculative child regions per cluster, masked form
 constexpr int kChildSpecFew = 4;         // ... branch-free form
 constexpr int64_t kChildFewMaxN = 1 << 24;  // branch-free form only below this block order
+constexpr int kChildSpecAll = 16;        // ... branch-free form with few clusters: every candidate
+constexpr int64_t kChildAllMaxN = 1 << 22;     // every-candidate form only below this block order
+constexpr int64_t kChildAllMaxRows = 1 << 25;  // ... and while its regions take at most this many rows
 constexpr int kCkptMinRun = 16;          // checkpointing eigenvector kernel: equal-node run length ...
 constexpr int kCkptMinN = 4096;          // ... and block order from which it is used
 

@@ -329,11 +329,14 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       const int ncl = std::min(hc.nclusters, max_clusters);
       if (ncl == 0) break;
       // capacity for the new nodes and the speculative child regions of every
-      // cluster (two with masked stores, four in the branch-free form)
+      // cluster (two with masked stores, four in the branch-free form, every
+      // candidate's when the regions stay small: no second pass)
       if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
       const bool masked = ncl >= kChildMaskedFrom || nmax_prob >= kChildFewMaxN;
-      const size_t spec = masked ? kChildSpecMany : kChildSpecFew;
-      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + spec * (size_t)hc.cluster_rows;
+      const bool all = !masked && nmax_prob < kChildAllMaxN &&
+                       (size_t)kChildSpecAll * (size_t)hc.cluster_rows <= (size_t)kChildAllMaxRows;
+      const int spec = masked ? kChildSpecMany : (all ? kChildSpecAll : kChildSpecFew);
+      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + (size_t)spec * (size_t)hc.cluster_rows;
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
         if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
         dpool = P_<Rep>(W.pool);
@@ -347,7 +350,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       }
       prof.begin(MRRR_K_CHILD);
       launch_child(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<double>(W.lo),
-                   P_<double>(W.hi), dpool, pool_cap, dC, masked);
+                   P_<double>(W.hi), dpool, pool_cap, dC, spec);
       prof.end();
       launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
                    P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),

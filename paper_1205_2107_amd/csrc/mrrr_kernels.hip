@@ -919,16 +919,18 @@ __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const 
   return side ? h0 + delta : l0 - delta;
 }
 
-// kMasked: the two closest candidates store their rows, each by its owning
-// lane under an execution mask (few store lanes per instruction: cheaper when
-// many wavefronts share the chip).  Otherwise the four closest candidates
-// (levels 0 and 1 at both ends) store theirs through one buffer resource
-// whose range check drops the other lanes' stores, which keeps the loop
-// branch-free (faster for a lone wavefront, whose LDS reads then batch across
-// rows) and saves the second pass when a level-1 candidate wins; that form
-// needs 3 n rows of 32 bytes to stay below 2^31 bytes (the host picks the
-// masked form for blocks of 2^24 rows or more).
-template <bool kMasked>
+// kMasked: the kSpec = 2 closest candidates store their rows, each by its
+// owning lane under an execution mask (few store lanes per instruction:
+// cheaper when many wavefronts share the chip).  Otherwise the kSpec closest
+// candidates (4: levels 0 and 1 at both ends; or all of them) store theirs
+// through one buffer resource whose range check drops the other lanes'
+// stores, which keeps the loop branch-free (faster for a lone wavefront,
+// whose LDS reads then batch across rows) and saves the second pass when one
+// of them wins; the instruction count does not depend on kSpec.  That form
+// needs (kSpec - 1) n rows of 32 bytes to stay below 2^31 bytes (the host
+// picks the masked form for blocks of 2^24 rows or more, and every candidate
+// only below 2^22 rows and with few clusters).
+template <bool kMasked, int kSpec>
 __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
                                               int node_base, const Cluster* __restrict__ clusters,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
@@ -944,7 +946,7 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   const double* Rd = reinterpret_cast<const double*>(pool + par.rep);
   // child-sized regions for the closest candidates (lanes 0 .. kSpec-1), which
   // store their rows while pass 1 runs; usually one of them wins
-  constexpr int kSpec = kMasked ? kChildSpecMany : kChildSpecFew;
+  static_assert(kMasked ? kSpec == 2 : (kSpec >= 2 && kSpec <= kChildCand), "speculative regions");
   long long base = -1;
   if (lane == 0) {
     base = (long long)atomicAdd(&C->pool_used, (unsigned long long)kSpec * (unsigned long long)n);
@@ -2399,15 +2401,19 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
-                  bool masked) {
+                  int spec) {
   // a lone or few wavefronts are latency-bound (branch-free stores), a full
   // chip is issue-bound (masked stores)
-  if (masked)
-    hipLaunchKernelGGL(k_child<true>, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo, hi,
-                       pool, pool_cap, C);
+  static_assert(kChildSpecAll == kChildCand, "every candidate");
+  if (spec == kChildSpecMany)
+    hipLaunchKernelGGL((k_child<true, kChildSpecMany>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base,
+                       clusters, lo, hi, pool, pool_cap, C);
+  else if (spec == kChildSpecFew)
+    hipLaunchKernelGGL((k_child<false, kChildSpecFew>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
+                       node_base, clusters, lo, hi, pool, pool_cap, C);
   else
-    hipLaunchKernelGGL(k_child<false>, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo,
-                       hi, pool, pool_cap, C);
+    hipLaunchKernelGGL((k_child<false, kChildSpecAll>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
+                       node_base, clusters, lo, hi, pool, pool_cap, C);
 }
 
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
