@@ -412,7 +412,8 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     HIP_TRY(hipStreamSynchronize(st));
     int64_t nmax_all = 1;
     for (auto& p : probs) nmax_all = std::max<int64_t>(nmax_all, p.n);
-    const int64_t stride = 2 * (int64_t)vslots * ((nmax_all + kSeg - 1) / kSeg);
+    // checkpoints per chunk: s, p and their derivatives, [segment][slot] each
+    const int64_t stride = 4 * (int64_t)vslots * ((nmax_all + kSeg - 1) / kSeg);
     // the stored-vector kernel's chunks (32 consecutive slots, scratch sized
     // by their largest block), planned and uploaded before either kernel
     // starts: a transfer queued while the checkpointing kernel fills the chip

@@ -1260,6 +1260,14 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
   return xn;
 }
 
+// Derivative of the transform variable with respect to lam along the same
+// step: d x' = (f b / (b + x)^2) d x - 1 = w^2 d x - 1 (f b = (L D)^2), from
+// d x = -1 at the start.  Accumulated this way, -d s_r and -d p_r are the
+// sums of the squared entries of the twisted solve's z (z_r = 1) above and
+// below the twist, in Horner form, so ||z||^2 = -(d s_r + d p_r + 1) =
+// -d gamma_r / d lam comes with the transforms and no solve is needed.
+__device__ __forceinline__ double dstep(double w, double dx) { return fma(w * w, dx, -1.0); }
+
 __device__ __forceinline__ int wave_max(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
@@ -1374,35 +1382,42 @@ __device__ inline void staged_segments(const Rep* __restrict__ R, int n, int J, 
 // 1-2. the two transforms and the twist index in one pass.  First half: lane
 //    2c runs the stationary transform over the segments above the middle one
 //    (hs = nseg / 2 segments), lane 2c+1 the progressive transform over the
-//    others, each storing its checkpoints (SC[k] = s at row k kSeg; PC[k] =
-//    p at row k kSeg, k >= 1).  Second half: each lane continues its
-//    transform into the other half, segment by segment, and recomputes there
-//    the partner's variable from the partner's checkpoints of the first half,
-//    so gamma_k = s_k + p_k + lam is formed on the way; the smallest |gamma|
-//    wins, ties to the smaller index.  Returns the lane's last transform value
-//    (s_n or p_1) for the finiteness test.
+//    others.  Second half: each lane continues its transform into the other
+//    half, segment by segment, and recomputes there the partner's variable
+//    from the partner's checkpoints of the first half, so gamma_k = s_k + p_k
+//    + lam is formed on the way; the smallest |gamma| wins, ties to the
+//    smaller index.  Each lane carries the derivative of its own variable
+//    along and stores checkpoints of both at every segment it passes (SC[k],
+//    DS[k] = s, d s at row k kSeg; PC[k], DP[k] = p, d p there, k >= 1).
+//    Returns the lane's last transform value (s_n or p_1) for the finiteness
+//    test.
 template <int kPairSlots, bool kMayGuard>
 __device__ inline double transform_twist(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
                                          bool guard, double lam, double x0, double xlast, double* __restrict__ SC,
-                                         double* __restrict__ PC, int c, double* __restrict__ lds, double& gmin_out,
-                                         int& r_out) {
+                                         double* __restrict__ PC, double* __restrict__ DS, double* __restrict__ DP,
+                                         int c, double* __restrict__ lds, double& gmin_out, int& r_out) {
   const int nseg = (n + kSeg - 1) / kSeg;
   const int hs = nseg >> 1;
   const int cnt1 = role ? nseg - hs : hs;  // first-half segments of the lane
-  double x = x0;
+  double x = x0, dx = -1.0;
   // first half: the lane's own transform, rows in its role's order
   staged_segments<0, true>(
       R, n, nseg - hs, role ? nseg - 1 : 0, role ? -1 : 1, lds, [](int, int) { return 0.0; },
       [&](int j, int k, const double* rows, double, double) {
         const bool on = j < cnt1;
-        if (go && on && !role) SC[(int64_t)k * kPairSlots + c] = x;
+        if (go && on && !role) {
+          SC[(int64_t)k * kPairSlots + c] = x;
+          DS[(int64_t)k * kPairSlots + c] = dx;
+        }
         if (__ballot(k == nseg - 1) == 0) {
 #pragma unroll
           for (int u = 0; u < kSeg; ++u) {
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
             const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
+            const double dxn = dstep(w, dx);
             x = on ? xn : x;
+            dx = on ? dxn : dx;
           }
         } else {
           // the last segment: no step at row n-1 and beyond
@@ -1412,10 +1427,16 @@ __device__ inline double transform_twist(bool go, int role, const Rep* __restric
             const double f = rows[4 * u + 3], LD = rows[4 * u + 2];
             double w;
             const double xn = xstep_bf<kMayGuard>(rows[4 * u], f, LD, x, lam, pivmin, guard, w);
-            x = (on && k * kSeg + o <= n - 2) ? xn : x;
+            const double dxn = dstep(w, dx);
+            const bool st = on && k * kSeg + o <= n - 2;
+            x = st ? xn : x;
+            dx = st ? dxn : dx;
           }
         }
-        if (go && on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
+        if (go && on && role && k >= 1) {
+          PC[(int64_t)k * kPairSlots + c] = x;
+          DP[(int64_t)k * kPairSlots + c] = dx;
+        }
       });
   __syncthreads();  // first-half checkpoints complete and visible to the partner lane
   // second half: lane 2c over segments hs .. nseg-1 (ascending), lane 2c+1
@@ -1432,25 +1453,33 @@ __device__ inline double transform_twist(bool go, int role, const Rep* __restric
       },
       [&](int j, int k, const double* rows, double ck, double) {
         const bool on = j < cnt2;
-        if (go && on && !role) SC[(int64_t)k * kPairSlots + c] = x;
+        if (go && on && !role) {
+          SC[(int64_t)k * kPairSlots + c] = x;
+          DS[(int64_t)k * kPairSlots + c] = dx;
+        }
         auto seg = [&](auto E) {
           constexpr bool kEdge = decltype(E)::value;
-          // s_i at the rows of the segment: lane 2c continues its transform,
-          // lane 2c+1 recomputes from the partner's checkpoint
+          // s_i at the rows of the segment: lane 2c continues its transform
+          // (and its derivative), lane 2c+1 recomputes from the partner's
+          // checkpoint
           double sv[kSeg];
-          double xs = role ? ck : x;
+          double xs = role ? ck : x, dxs = dx;
 #pragma unroll
           for (int u = 0; u < kSeg; ++u) {
             sv[u] = xs;
             double w;
             const double LD = rows[4 * u + 2];
             const double xn = xstep_bf<kMayGuard>(rows[4 * u], rows[4 * u + 3], LD, xs, lam, pivmin, guard, w);
-            xs = (!kEdge || k * kSeg + u <= n - 2) ? xn : xs;
+            const bool st = !kEdge || k * kSeg + u <= n - 2;
+            xs = st ? xn : xs;
+            if (!role) dxs = st ? dstep(w, dxs) : dxs;
           }
           // p_i downward from the first row of the next segment (or p_n): lane
-          // 2c+1 continues its transform, lane 2c recomputes from a checkpoint
+          // 2c+1 continues its transform (and its derivative), lane 2c
+          // recomputes from a checkpoint
           const int rs = min((k + 1) * kSeg, n - 1);
           double xp = role ? x : ((kEdge && rs == n - 1) ? xlast : ck);
+          double dxp = dx;
           double gseg = INFINITY;
           int rseg = -1;
 #pragma unroll
@@ -1460,7 +1489,9 @@ __device__ inline double transform_twist(bool go, int role, const Rep* __restric
             const double D = rows[4 * u];
             const double xpn =
                 xstep_bf<kMayGuard>(rows[4 * u + 3], D, rows[4 * u + 2], xp, lam, pivmin, guard, w);
-            xp = (!kEdge || row < rs) ? xpn : xp;
+            const bool st = !kEdge || row < rs;
+            xp = st ? xpn : xp;
+            if (role) dxp = st ? dstep(w, dxp) : dxp;
             const double g = sv[u] + xp + lam;
             const bool take = (!kEdge || row <= rs) && isfinite(g) && fabs(g) <= fabs(gseg);
             gseg = take ? g : gseg;
@@ -1475,13 +1506,17 @@ __device__ inline double transform_twist(bool go, int role, const Rep* __restric
               rbest = rseg;
             }
             x = role ? xp : xs;
+            dx = role ? dxp : dxs;
           }
         };
         if (__ballot(k >= nseg - 1) != 0)
           seg(std::true_type{});
         else
           seg(std::false_type{});
-        if (go && on && role && k >= 1) PC[(int64_t)k * kPairSlots + c] = x;
+        if (go && on && role && k >= 1) {
+          PC[(int64_t)k * kPairSlots + c] = x;
+          DP[(int64_t)k * kPairSlots + c] = dx;
+        }
       });
   // the partner's candidate; lane 2c+1 searched the smaller indices
   const double go_g = __shfl_xor(gbest, 1, 64);
@@ -1493,11 +1528,53 @@ __device__ inline double transform_twist(bool go, int role, const Rep* __restric
   int r = take_b ? rb : rt;
   if (r < 0) {
     r = 0;
-    gmin = 0.0;
+    gmin = NAN;  // no finite gamma: marks the round for the solve
   }
   gmin_out = gmin;
   r_out = r;
   return x;
+}
+
+// d s_r (lane 2c: from the checkpoint of r's segment up to row r) and d p_r
+// (lane 2c+1: from the checkpoint of the next segment, or p_n, down to row
+// r), the same steps as the transforms, so the same bits; returns
+// d s_r + d p_r for both lanes of the pair.
+template <int kPairSlots, bool kMayGuard>
+__device__ inline double twist_derivative(bool go, int role, const Rep* __restrict__ R, int n, double pivmin,
+                                          bool guard, double lam, double xlast, int r,
+                                          const double* __restrict__ SC, const double* __restrict__ PC,
+                                          const double* __restrict__ DS, const double* __restrict__ DP, int c) {
+  const int nseg = (n + kSeg - 1) / kSeg;
+  const int kr = r / kSeg;
+  double x = 0.0, dx = 0.0;
+  int start;  // first row stepped: lane 2c upward from kr kSeg, lane 2c+1 downward from start
+  if (!role) {
+    start = kr * kSeg;
+    x = go ? SC[(int64_t)kr * kPairSlots + c] : 0.0;
+    dx = go ? DS[(int64_t)kr * kPairSlots + c] : 0.0;
+  } else {
+    const int ke = kr + 1;
+    const bool at_end = ke >= nseg || ke * kSeg >= n - 1;
+    start = at_end ? n - 1 : ke * kSeg;
+    x = at_end ? xlast : (go ? PC[(int64_t)ke * kPairSlots + c] : 0.0);
+    dx = at_end ? -1.0 : (go ? DP[(int64_t)ke * kPairSlots + c] : 0.0);
+  }
+#pragma unroll
+  for (int t = 0; t < kSeg; ++t) {
+    // lane 2c: step at row start + t while it is below r; lane 2c+1: step at
+    // row start - 1 - t while it is at or above r
+    const int row = role ? start - 1 - t : start + t;
+    const bool st = go && (role ? row >= r : row < r);
+    const Rep q = R[min(max(row, 0), n - 1)];
+    double w;
+    const double b = role ? q.LLD : q.D, f = role ? q.D : q.LLD;
+    const double xn = xstep_bf<kMayGuard>(b, f, q.LD, x, lam, pivmin, guard, w);
+    const double dxn = dstep(w, dx);
+    x = st ? xn : x;
+    dx = st ? dxn : dx;
+  }
+  const double o = __shfl_xor(dx, 1, 64);
+  return role ? o + dx : dx + o;  // d s_r + d p_r
 }
 
 // 3. the solve outward from the twist r: lane 2c from row r-1 up to row 0,
@@ -1589,12 +1666,16 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
 
 // Rayleigh-quotient iteration for the eigenvector of lane pair c (role 0 =
 // top-down / upward lane, role 1 = bottom-up / downward lane) over
-// checkpoints SC, PC ([segment][kPairSlots] each).  Returns the twist index of
-// the last solve, with its shift in lam_last and its guard flag in g_last.
+// checkpoints SC, PC, DS, DP ([segment][kPairSlots] each).  Every round is one
+// pass of the transforms with the twist search; ||z||^2 comes from the
+// derivative of gamma_r (a solve runs only where that is not finite).
+// Returns the twist index of the last round, with its shift in lam_last and
+// its guard flag in g_last.
 template <int kPairSlots>
 __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, int n, double pivmin,
-                               double* __restrict__ SC, double* __restrict__ PC, int c, double* __restrict__ lds,
-                               VecState& V, double& lam_last, bool& g_last) {
+                               double* __restrict__ SC, double* __restrict__ PC, double* __restrict__ DS,
+                               double* __restrict__ DP, int c, double* __restrict__ lds, VecState& V,
+                               double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
   int rout = 0;
@@ -1604,53 +1685,59 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     if (__ballot(go) == 0) break;
     const double lam = V.lam;
     const double xlast = dn - lam;  // p_n
-    // 1. the two transforms, concurrently.  Without a zero or overflowing
-    //    pivot (the usual case) the guard and the special-case rule are
-    //    no-ops, so the first pass runs without them; a lane that ends with a
-    //    non-finite value makes the wavefront repeat the pass with both, and
-    //    the recomputations of this solve follow the pass that was kept.
+    // 1-2. the two transforms, concurrently, with the twist search.  Without
+    //    a zero or overflowing pivot (the usual case) the guard and the
+    //    special-case rule are no-ops, so the first pass runs without them; a
+    //    lane that ends with a non-finite value makes the wavefront repeat the
+    //    pass with both, and the recomputations of this round follow the pass
+    //    that was kept.
     const double x0 = role ? xlast : -lam;
     bool any_guard = false, gl = false;  // the lane's transform needed the guarded form
     double gmin;
     int r;
     {
-      const double x = transform_twist<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, xlast, SC, PC, c,
-                                                          lds, gmin, r);
+      const double x = transform_twist<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, xlast, SC, PC, DS,
+                                                          DP, c, lds, gmin, r);
       gl = go && !isfinite(x);
-      // the pair's two lanes share the guard: the checkpoints of both are recomputed
-      // every lane reads its partner's flag: a cross-lane read under the
-      // short circuit would run with the flagged lanes switched off
+      // the pair's two lanes share the guard: the checkpoints of both are
+      // recomputed; every lane reads its partner's flag (a cross-lane read
+      // under the short circuit would run with the flagged lanes switched off)
       const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
       gl = gl || gp;
       any_guard = __ballot(gl) != 0;
       if (any_guard) {
         __syncthreads();  // the first pass's checkpoints are read before they are rewritten
-        transform_twist<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, xlast, SC, PC, c, lds, gmin, r);
+        transform_twist<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, xlast, SC, PC, DS, DP, c, lds, gmin,
+                                          r);
       }
     }
     __syncthreads();  // checkpoints complete and visible to the partner lane
-    // 3. solve: ||z||^2 and the largest entry
-    double nrm, zbest;
-    if (any_guard)
-      solve_pass<kPairSlots, true, false>(go, role, R, n, pivmin, gl, lam, xlast, r, SC, PC, c, lds, nullptr, 1.0,
-                                          nrm, zbest);
-    else
-      solve_pass<kPairSlots, false, false>(go, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, lds, nullptr,
-                                           1.0, nrm, zbest);
-    {
-      // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
-      const double nrm_o = __shfl_xor(nrm, 1, 64);
-      const double zb_o = __shfl_xor(zbest, 1, 64);
-      nrm += nrm_o;
-      const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
-      zbest = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+    // 3. ||z||^2 = -(d s_r + d p_r + 1); a pair without a finite value solves
+    const double dg = any_guard ? twist_derivative<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, xlast, r, SC,
+                                                                     PC, DS, DP, c)
+                                : twist_derivative<kPairSlots, false>(go, role, R, n, pivmin, false, lam, xlast, r,
+                                                                      SC, PC, DS, DP, c);
+    double nrm = -(dg + 1.0);
+    const bool need = go && !(nrm < INFINITY && gmin == gmin);
+    gmin = (gmin == gmin) ? gmin : 0.0;
+    if (__ballot(need) != 0) {
+      double ns, zb;
+      if (any_guard)
+        solve_pass<kPairSlots, true, false>(need, role, R, n, pivmin, gl, lam, xlast, r, SC, PC, c, lds, nullptr,
+                                            1.0, ns, zb);
+      else
+        solve_pass<kPairSlots, false, false>(need, role, R, n, pivmin, false, lam, xlast, r, SC, PC, c, lds,
+                                             nullptr, 1.0, ns, zb);
+      const double ns_o = __shfl_xor(ns, 1, 64);  // combine the halves
+      ns += ns_o;
+      nrm = need ? ns : nrm;
+      __syncthreads();
     }
-    __syncthreads();  // checkpoints read before the next transform overwrites them
     if (go) {
       rout = r;
       lam_last = lam;
       g_last = gl;
-      rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
+      rqi_commit(V, conv, last, it, n, gmin, nrm, 1.0, lam);
     }
   }
   if (solve && !conv) V.lam_out = V.lam;
@@ -1693,6 +1780,8 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
   double* SC = scratch + (int64_t)ci * stride;
   double* PC = SC + (int64_t)((n + kSeg - 1) / kSeg) * kPairSlots;
+  double* DS = PC + (int64_t)((n + kSeg - 1) / kSeg) * kPairSlots;
+  double* DP = DS + (int64_t)((n + kSeg - 1) / kSeg) * kPairSlots;
   const int cs = lane_slot ? c : 0;  // checkpoint column (idle lanes never store)
   VecState V;
   V.lo = lo_a[ss];
@@ -1713,12 +1802,9 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   bool g_last = false;
   const Rep* R = pool + uniform_ll(nd.rep);
   const double pivmin = __longlong_as_double(uniform_ll(__double_as_longlong(blk.pivmin)));
-  const int r = pair_rqi<kPairSlots>(solve, role, R, n, pivmin, SC, PC, cs, lds, V, lam_last, g_last);
-  double scale = 1.0;
-  if (solve) {
-    scale = 1.0 / sqrt(V.nrm);
-    if (V.zmaxv < 0.0) scale = -scale;
-  }
+  const int r = pair_rqi<kPairSlots>(solve, role, R, n, pivmin, SC, PC, DS, DP, cs, lds, V, lam_last, g_last);
+  // the sign (largest entry positive) is known once the vector is written
+  const double scale = solve ? 1.0 / sqrt(V.nrm) : 1.0;
   const Problem pr = P[blk.prob];
   // eigenvalue (once per pair)
   if (act && !role) {
@@ -1743,6 +1829,29 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
       solve_pass<kPairSlots, true, true>(solve, role, R, n, pivmin, g_last, lam_last, R[n - 1].D - lam_last, r, SC,
                                          PC, cs, lds, Zc, scale, nrm_d, zb_d);
     if (act && role) Zc[solve ? r : 0] = scale;  // z_r = 1 (n = 1: the unit vector)
+    if (n > 1) {
+      // the signed entry of largest magnitude (ties: smaller row) decides the
+      // sign; its twist row holds z_r = 1 > 0, so a flip is rare.  A pair
+      // whose entry is negative negates its rows: lane 2c rows 0 .. r-1, lane
+      // 2c+1 rows r .. n-1 (the values -(z s) equal z (-s) bit for bit).
+      const double zb_o = __shfl_xor(zb_d, 1, 64);
+      const double zt = role ? zb_o : zb_d, zb = role ? zb_d : zb_o;
+      const double zmax = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+      const bool flip = solve && zmax < 0.0;
+      if (__ballot(flip) != 0) {
+        const int a = role ? r : 0;
+        const int len = flip ? (role ? n - r : r) : 0;
+        const int T = wave_max(len);
+        for (int t0 = 0; t0 < T; t0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = (t0 + u < len) ? Zc[a + t0 + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (t0 + u < len) Zc[a + t0 + u] = -v[u];
+        }
+      }
+    }
     // rows of the problem outside the block are exact zeros
     for (int cl = 0; cl < kPairSlots; ++cl) {
       if (s_col[cl] < 0) continue;
@@ -1801,8 +1910,9 @@ constexpr int kHB = 8;  // steps per half of a double buffer
 // one half of kHB steps are issued while the other half is consumed, so every
 // value arrives kHB .. 2 kHB - 1 steps after its load was issued.  load(t)
 // must be in bounds for any t >= 0; step(t, v) sees steps in order.
-template <class Ld, class St>
+template <int kH = kHB, class Ld, class St>
 __device__ __forceinline__ void pipelined(int T, Ld&& load, St&& step) {
+  constexpr int kHB = kH;  // this pipeline's half depth
   using V = decltype(load(0));
   V a[kHB], b[kHB];
 #pragma unroll
@@ -1823,19 +1933,116 @@ __device__ __forceinline__ void pipelined(int T, Ld&& load, St&& step) {
   }
 }
 
-struct Pair2 {
-  double s, p;
+struct Quad {
+  double s, p, ds, dp;
 };
+struct Row2x {
+  double x, b, LD;
+};
+
+// The quotient of the step at one row, as the transform step computes it
+// (same operations, so the same bits): w = LD / (b + x), the pivot replaced
+// by -pivmin below pivmin in the guarded form.
+__device__ __forceinline__ double step_w(double b, double x, double LD, double pivmin, bool guard) {
+  double den = b + x;
+  den = (guard && fabs(den) < pivmin) ? -pivmin : den;
+  const double rc = rcp_nr1(den);
+  const double w0 = LD * rc;
+  return fma(rc, fma(-den, w0, LD), w0);
+}
+
+// Solve outward from the twist r of every lane with `on_lane`: z_i = -L+_i
+// z_{i+1} upward (lane 2c), z_{i+1} = -U-_i z_i downward (lane 2c+1), the
+// quotients recomputed from the stored s (top) or p (bottom) and the
+// representation row; where a z is zero the row of L D L^T - lam I gives the
+// next one from the one before.  z goes to the lane's work vector Wr (rows
+// < r in W0, rows >= r in W1, z_r = 1); returns ||z||^2 and the signed entry
+// of largest magnitude (ties: smaller row) over both halves.  Rows are
+// visited in a wave-uniform order per role (top lanes from the largest twist
+// index of the wave down, bottom lanes from the smallest up), each lane
+// active on its own side of its twist, so every access is one coalesced row
+// of the work vector.
+template <int kPairSlots>
+__device__ inline void solve_stored(bool on_lane, int role, const Rep* __restrict__ R, int n, double pivmin,
+                                    bool guard, int r, const double* __restrict__ S, const double* __restrict__ P,
+                                    double* __restrict__ Wr, int c, double& nrm_out, double& zbest_out) {
+  double nrm = 0.0, zbest = 0.0;
+  if (on_lane && role) {
+    nrm = 1.0;
+    zbest = 1.0;
+  }
+  int rmax = (on_lane && !role) ? r : 0;        // top lanes: rows rmax-1 .. 0
+  int rmin = (on_lane && role) ? r : INT_MAX;   // bottom lanes: rows rmin .. n-2
+  for (int o = 32; o > 0; o >>= 1) {
+    rmax = max(rmax, __shfl_xor(rmax, o, 64));
+    rmin = min(rmin, __shfl_xor(rmin, o, 64));
+  }
+  if (rmin == INT_MAX) rmin = 0;  // no lane iterating: nothing to visit
+  int nb = (on_lane && role) ? n - 1 - rmin : 0;
+  for (int o = 32; o > 0; o >>= 1) nb = max(nb, __shfl_xor(nb, o, 64));
+  const int T3 = max(rmax, nb);
+  const int base = role ? rmin : rmax - 1;
+  const int dir = role ? 1 : -1;
+  double zc = 1.0, zp = 0.0;
+  pipelined<4>(
+      T3,
+      [&](int t) {
+        // top: s_i with D_i; bottom: p_{i+1} with LLD_i
+        const int row = clamp_row(base + dir * t, n);
+        const int xr = role ? min(row + 1, n - 1) : row;
+        Row2x v;
+        v.x = (role ? P : S)[(int64_t)xr * kPairSlots + c];
+        v.b = role ? R[row].LLD : R[row].D;
+        v.LD = R[row].LD;
+        return v;
+      },
+      [&](int t, const Row2x& v) {
+        const int row = base + dir * t;
+        const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
+        if (t < T3 && on_lane && on) {
+          const bool first = role ? (row == r) : (row == r - 1);
+          double zn;
+          if (zc != 0.0 || first) {
+            zn = -step_w(v.b, v.x, v.LD, pivmin, guard) * zc;
+          } else if (zp != 0.0) {
+            const double ldi = R[row].LD;
+            const double ldn = R[row - dir].LD;
+            zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
+          } else {
+            zn = 0.0;  // an underflowed tail stays zero
+          }
+          zn = isfinite(zn) ? zn : 0.0;
+          const int zrow = role ? row + 1 : row;
+          Wr[(int64_t)zrow * kPairSlots + c] = zn;
+          zp = zc;
+          zc = zn;
+          nrm += zn * zn;
+          // largest magnitude, ties to the smaller row
+          if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
+        }
+      });
+  if (on_lane && role) Wr[(int64_t)r * kPairSlots + c] = 1.0;
+  // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
+  const double nrm_o = __shfl_xor(nrm, 1, 64);
+  const double zb_o = __shfl_xor(zbest, 1, 64);
+  nrm += nrm_o;
+  const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
+  nrm_out = nrm;
+  zbest_out = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+}
 
 // one Rayleigh-quotient iteration sequence for the eigenvector of lane pair c;
 // role 0 = top-down / upward lane, role 1 = bottom-up / downward lane.  Work
-// vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = L+_i then z above the
-// twist, W1 = U-_i then z from the twist down.  Returns the twist index of the
-// last solve (z is in W0 for rows < r and in W1 for rows >= r).
+// vectors, each [row][kPairSlots]: S = s_i, P = p_i, W0 = d s_i / d lam (then
+// z above the twist), W1 = d p_i / d lam (then z from the twist down).  Every
+// round is the two transforms and the twist scan; ||z||^2 comes from the
+// derivatives at the twist (a solve runs only where that is not finite).
+// Returns the twist index of the last round, with its shift in lam_last and
+// its guard flag in g_last.
 template <int kPairSlots>
 __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restrict__ R, int n, int nmax, double pivmin,
-                               double* __restrict__ S, double* __restrict__ P, double* __restrict__ W0,
-                               double* __restrict__ W1, int c, VecState& V) {
+                                      double* __restrict__ S, double* __restrict__ P, double* __restrict__ W0,
+                                      double* __restrict__ W1, int c, VecState& V, double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
   int rout = 0;
@@ -1843,20 +2050,23 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
   int T = n - 1;
   for (int o = 32; o > 0; o >>= 1) T = max(T, __shfl_xor(T, o, 64));
   double* const X = role ? P : S;    // this lane's transform variable
-  double* const Wr = role ? W1 : W0;  // this lane's quotients, then z
+  double* const Wr = role ? W1 : W0;  // this lane's derivatives, then z
   for (int it = 0; it <= kMaxRqi; ++it) {
     const bool go = solve && !conv;
     if (__ballot(go) == 0) break;
     const double lam = V.lam;
-    // 1. the two transforms, concurrently; each step also stores the quotient
-    //    the solve will need (L+_i on the top lane, U-_i on the bottom lane)
-    double x;
+    // 1. the two transforms, concurrently, each with its derivative
+    double x, dx = -1.0;
     if (role) {
       x = R[n - 1].D - lam;
-      if (go) P[(int64_t)(n - 1) * kPairSlots + c] = x;
+      if (go) {
+        P[(int64_t)(n - 1) * kPairSlots + c] = x;
+        W1[(int64_t)(n - 1) * kPairSlots + c] = dx;
+      }
     } else {
       x = -lam;
     }
+    bool gl;
     {
       // rows in two buffers of kHB: one is consumed while the other's loads
       // are in flight (prefetch distance kHB .. 2 kHB - 1 steps)
@@ -1867,27 +2077,29 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
       // wavefront.
       auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
       const double x0 = x;
-      auto pass = [&](auto G, bool gl) {
+      auto pass = [&](auto G, bool glp) {
         constexpr bool kG = decltype(G)::value;
         x = x0;
+        dx = -1.0;
         auto step = [&](int t, const Row3& rr) {
           if (t < T && go && t < n - 1) {
             const int row = role ? n - 2 - t : t;
             const double b = role ? rr.LLD : rr.D;
             const double f = role ? rr.D : rr.LLD;
-            // L+_i = LD_i / (D_i + s_i) (top), U-_i = L_i D_i / (LLD_i + p_{i+1}) (bottom)
             double w;
-            const double xn = xstep_bf<kG>(b, f, rr.LD, x, lam, pivmin, gl, w);
+            const double xn = xstep_bf<kG>(b, f, rr.LD, x, lam, pivmin, glp, w);
+            const double dxn = dstep(w, dx);
             const int64_t o = (int64_t)row * kPairSlots + c;
             X[o] = role ? xn : x;
-            Wr[o] = w;
+            Wr[o] = role ? dxn : dx;
             x = xn;
+            dx = dxn;
           }
         };
         pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
       };
       pass(std::false_type{}, false);
-      bool gl = go && !isfinite(x);
+      gl = go && !isfinite(x);
       // both transforms of a pair in one form; every lane reads its partner's
       // flag (a cross-lane read under the short circuit would run with the
       // flagged lanes switched off)
@@ -1895,113 +2107,74 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
       gl = gl || gp;
       if (__ballot(gl) != 0) pass(std::true_type{}, gl);
     }
-    if (go && !role) S[(int64_t)(n - 1) * kPairSlots + c] = x;
-    __syncthreads();  // S and P complete and visible to the partner lane
+    if (go && !role) {
+      S[(int64_t)(n - 1) * kPairSlots + c] = x;
+      W0[(int64_t)(n - 1) * kPairSlots + c] = dx;
+    }
+    __syncthreads();  // S, P and the derivatives complete and visible to the partner lane
     // 2. twist index: lane 2c scans k < h, lane 2c+1 scans k >= h
     const int h = n >> 1;
-    double gmin = INFINITY;
+    double gmin = INFINITY, dg = 0.0;
     int r = -1;
     {
       const int kb = role ? h : 0;
       const int kc = role ? n - h : h;
       int T2 = kc;
       for (int o = 32; o > 0; o >>= 1) T2 = max(T2, __shfl_xor(T2, o, 64));
-      pipelined(
+      pipelined<4>(
           T2,
           [&](int t) {
             const int64_t o = (int64_t)clamp_row(kb + t, n) * kPairSlots + c;
-            Pair2 v;
+            Quad v;
             v.s = S[o];
             v.p = P[o];
+            v.ds = W0[o];
+            v.dp = W1[o];
             return v;
           },
-          [&](int t, const Pair2& v) {
+          [&](int t, const Quad& v) {
             if (t < T2 && go && t < kc) {
               const double g = v.s + v.p + lam;
               if (isfinite(g) && fabs(g) < fabs(gmin)) {
                 gmin = g;
+                dg = v.ds + v.dp;
                 r = kb + t;
               }
             }
           });
       // the partner's candidate; ties go to the smaller index (the upper half)
       const double go_g = __shfl_xor(gmin, 1, 64);
+      const double go_d = __shfl_xor(dg, 1, 64);
       const int go_r = __shfl_xor(r, 1, 64);
       const double gt = role ? go_g : gmin, gb = role ? gmin : go_g;
+      const double dt = role ? go_d : dg, db = role ? dg : go_d;
       const int rt = role ? go_r : r, rb = role ? r : go_r;
       const bool take_b = (rb >= 0) && (rt < 0 || fabs(gb) < fabs(gt));
       gmin = take_b ? gb : gt;
+      dg = take_b ? db : dt;
       r = take_b ? rb : rt;
       if (r < 0) {
+        // no finite gamma: no norm either (the solve supplies it)
         r = 0;
         gmin = 0.0;
+        dg = NAN;
       }
     }
-    // 3. solves outward from the twist: z_i = -L+_i z_{i+1} upward (lane 2c),
-    //    z_{i+1} = -U-_i z_i downward (lane 2c+1); where a z is zero the row
-    //    of L D L^T - lam I gives the next one from the one before.  Rows are
-    //    visited in a wave-uniform order per role (top lanes from the largest
-    //    twist index of the wave down, bottom lanes from the smallest up), each
-    //    lane active on its own side of its twist, so every access is one
-    //    coalesced row of the work vector.
-    double nrm = 0.0, zbest = 0.0;
-    {
-      if (go && role) {
-        nrm = 1.0;
-        zbest = 1.0;
-      }
-      int rmax = (go && !role) ? r : 0;        // top lanes: rows rmax-1 .. 0
-      int rmin = (go && role) ? r : INT_MAX;   // bottom lanes: rows rmin .. n-2
-      for (int o = 32; o > 0; o >>= 1) {
-        rmax = max(rmax, __shfl_xor(rmax, o, 64));
-        rmin = min(rmin, __shfl_xor(rmin, o, 64));
-      }
-      if (rmin == INT_MAX) rmin = 0;  // no lane iterating: nothing to visit
-      int nb = (go && role) ? n - 1 - rmin : 0;
-      for (int o = 32; o > 0; o >>= 1) nb = max(nb, __shfl_xor(nb, o, 64));
-      const int T3 = max(rmax, nb);
-      const int base = role ? rmin : rmax - 1;
-      const int dir = role ? 1 : -1;
-      double zc = 1.0, zp = 0.0;
-      pipelined(
-          T3, [&](int t) { return Wr[(int64_t)clamp_row(base + dir * t, n) * kPairSlots + c]; },
-          [&](int t, double w) {
-            const int row = base + dir * t;
-            const bool on = role ? (row >= r && row < n - 1) : (row < r && row >= 0);
-            if (t < T3 && go && on) {
-              const bool first = role ? (row == r) : (row == r - 1);
-              double zn;
-              if (zc != 0.0 || first) {
-                zn = -w * zc;
-              } else if (zp != 0.0) {
-                const double ldi = R[row].LD;
-                const double ldn = R[row - dir].LD;
-                zn = (ldi != 0.0) ? -div_nr(ldn, ldi) * zp : 0.0;
-              } else {
-                zn = 0.0;  // an underflowed tail stays zero
-              }
-              zn = isfinite(zn) ? zn : 0.0;
-              const int zrow = role ? row + 1 : row;
-              Wr[(int64_t)zrow * kPairSlots + c] = zn;
-              zp = zc;
-              zc = zn;
-              nrm += zn * zn;
-              // largest magnitude, ties to the smaller row
-              if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
-            }
-          });
-      if (go && role) W1[(int64_t)r * kPairSlots + c] = 1.0;
-      // combine the halves: rows < r (lane 2c) and rows >= r (lane 2c+1)
-      const double nrm_o = __shfl_xor(nrm, 1, 64);
-      const double zb_o = __shfl_xor(zbest, 1, 64);
-      nrm += nrm_o;
-      const double zt = role ? zb_o : zbest, zb = role ? zbest : zb_o;
-      zbest = (fabs(zt) >= fabs(zb) && zt != 0.0) ? zt : zb;
+    // 3. ||z||^2 = -(d s_r + d p_r + 1); a pair without a finite value solves
+    double nrm = -(dg + 1.0);
+    const bool need = go && !(nrm < INFINITY);
+    if (__ballot(need) != 0) {
+      __syncthreads();  // the derivatives are read before z overwrites them
+      double ns, zb;
+      solve_stored<kPairSlots>(need, role, R, n, pivmin, gl, r, S, P, Wr, c, ns, zb);
+      nrm = need ? ns : nrm;
     }
-    __syncthreads();  // z complete before the next transform overwrites the work vectors
+    __syncthreads();  // the work vectors are read before the next transform overwrites them
     if (go) {
       rout = r;
-      rqi_commit(V, conv, last, it, n, gmin, nrm, zbest, lam);
+      lam_last = lam;
+      g_last = gl;
+      rqi_commit(V, conv, last, it, n, gmin, nrm, 1.0, lam);
     }
   }
   if (solve && !conv) V.lam_out = V.lam;
@@ -2064,7 +2237,18 @@ __global__ void __launch_bounds__(64, 2) k_vectors_stored(
   const bool solve = act && n > 1;
   int r = 0;
   if (act && n == 1 && role) W1[c] = 1.0;
-  r = pair_rqi_stored<kPairSlots>(solve, role, pool + nd.rep, n, nmax, blk.pivmin, S, Pv, W0, W1, cs, V);
+  double lam_last = V.lam;
+  bool g_last = false;
+  r = pair_rqi_stored<kPairSlots>(solve, role, pool + nd.rep, n, nmax, blk.pivmin, S, Pv, W0, W1, cs, V, lam_last,
+                                  g_last);
+  // the vector of the last round: z into W0 / W1, its largest entry for the sign
+  {
+    double nz, zb;
+    solve_stored<kPairSlots>(solve, role, pool + nd.rep, n, blk.pivmin, g_last, r, S, Pv, role ? W1 : W0, cs, nz,
+                             zb);
+    if (solve) V.zmaxv = zb;
+  }
+  __syncthreads();  // z complete before the transposed write reads it
   double scale = 1.0;
   if (solve) {
     scale = 1.0 / sqrt(V.nrm);
