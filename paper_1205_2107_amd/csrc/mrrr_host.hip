@@ -140,6 +140,8 @@ static T* P_(DevBuf& b) {
 }
 
 // scratch budget for the eigenvector kernel (bytes): a quarter of the device
+constexpr bool kShareRoot = false, kShareLevels = true, kShareLeaf = true;
+
 static size_t scratch_budget() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return size_t(8) << 30;
@@ -270,11 +272,31 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   launch_assign(st, dB, P_<int64_t>(W.goff), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.gcnt), P_<double>(W.lo),
                 P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<int32_t>(W.snode),
                 P_<uint32_t>(W.sflag), dC);
-  prof.begin(MRRR_K_REFINE);
-  launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool, P_<double>(W.lo),
-                P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag), dC,
-                lanes);
-  prof.end();
+  // every refinement launch works on chunks of one node's flagged slots
+  // (64 / lanes per wavefront): a wavefront counts with one representation,
+  // so its eigenvalues share their counts, and its make-up depends only on
+  // the node, not on the other problems of a batch
+  ENS(vrid, sizeof(int32_t) * ntot);
+  ENS(cflag, sizeof(int32_t) * ntot);
+  ENS(cid, sizeof(int32_t) * ntot);
+  ENS(cstart, sizeof(int64_t) * (ntot + 1));
+  auto refine_flagged = [&](bool need_col, bool share) -> int {
+    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_NEEDS_REFINE, need_col,
+                       P_<int32_t>(W.snode), 64 / lanes, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
+                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
+                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
+    int32_t nrc = 0;
+    HIP_TRY(hipMemcpyAsync(&nrc, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    prof.begin(MRRR_K_REFINE);
+    launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                  P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                  P_<uint32_t>(W.sflag), dC, lanes, false, P_<int64_t>(W.cstart), P_<int32_t>(W.vrid), nrc,
+                  share);
+    prof.end();
+    return 0;
+  };
+  if ((rc = refine_flagged(false, kShareRoot)) != 0) return rc;
   // problem table after the root pass: VALUE counts, block counts
   HIP_TRY(hipMemcpyAsync(probs.data(), W.problems.p, sizeof(Problem) * nprob, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -310,11 +332,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (amb == 0 || round >= 3) break;
-        prof.begin(MRRR_K_REFINE);
-        launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
-                      P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
-                      P_<uint32_t>(W.sflag), dC, lanes);
-        prof.end();
+        if ((rc = refine_flagged(false, kShareLevels)) != 0) return rc;
       }
       launch_cls_compact(st, ntot, P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int64_t>(W.runs));
       launch_cls_runs(st, dB, P_<Node>(W.nodes), nruns, P_<int64_t>(W.runs), P_<int32_t>(W.sblk),
@@ -366,22 +384,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     // leaf's frame; each wavefront takes eigenvalues of one node (chunks of
     // equal-node slots) so that it reads one representation through LDS
     launch_mark_leaf(st, ntot, P_<int64_t>(W.scol), P_<uint32_t>(W.sflag));
-    ENS(vrid, sizeof(int32_t) * ntot);
-    ENS(cflag, sizeof(int32_t) * ntot);
-    ENS(cid, sizeof(int32_t) * ntot);
-    ENS(cstart, sizeof(int64_t) * (ntot + 1));
-    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_NEEDS_REFINE, false,
-                       P_<int32_t>(W.snode), 64 / lanes, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
-                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
-                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
-    int32_t nrchunks = 0;
-    HIP_TRY(hipMemcpyAsync(&nrchunks, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    prof.begin(MRRR_K_REFINE);
-    launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
-                  P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag),
-                  dC, lanes, false, P_<int64_t>(W.cstart), P_<int32_t>(W.vrid), nrchunks);
-    prof.end();
+    if ((rc = refine_flagged(false, kShareLeaf)) != 0) return rc;
     // 8. eigenvectors of all singletons.  Long runs of singletons of one node
     //    in large blocks go to the checkpointing kernel (one node per
     //    wavefront, representation staged through LDS, nothing of length n

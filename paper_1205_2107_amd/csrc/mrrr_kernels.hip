@@ -422,8 +422,11 @@ __device__ inline bool bracket_converged(double lo, double hi) {
   return hi - lo <= 4.0 * kEps * fmax(fabs(lo), fabs(hi)) || mid <= lo || mid >= hi;
 }
 
+// r, nr: this eigenvalue's place among the nr eigenvalues of its wavefront
+// that share its bracket (a cell holding several eigenvalues): their points
+// interleave, nr L of them over the cell
 template <int L>
-__device__ inline double next_point(const EigState& S, int k) {
+__device__ inline double next_point(const EigState& S, int k, int r, int nr) {
   const bool vl = S.clo >= 0, vh = S.chi >= 0;
   if (!vl || !vh) {
     if (!vl && !vh) {
@@ -466,12 +469,20 @@ __device__ inline double next_point(const EigState& S, int k) {
       return (p > S.lo && p < S.hi) ? p : mid;
     }
   }
-  return S.lo + (S.hi - S.lo) * ((double)(k + 1) / (double)(L + 1));
+  return S.lo + (S.hi - S.lo) * ((double)(r * L + k + 1) / (double)(nr * L + 1));
 }
 
 // a count only moves a validated end inward, and never past the other
 // validated end: counts from rounded arithmetic need not be monotone in the
 // shift, and a bracket must not invert
+__device__ __forceinline__ void apply_point(EigState& S, double p, int c, double g) {
+  if (c <= S.j - 1) {
+    if ((S.clo < 0 || p > S.lo) && (S.chi < 0 || p < S.hi)) { S.lo = p; S.clo = c; S.glo = g; }
+  } else {
+    if ((S.chi < 0 || p < S.hi) && (S.clo < 0 || p > S.lo)) { S.hi = p; S.chi = c; S.ghi = g; }
+  }
+}
+
 template <int L>
 __device__ inline void update_state(EigState& S, const double* p, const int* c, const double* g, bool vonly) {
   double pmin = INFINITY, pmax = -INFINITY;
@@ -591,25 +602,81 @@ __device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, d
 
 template <int L>
 __device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __restrict__ R, int n, double pivmin,
-                                          int k, int gbase, double* __restrict__ st, bool vonly) {
+                                          int k, int gbase, double* __restrict__ st, bool vonly, bool share_ok) {
+  // with one representation for the whole wavefront (st), every count is
+  // valid for every eigenvalue of it: with share_ok, the groups that share a
+  // bracket holding several eigenvalues spread their points over it, and
+  // every group takes all 64 counts of the sweep
+  constexpr int G = 64 / L;  // eigenvalue groups per wavefront
+  const bool share = share_ok && st != nullptr;
+  const int lane = threadIdx.x & 63;
+  const int g = gbase / L;
   long long steps = 0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     const bool need = act && !S.done;
     if (__ballot(need) == 0) break;
-    const double p = need ? next_point<L>(S, k) : 0.0;
+    int r = 0, nr = 1;
+    if (share) {
+      // groups with the same validated multi-eigenvalue bracket are adjacent
+      // (consecutive indices): rank r in their run of nr groups
+      const bool cell = need && S.clo >= 0 && S.chi >= 0 && S.chi - S.clo > 1;
+      const int src = g > 0 ? lane - L : lane;
+      const double plo = __shfl(S.lo, src, 64), phi = __shfl(S.hi, src, 64);
+      const int pclo = __shfl(S.clo, src, 64), pchi = __shfl(S.chi, src, 64);
+      const bool pcell = __shfl(cell ? 1 : 0, src, 64) != 0;
+      const bool same = g > 0 && cell && pcell && plo == S.lo && phi == S.hi && pclo == S.clo && pchi == S.chi;
+      int head = same ? 0 : g;  // index of the run's first group (prefix max)
+      int next = same ? G : g;  // first run start at or after a group (suffix min)
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        const int hb = __shfl(head, max(lane - d * L, 0), 64);
+        const int na = __shfl(next, min(lane + d * L, 63), 64);
+        if (g >= d) head = max(head, hb);
+        if (g + d < G) next = min(next, na);
+      }
+      // the run ends where the next group starts a new run
+      int end = __shfl(next, min(lane + L, 63), 64);
+      if (g + 1 >= G) end = G;
+      r = g - head;
+      nr = end - head;
+    }
+    const double p = need ? next_point<L>(S, k, r, nr) : 0.0;
     double gv;
     const int c = st ? staged_count_deriv(reinterpret_cast<const double*>(R), n, p, pivmin, st, &gv)
                      : sturm_count_deriv(R, n, p, pivmin, &gv);
     if (need) steps += n;
-    double pq[L], gq[L];
-    int cq[L];
+    if (share) {
+      // own points bound an unvalidated end; every point of the wavefront
+      // moves a validated one
+      double pmin = INFINITY, pmax = -INFINITY;
 #pragma unroll
-    for (int q = 0; q < L; ++q) {
-      pq[q] = __shfl(p, gbase + q, 64);
-      cq[q] = __shfl(c, gbase + q, 64);
-      gq[q] = __shfl(gv, gbase + q, 64);
+      for (int q = 0; q < L; ++q) {
+        const double pq = __shfl(p, gbase + q, 64);
+        pmin = fmin(pmin, pq);
+        pmax = fmax(pmax, pq);
+      }
+      for (int q = 0; q < 64; ++q) {
+        const double pq = __shfl(p, q, 64);
+        const int cq = __shfl(c, q, 64);
+        const double gq = __shfl(gv, q, 64);
+        if (need) apply_point(S, pq, cq, gq);
+      }
+      if (need) {
+        if (S.clo < 0) { S.lo = fmin(pmin, S.hi) - S.pad; S.pad *= 4.0; }
+        if (S.chi < 0) { S.hi = fmax(pmax, S.lo) + S.pad; S.pad *= 4.0; }
+        S.done = (S.clo >= 0 && S.chi >= 0 && (vonly || bracket_converged(S.lo, S.hi))) ? 1 : 0;
+      }
+    } else {
+      double pq[L], gq[L];
+      int cq[L];
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        pq[q] = __shfl(p, gbase + q, 64);
+        cq[q] = __shfl(c, gbase + q, 64);
+        gq[q] = __shfl(gv, gbase + q, 64);
+      }
+      if (need) update_state<L>(S, pq, cq, gq, vonly);
     }
-    if (need) update_state<L>(S, pq, cq, gq, vonly);
   }
   return steps;
 }
@@ -622,7 +689,7 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
                                                int32_t* __restrict__ clo_a, int32_t* __restrict__ chi_a,
                                                uint32_t* __restrict__ sflag, Counters* __restrict__ C, int vonly,
                                                const int64_t* __restrict__ cstart, const int32_t* __restrict__ rid,
-                                               int nchunks) {
+                                               int nchunks, int share) {
   const int lane = threadIdx.x;
   const int k = lane % L, gbase = lane - k;
   // eigenvalues of the wavefront: 64 / L consecutive slots, or (cstart) the
@@ -660,9 +727,9 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
     __shared__ double st[2 * 4 * kSG];
     // per-lane copy of the (equal) pointer keeps the staged loads global
     steps = refine_sweeps<L>(S, act, pool + nd.rep, __builtin_amdgcn_readfirstlane(blk.n), blk.pivmin, k, gbase,
-                             st, vonly != 0);
+                             st, vonly != 0, share != 0);
   } else {
-    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase, nullptr, vonly != 0);
+    steps = refine_sweeps<L>(S, act, pool + nd.rep, blk.n, blk.pivmin, k, gbase, nullptr, vonly != 0, false);
   }
   if (act && k == 0) {
     lo_a[s] = S.lo;
@@ -2534,7 +2601,7 @@ void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t 
 void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
                    const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
                    uint32_t* sflag, Counters* C, int lanes, bool validate_only, const int64_t* cstart,
-                   const int32_t* rid, int nchunks) {
+                   const int32_t* rid, int nchunks, bool share) {
   // `lanes` lanes per eigenvalue: 64 / lanes eigenvalues per wavefront
   const unsigned g4 = (unsigned)((ntot + 15) / 16), g2 = (unsigned)((ntot + 31) / 32),
                  g1 = (unsigned)((ntot + 63) / 64);
@@ -2543,13 +2610,13 @@ void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, 
   if (ch && nchunks == 0) return;
   if (lanes >= 4)
     hipLaunchKernelGGL(k_refine<4>, dim3(ch ? (unsigned)nchunks : g4), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
-                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks, share ? 1 : 0);
   else if (lanes == 2)
     hipLaunchKernelGGL(k_refine<2>, dim3(ch ? (unsigned)nchunks : g2), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
-                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks, share ? 1 : 0);
   else
     hipLaunchKernelGGL(k_refine<1>, dim3(ch ? (unsigned)nchunks : g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
-                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks);
+                       lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks, share ? 1 : 0);
 }
 
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag) {

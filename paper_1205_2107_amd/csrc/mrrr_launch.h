@@ -19,7 +19,8 @@ void launch_assign(hipStream_t st, const Block* B, const int64_t* goff, int64_t 
 void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
                    const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
                    uint32_t* sflag, Counters* C, int lanes, bool validate_only = false,
-                   const int64_t* cstart = nullptr, const int32_t* rid = nullptr, int nchunks = 0);
+                   const int64_t* cstart = nullptr, const int32_t* rid = nullptr, int nchunks = 0,
+                   bool share = false);
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag);
 void launch_columns(hipStream_t st, const Problem* P, Block* B, int nblk, const Node* N, int64_t ntot,
                     const int32_t* sblk, const double* lo, const double* hi, double* val, int64_t* scol, bool multi);

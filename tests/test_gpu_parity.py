@@ -242,7 +242,7 @@ def gpu_metrics(d, e, w, Z):
 # matrix also holds pairs of eigenvalues equal to the last bit inside clusters
 # of ~950 whose child representations can only be had with large element
 # growth (LAPACK's dstemr stops on it without a suitable representation): the
-# residual bound holds, orthogonality is allowed 50 n eps there.
+# residual bound holds, orthogonality (about 15 n eps) is allowed 20 n eps there.
 @pytest.mark.parametrize("kind", ["random", "toeplitz", "geometric", "glued_1"])
 def test_full_size_n20000(M, kind):
     n = 20000
@@ -261,7 +261,7 @@ def test_full_size_n20000(M, kind):
     wn = w.cpu().numpy()
     assert np.all(np.diff(wn) >= 0)
     r, o = gpu_metrics(d, e, w, Z)
-    assert r <= 10.0 and o <= (50.0 if kind == "glued_1" else 10.0)
+    assert r <= 10.0 and o <= (20.0 if kind == "glued_1" else 10.0)
     tol = eig_tol(d, e)
     idx = np.unique(np.r_[1, 2, n // 3, n // 2, n - 1, n, np.random.default_rng(0).integers(1, n + 1, 14)])
     for j in idx:
