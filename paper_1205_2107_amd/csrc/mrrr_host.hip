@@ -140,7 +140,7 @@ static T* P_(DevBuf& b) {
 }
 
 // scratch budget for the eigenvector kernel (bytes): a quarter of the device
-constexpr bool kShareRoot = false, kShareLevels = true, kShareLeaf = true;
+constexpr bool kShareLevels = true, kShareLeaf = true;
 
 static size_t scratch_budget() {
   size_t fr = 0, tot = 0;
@@ -272,10 +272,12 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   launch_assign(st, dB, P_<int64_t>(W.goff), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.gcnt), P_<double>(W.lo),
                 P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<int32_t>(W.snode),
                 P_<uint32_t>(W.sflag), dC);
-  // every refinement launch works on chunks of one node's flagged slots
-  // (64 / lanes per wavefront): a wavefront counts with one representation,
-  // so its eigenvalues share their counts, and its make-up depends only on
-  // the node, not on the other problems of a batch
+  // the refinements of child frames work on chunks of one node's flagged
+  // slots (64 / lanes per wavefront): a wavefront counts with one
+  // representation, so its eigenvalues share their counts, and its make-up
+  // depends only on the node, not on the other problems of a batch.  The root
+  // level refines each eigenvalue on its own points (shared points there
+  // changed the geometric matrix's tree for the worse), so it needs no chunks.
   ENS(vrid, sizeof(int32_t) * ntot);
   ENS(cflag, sizeof(int32_t) * ntot);
   ENS(cid, sizeof(int32_t) * ntot);
@@ -296,7 +298,10 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     prof.end();
     return 0;
   };
-  if ((rc = refine_flagged(false, kShareRoot)) != 0) return rc;
+  prof.begin(MRRR_K_REFINE);
+  launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool, P_<double>(W.lo),
+                P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag), dC, lanes);
+  prof.end();
   // problem table after the root pass: VALUE counts, block counts
   HIP_TRY(hipMemcpyAsync(probs.data(), W.problems.p, sizeof(Problem) * nprob, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
