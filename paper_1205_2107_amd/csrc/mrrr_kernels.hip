@@ -1260,10 +1260,12 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
   // resid / gap bounds the sine of the angle between z and the eigenvector
   // (gap theorem); otherwise stop once the correction is below half an ulp
-  // of lambda.  At the rounding floor (a solve without a smaller residual,
-  // or the iteration cap) the solve with the smallest residual is repeated,
-  // unless it is the current one.
+  // of lambda.  At the rounding floor (a solve that does not halve the
+  // smallest residual so far: away from the floor the iteration converges
+  // much faster than that; or the iteration cap) the solve with the smallest
+  // residual is kept: the current one if it is that, else it is repeated.
   const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
+  const bool progress = resid < 0.5 * V.resid;
   const bool improved = resid < V.resid;
   if (improved) {
     V.resid = resid;
@@ -1274,7 +1276,7 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   if (last || small) {
     conv = true;
     V.lam_out = inside ? lamc : lam;
-  } else if (V.stall >= 1 || it + 1 >= kMaxRqi) {
+  } else if (!progress || it + 1 >= kMaxRqi) {
     V.fallback = true;
     if (improved) {
       conv = true;
@@ -1745,6 +1747,7 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
                                double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
+  bool sticky = false;  // the pair needed the guarded form in an earlier round
   int rout = 0;
   const double dn = R[n - 1].D;
   for (int it = 0; it <= kMaxRqi; ++it) {
@@ -1757,26 +1760,36 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
     //    special-case rule are no-ops, so the first pass runs without them; a
     //    lane that ends with a non-finite value makes the wavefront repeat the
     //    pass with both, and the recomputations of this round follow the pass
-    //    that was kept.
+    //    that was kept.  A pair that needed the guard once (a shift at an
+    //    eigenvalue of a leading or trailing submatrix) keeps it: its later
+    //    rounds start in the guarded form, in which the other pairs' steps
+    //    are the fast ones.
     const double x0 = role ? xlast : -lam;
-    bool any_guard = false, gl = false;  // the lane's transform needed the guarded form
+    bool any_guard = false, gl = false;  // the lane's kept pass is the guarded form
     double gmin;
     int r;
     {
-      const double x = transform_twist<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, xlast, SC, PC, DS,
-                                                          DP, c, lds, gmin, r);
-      gl = go && !isfinite(x);
+      const bool gs = go && sticky;
+      const bool pre = __ballot(gs) != 0;
+      const double x =
+          pre ? transform_twist<kPairSlots, true>(go, role, R, n, pivmin, gs, lam, x0, xlast, SC, PC, DS, DP, c, lds,
+                                                  gmin, r)
+              : transform_twist<kPairSlots, false>(go, role, R, n, pivmin, false, lam, x0, xlast, SC, PC, DS, DP, c,
+                                                   lds, gmin, r);
+      bool gn = go && !gs && !isfinite(x);
       // the pair's two lanes share the guard: the checkpoints of both are
       // recomputed; every lane reads its partner's flag (a cross-lane read
       // under the short circuit would run with the flagged lanes switched off)
-      const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
-      gl = gl || gp;
+      const bool gp = __shfl_xor(gn ? 1 : 0, 1, 64) != 0;
+      gn = gn || gp;
+      gl = gs || gn;
       any_guard = __ballot(gl) != 0;
-      if (any_guard) {
+      if (__ballot(gn) != 0) {
         __syncthreads();  // the first pass's checkpoints are read before they are rewritten
         transform_twist<kPairSlots, true>(go, role, R, n, pivmin, gl, lam, x0, xlast, SC, PC, DS, DP, c, lds, gmin,
                                           r);
       }
+      sticky = sticky || gl;
     }
     __syncthreads();  // checkpoints complete and visible to the partner lane
     // 3. ||z||^2 = -(d s_r + d p_r + 1); a pair without a finite value solves
@@ -2112,6 +2125,7 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
                                       double* __restrict__ W1, int c, VecState& V, double& lam_last, bool& g_last) {
   bool conv = !solve;
   bool last = false;
+  bool sticky = false;  // the pair needed the guarded form in an earlier round
   int rout = 0;
   // wave-uniform trip counts
   int T = n - 1;
@@ -2141,7 +2155,8 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
       // with a non-finite value (a zero or overflowing pivot) repeats its
       // transform in the guarded form, the other lanes repeat theirs
       // unchanged, so each eigenvector's values do not depend on its
-      // wavefront.
+      // wavefront.  A pair that needed the guard once starts its later
+      // rounds in the guarded form.
       auto rowof = [&](int t) { return clamp_row(role ? n - 2 - t : t, n); };
       const double x0 = x;
       auto pass = [&](auto G, bool glp) {
@@ -2165,14 +2180,20 @@ __device__ inline int pair_rqi_stored(bool solve, int role, const Rep* __restric
         };
         pipelined(T, [&](int t) { return load_row3(R, rowof(t)); }, step);
       };
-      pass(std::false_type{}, false);
-      gl = go && !isfinite(x);
+      const bool gs = go && sticky;
+      if (__ballot(gs) != 0)
+        pass(std::true_type{}, gs);
+      else
+        pass(std::false_type{}, false);
+      bool gn = go && !gs && !isfinite(x);
       // both transforms of a pair in one form; every lane reads its partner's
       // flag (a cross-lane read under the short circuit would run with the
       // flagged lanes switched off)
-      const bool gp = __shfl_xor(gl ? 1 : 0, 1, 64) != 0;
-      gl = gl || gp;
-      if (__ballot(gl) != 0) pass(std::true_type{}, gl);
+      const bool gp = __shfl_xor(gn ? 1 : 0, 1, 64) != 0;
+      gn = gn || gp;
+      gl = gs || gn;
+      if (__ballot(gn) != 0) pass(std::true_type{}, gl);
+      sticky = sticky || gl;
     }
     if (go && !role) {
       S[(int64_t)(n - 1) * kPairSlots + c] = x;
