@@ -146,12 +146,15 @@ typedef struct {
   int32_t refine_wave_slots; /* eigenvalues per wavefront in refinement (0 = automatic, 16, 32 or 64) */
   int32_t vec_wave_slots;  /* eigenvectors per wavefront (0 = automatic, 8, 16 or 32) */
   /* eigenvector kernel choice: runs of at least this many singletons of one
-   * representation (in blocks of 4096 rows or more) go to the checkpointing
+   * representation (in blocks of vec_ckpt_min_n rows or more) go to the checkpointing
    * kernel, the rest to the stored-vector kernel.  0 = automatic (16), -1 =
    * stored-vector kernel only, else 1 .. 2^30.  Both kernels give bit-identical
    * results; this only moves work between them. */
   int32_t vec_ckpt_min_run;
-  int32_t reserved[4];
+  /* ... and the block order from which that applies: 0 = automatic, else
+   * 64 .. 2^30. */
+  int32_t vec_ckpt_min_n;
+  int32_t reserved[3];
 } mrrr_tuning;
 
 int mrrr_get_tuning(mrrr_tuning* t);

@@ -242,10 +242,12 @@ def get_tuning():
     t = MrrrTuning()
     _lib.check(_lib.load().mrrr_get_tuning(ctypes.byref(t)))
     return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
-            "vec_wave_slots": t.vec_wave_slots, "vec_ckpt_min_run": t.vec_ckpt_min_run}
+            "vec_wave_slots": t.vec_wave_slots, "vec_ckpt_min_run": t.vec_ckpt_min_run,
+            "vec_ckpt_min_n": t.vec_ckpt_min_n}
 
 
-def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, vec_ckpt_min_run=None):
+def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, vec_ckpt_min_run=None,
+               vec_ckpt_min_n=None):
     t = MrrrTuning()
     lib = _lib.load()
     _lib.check(lib.mrrr_get_tuning(ctypes.byref(t)))
@@ -257,6 +259,8 @@ def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, v
         t.vec_wave_slots = int(vec_wave_slots)
     if vec_ckpt_min_run is not None:
         t.vec_ckpt_min_run = int(vec_ckpt_min_run)
+    if vec_ckpt_min_n is not None:
+        t.vec_ckpt_min_n = int(vec_ckpt_min_n)
     if lib.mrrr_set_tuning(ctypes.byref(t)) != 0:
         raise ValueError("tuning value out of range")
 

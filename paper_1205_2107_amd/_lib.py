@@ -36,7 +36,7 @@ class MrrrInfo(ctypes.Structure):
 class MrrrTuning(ctypes.Structure):
     _fields_ = [("grid_density", ctypes.c_int32), ("refine_wave_slots", ctypes.c_int32),
                 ("vec_wave_slots", ctypes.c_int32), ("vec_ckpt_min_run", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("vec_ckpt_min_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class MrrrKernelTime(ctypes.Structure):

@@ -32,7 +32,7 @@ constexpr int kChildSpecAll = 16;        // ... branch-free form with few cluste
 constexpr int64_t kChildAllMaxN = 1 << 22;     // every-candidate form only below this block order
 constexpr int64_t kChildAllMaxRows = 1 << 25;  // ... and while its regions take at most this many rows
 constexpr int kCkptMinRun = 16;          // checkpointing eigenvector kernel: equal-node run length ...
-constexpr int kCkptMinN = 4096;          // ... and block order from which it is used
+constexpr int kCkptMinN = 256;           // ... and block order from which it is used
 
 // slot flags
 constexpr uint32_t F_NEEDS_REFINE = 1u;   // bracket must be (re)validated/refined

@@ -39,7 +39,7 @@ void prof_add(int kernel, int64_t launches, double ms, double work, double bytes
   g_prof[kernel].bytes += bytes;
 }
 
-static mrrr_tuning g_tune = {4, 0, 0, 0, {0, 0, 0, 0}};
+static mrrr_tuning g_tune = {4, 0, 0, 0, 0, {0, 0, 0}};
 static std::mutex g_tune_mu;
 
 static int fail(int code, const char* fmt, ...) {
@@ -409,8 +409,9 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
                        P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
     const int min_run = tune.vec_ckpt_min_run == 0 ? kCkptMinRun
                         : (tune.vec_ckpt_min_run < 0 ? INT_MAX : tune.vec_ckpt_min_run);
+    const int min_n = tune.vec_ckpt_min_n > 0 ? tune.vec_ckpt_min_n : kCkptMinN;
     launch_mark_ckpt(st, ntot, dB, P_<int32_t>(W.sblk), P_<int32_t>(W.vrid), P_<int64_t>(W.runs), min_run,
-                     kCkptMinN, P_<uint32_t>(W.sflag));
+                     min_n, P_<uint32_t>(W.sflag));
     launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_SINGLETON | F_CKPT, true,
                        P_<int32_t>(W.snode), vslots, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
                        P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
@@ -822,6 +823,7 @@ int mrrr_set_tuning(const mrrr_tuning* t) {
   if (!(t->vec_wave_slots == 0 || t->vec_wave_slots == 8 || t->vec_wave_slots == 16 || t->vec_wave_slots == 32))
     return -1;
   if (t->vec_ckpt_min_run < -1 || t->vec_ckpt_min_run > (1 << 30)) return -1;
+  if (t->vec_ckpt_min_n != 0 && (t->vec_ckpt_min_n < 64 || t->vec_ckpt_min_n > (1 << 30))) return -1;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = *t;
   return 0;

@@ -70,3 +70,9 @@ def test_tuning_roundtrip():
     for ok in (-1, 1, 0):
         t.vec_ckpt_min_run = ok
         assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0
+    for bad in (-1, 1, 63, (1 << 30) + 1):
+        t.vec_ckpt_min_n = bad
+        assert lib.mrrr_set_tuning(ctypes.byref(t)) == -1
+    for ok in (64, 4096, 0):
+        t.vec_ckpt_min_n = ok
+        assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0

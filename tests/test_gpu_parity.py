@@ -432,6 +432,33 @@ def test_checkpointing_and_stored_vector_kernels_agree(M):
         M.set_tuning(**old)
 
 
+def test_checkpointing_kernel_on_small_blocks(M):
+    # the checkpointing eigenvector kernel on blocks far below its default
+    # size threshold (few segments, a middle segment near the top) agrees bit
+    # for bit with the stored-vector kernel, and with the oracle
+    probs = [p for p in batched_problems(40, 4303, nmax=600) if p[0].shape[0] >= 64]
+    d, e, ns, off = W.pack(probs)
+    dt, et = torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda")
+    old = M.get_tuning()
+    try:
+        M.set_tuning(vec_ckpt_min_run=1, vec_ckpt_min_n=64)
+        M.profile(True)
+        w0, Z0, zoff0 = M.eigh_tridiagonal_batched(dt, et, ns)
+        ran = M.profile_read()["vectors_ckpt"]["launches"]
+        M.profile(False)
+        assert ran > 0
+        M.set_tuning(vec_ckpt_min_run=-1, vec_ckpt_min_n=0)
+        w1, Z1, zoff1 = M.eigh_tridiagonal_batched(dt, et, ns)
+    finally:
+        M.set_tuning(**old)
+    assert torch.equal(w0, w1) and torch.equal(Z0, Z1)
+    wn = w0.cpu().numpy()
+    for b, p in enumerate(probs):
+        nb = p[0].shape[0]
+        wo, Zo, st = oracle.mrrr(p[0], p[1])
+        assert np.abs(wn[off[b]:off[b] + nb] - wo).max() <= eig_tol(p[0], p[1])
+
+
 def test_autotune_batched(M):
     probs = batched_problems(64, 4202, nmax=600)
     d, e, ns, off = W.pack(probs)
