@@ -164,14 +164,15 @@ int mrrr_set_tuning(const mrrr_tuning* t); /* -1 on out-of-range fields */
 /* Autotuner of the batched form (a schedule choice, not part of the method).
  * Solves the batch described exactly as for mrrr_step_batched several times
  * with different launch shapes -- eigenvectors per wavefront, eigenvalues per
- * refinement wavefront, count-grid density -- by a coordinate search, timing
+ * refinement wavefront, count-grid density, the run length from which the
+ * checkpointing eigenvector kernel takes singletons -- by a coordinate search, timing
  * each synchronised solve on the host clock, and stores the fastest shape in a
  * process-wide cache keyed by the batch's size histogram (problem counts per
  * power-of-two size class, counts rounded to powers of two).  Later
  * mrrr_step_batched calls whose batch has the same key use the cached shape;
  * other calls use the global tuning.  w and Z receive the results of the last
  * trial (a valid solve).  best (may be NULL) receives the chosen shape.
- * Costs about ten solves of the batch.  Returns 0 or a status / negative
+ * Costs about twelve solves of the batch.  Returns 0 or a status / negative
  * argument code as mrrr_step_batched. */
 int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* off_host, const double* d,
                           const double* e, double* w, double* Z, const int64_t* zoff_host, mrrr_tuning* best,

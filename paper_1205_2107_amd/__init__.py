@@ -148,7 +148,7 @@ def autotune_batched(d, e, sizes, stream=None):
                                    _stream_ptr(stream))
     _lib.check(rc)
     return {"grid_density": t.grid_density, "refine_wave_slots": t.refine_wave_slots,
-            "vec_wave_slots": t.vec_wave_slots}
+            "vec_wave_slots": t.vec_wave_slots, "vec_ckpt_min_run": t.vec_ckpt_min_run}
 
 
 def _colmajor(X, n):

@@ -777,6 +777,7 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
   }
   if (cur.refine_wave_slots == 0) cur.refine_wave_slots = (tot <= 32768) ? 16 : (tot <= 131072 ? 32 : 64);
   if (cur.vec_wave_slots == 0) cur.vec_wave_slots = 32;
+  if (cur.vec_ckpt_min_run == 0) cur.vec_ckpt_min_run = kCkptMinRun;
   double best_ms = 0.0;
   int rc = run(cur, &best_ms);  // grows the workspace
   if (rc != 0) return rc;
@@ -784,11 +785,15 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
   const int vec_c[] = {32, 16, 8};
   const int ref_c[] = {16, 32, 64};
   const int grid_c[] = {2, 4, 8};
-  for (int param = 0; param < 3; ++param) {
-    const int* cand = param == 0 ? vec_c : (param == 1 ? ref_c : grid_c);
+  const int run_c[] = {16, 8, 4};  // equal-node run length for the checkpointing eigenvector kernel
+  for (int param = 0; param < 4; ++param) {
+    const int* cand = param == 0 ? vec_c : (param == 1 ? ref_c : (param == 2 ? grid_c : run_c));
     for (int k = 0; k < 3; ++k) {
       mrrr_tuning t = cur;
-      int* field = param == 0 ? &t.vec_wave_slots : (param == 1 ? &t.refine_wave_slots : &t.grid_density);
+      int* field = param == 0   ? &t.vec_wave_slots
+                   : param == 1 ? &t.refine_wave_slots
+                   : param == 2 ? &t.grid_density
+                                : &t.vec_ckpt_min_run;
       if (*field == cand[k]) continue;
       *field = cand[k];
       double ms = 0.0;
