@@ -371,6 +371,33 @@ def test_batched_vs_oracle_and_looped(M):
         assert np.array_equal(Z, Zl)
 
 
+def test_batched_degenerate_members(M):
+    # orders 1 and 2, a diagonal member (all off-diagonals zero), a member
+    # that splits into several blocks and ordinary ones in one batched call:
+    # each member equals its single-problem call bit for bit and meets the
+    # oracle's bounds
+    probs = [(np.array([2.5]), np.zeros(0)), (np.array([1.0, 1.0]), np.array([1.0])),
+             (np.array([-3.0]), np.zeros(0)), W.random_uniform(37, 11),
+             (np.array([4.0, -4.0]), np.array([0.0])), split_matrix(), W.toeplitz(64),
+             (np.array([0.0]), np.zeros(0)), (np.array([2.0, -1.0, 2.0, 0.5]), np.zeros(3))]
+    d, e, ns, off = W.pack(probs)
+    wb, Zb, zoff, infos = M.eigh_tridiagonal_batched(torch.tensor(d, device="cuda"),
+                                                      torch.tensor(e, device="cuda"), ns, return_info=True)
+    wb = wb.cpu().numpy()
+    Zb = Zb.cpu().numpy()
+    for b, p in enumerate(probs):
+        nb = int(ns[b])
+        w = wb[off[b]:off[b] + nb]
+        Z = Zb[zoff[b]:zoff[b] + nb * nb].reshape(nb, nb).T
+        wl, Zl, _ = gpu_solve(M, p[0], p[1])
+        assert np.array_equal(w, wl), b
+        assert np.array_equal(Z, Zl), b
+        wo, Zo, st = oracle.mrrr(p[0], p[1])
+        assert_parity(p[0], p[1], w, Z, wo, Zo)
+    assert wb[off[0]] == 2.5 and wb[off[2]] == -3.0 and wb[off[7]] == 0.0
+    assert np.array_equal(wb[off[4]:off[4] + 2], [-4.0, 4.0])
+
+
 def test_batched_c4_shape(M):
     # the benchmark's batch mix (4096 problems, sizes in [32, 2048]) on a sample of 256
     probs = W.batched_mix(256, W.SEEDS["c4"])
