@@ -139,6 +139,20 @@ def test_subsets_vs_oracle(M, case):
     assert_parity(d, e, w, Z, wo, Zo, full_w=wall, sel=sel)
 
 
+def test_empty_value_ranges(M):
+    # (vl, vu] beyond the spectrum, and inside the gap between two consecutive
+    # eigenvalues: no eigenpairs, no error, like the oracle
+    d, e = W.random_uniform(500, 77)
+    wall = oracle.mrrr(d, e, vectors=False)[0]
+    k = int(np.argmax(np.diff(wall)))
+    g = wall[k + 1] - wall[k]
+    for vl, vu in [(5.0, 6.0), (wall[k] + 0.25 * g, wall[k] + 0.75 * g), (-7.0, wall[0] - 0.5)]:
+        w, Z, info = gpu_solve(M, d, e, select="v", vl=vl, vu=vu)
+        wo, Zo, st = oracle_solve(d, e, select="v", vl=vl, vu=vu)
+        assert info["status"] == 0 and info["m"] == 0
+        assert w.shape == (0,) and Z.shape == (500, 0) and len(wo) == 0
+
+
 def split_matrix():
     rng = np.random.default_rng(5)
     n = 300
