@@ -217,6 +217,47 @@ def test_scaling_is_exact(M, s):
     assert np.array_equal(Zs, Z)
 
 
+def test_caller_streams_and_threads(M):
+    # work is ordered on the caller's stream (a non-default one here), and
+    # calls from several host threads, each on its own stream, are serialized
+    # by the library: every result equals the default-stream call bit for bit
+    import threading
+    mats = [W.random_uniform(700, 21), W.toeplitz(600), W.glued_wilkinson(500, 23), W.geometric(650, 24)]
+    ref = [gpu_solve(M, d, e)[:2] for d, e in mats]
+    s = torch.cuda.Stream()
+    dt = torch.tensor(mats[0][0], device="cuda")
+    et = torch.tensor(mats[0][1], device="cuda")
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        w, Z = M.eigh_tridiagonal(dt, et, stream=s)
+        w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    assert np.array_equal(w, ref[0][0]) and np.array_equal(Z, ref[0][1])
+    out = [None] * len(mats)
+    errors = []
+
+    def run(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for _ in range(2):
+                    d = torch.tensor(mats[k][0], device="cuda")
+                    e = torch.tensor(mats[k][1], device="cuda")
+                    wk, Zk = M.eigh_tridiagonal(d, e, stream=st)
+                    out[k] = (wk.cpu().numpy(), Zk.cpu().numpy())
+        except Exception as ex:  # reported in the main thread
+            errors.append(ex)
+
+    threads = [threading.Thread(target=run, args=(k,)) for k in range(len(mats))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    for k in range(len(mats)):
+        assert np.array_equal(out[k][0], ref[k][0]) and np.array_equal(out[k][1], ref[k][1]), k
+
+
 def test_repeatable(M):
     d, e = W.random_uniform(777, 9)
     a = gpu_solve(M, d, e)
