@@ -54,6 +54,30 @@ def test_host_side_argument_checks():
     assert lib.mrrr_step_backward(-1, None, None, 1, None, None, 1, None, None, None) == -1
 
 
+def test_batched_host_side_argument_checks():
+    """the batched entry point rejects bad sizes and offsets on the host, before
+    any device work, and leaves a message for the calling thread"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    I64 = ctypes.c_int64
+    ns = (I64 * 3)(4, 0, 5)
+    off = (I64 * 3)(0, 4, 4)
+    assert lib.mrrr_step_batched(-1, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.mrrr_step_batched(0, None, None, None, None, None, None, None, None, None) == 0
+    assert lib.mrrr_step_batched(3, None, off, fake, fake, fake, None, None, None, None) == -2
+    assert lib.mrrr_step_batched(3, ns, None, fake, fake, fake, None, None, None, None) == -3
+    assert lib.mrrr_step_batched(3, ns, off, None, fake, fake, None, None, None, None) == -4
+    assert lib.mrrr_step_batched(3, ns, off, fake, fake, None, None, None, None, None) == -6
+    assert lib.mrrr_step_batched(3, ns, off, fake, fake, fake, fake, None, None, None) == -8
+    assert lib.mrrr_step_batched(3, ns, off, fake, fake, fake, None, None, None, None) == -2
+    assert b"n_host[1]" in lib.mrrr_last_error()
+    ns[1] = 2
+    off[2] = -6
+    assert lib.mrrr_step_batched(3, ns, off, fake, fake, fake, None, None, None, None) == -3
+    assert b"off_host[2]" in lib.mrrr_last_error()
+
+
 def test_tuning_roundtrip():
     from paper_1205_2107_amd import _lib
     lib = _lib.load()
