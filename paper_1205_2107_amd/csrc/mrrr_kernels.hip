@@ -1259,12 +1259,13 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   const double slack = 0.25 * V.gap;
   const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
   // resid / gap bounds the sine of the angle between z and the eigenvector
-  // (gap theorem); otherwise stop once the correction is below half an ulp
-  // of lambda.  At the rounding floor (a solve that does not halve the
+  // (gap theorem); otherwise stop once the correction is within 2 eps |lambda|
+  // (two to four ulps: a further solve would only move lambda by rounding;
+  // LAPACK's dlarrv uses the same tolerance).  At the rounding floor (a solve that does not halve the
   // smallest residual so far: away from the floor the iteration converges
   // much faster than that; or the iteration cap) the solve with the smallest
   // residual is kept: the current one if it is that, else it is repeated.
-  const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 0.5 * kEps * fabs(lam);
+  const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 2.0 * kEps * fabs(lam);
   const bool progress = resid < 0.5 * V.resid;
   const bool improved = resid < V.resid;
   if (improved) {
