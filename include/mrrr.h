@@ -75,6 +75,9 @@ typedef struct {
 #define MRRR_CNT_CHILD_REJECT 8  /* clusters whose child failed the growth bound */
 #define MRRR_CNT_WORKSPACE_MB 9  /* device workspace in use after the call */
 #define MRRR_CNT_WAVE_SOLVES 10  /* twisted-factorization rounds summed over wavefronts (lockstep cost) */
+#define MRRR_CNT_POOL_ROWS 11    /* representation rows in use (roots, children, speculative candidates) */
+#define MRRR_CNT_AMBIGUOUS_LEFT 12 /* adjacent pairs classified from unrefined brackets after three refinements */
+#define MRRR_CNT_WORKSPACE_BYTES 13 /* device workspace bytes in use after the call (carved bytes with `work`) */
 
 /*
  * mrrr_step -- eigenpairs of one tridiagonal (Stage 4, STEP).
@@ -94,6 +97,69 @@ typedef struct {
  */
 int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
               int64_t ldz, mrrr_info* info, void* stream);
+
+/*
+ * mrrr_workspace_size -- bytes of caller workspace for mrrr_step_ws on a
+ * problem of order n and this range: the per-row arrays (slots, count grid,
+ * node table, cluster list), the root representations plus room for child
+ * representations of n rows each (MRRR_WS_CHILD_ROWS_PER_N * n rows beyond
+ * the speculative candidates of one level), and the eigenvector scratch for
+ * every wanted pair at once.  A smaller workspace also works down to a floor
+ * the solver checks as it goes: the eigenvector phase then runs in several
+ * launches, and a tree whose representations do not fit returns status
+ * MRRR_ERR_CAPACITY.  Host-only (no device work, no allocation).  Returns 0
+ * for an invalid range or n < 0.  Uses the current tuning (grid density,
+ * eigenvectors per wavefront).
+ */
+#define MRRR_WS_CHILD_ROWS_PER_N 32
+size_t mrrr_workspace_size(int64_t n, mrrr_range range);
+
+/*
+ * mrrr_step_ws -- mrrr_step with a caller-provided device workspace and a
+ * device-resident report (the boundary of the problem statement in Sec. 1.1 /
+ * Stage 4 of Sec. 1.2: the eigenpairs of T, all or a subset).
+ *   n, d, e, range, w, Z, ldz   as for mrrr_step                  [args 1-7]
+ *   work        device, work_bytes bytes (256-byte aligned recommended),
+ *               owned by the caller; NULL: the library's own grow-only
+ *               workspace (as mrrr_step)                              [arg 8]
+ *   work_bytes  size of work (see mrrr_workspace_size)                [arg 9]
+ *   info_dev    DEVICE pointer to one mrrr_info, may be NULL: written on
+ *               `stream` at the end of the solve                      [arg 10]
+ *   stream      hipStream_t as void*                                   [arg 11]
+ * With work != NULL the call allocates no device memory: every buffer is
+ * carved from work (its contents on entry are ignored and on return are
+ * undefined).  Two calls that share a workspace must not overlap in time.
+ * Returns 0, a negative argument index (checked on the host before any
+ * device work), or a status; MRRR_ERR_CAPACITY when work is too small for
+ * this input (outputs are then undefined).
+ */
+int mrrr_step_ws(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
+                 int64_t ldz, void* work, size_t work_bytes, mrrr_info* info_dev, void* stream);
+
+/*
+ * Limits of the representation tree.  Lowering them makes the solver report
+ * the corresponding status instead of going on (used by the tests of those
+ * paths):
+ *   max_depth           1 .. 64 (default 64): nodes at this depth do not get
+ *                       child representations; their clustered eigenvalues
+ *                       are computed as singletons of the deepest node and the
+ *                       call returns MRRR_ERR_DEPTH.
+ *   child_growth_limit  0 (default): a cluster takes the candidate shift with
+ *                       the least element growth when none meets the growth
+ *                       bound of 8 spectral diameters; > 0: candidates whose
+ *                       max |D_c| exceeds this many spectral diameters are
+ *                       rejected, and a cluster without an acceptable one is
+ *                       handed back to its parent (MRRR_ERR_NO_RRR).
+ * mrrr_set_limits returns -1 for out-of-range fields.
+ */
+typedef struct {
+  int32_t max_depth;
+  int32_t reserved;
+  double child_growth_limit;
+} mrrr_limits;
+
+int mrrr_get_limits(mrrr_limits* l);
+int mrrr_set_limits(const mrrr_limits* l);
 
 /*
  * mrrr_step_batched -- all eigenpairs of `batch` independent tridiagonals in one

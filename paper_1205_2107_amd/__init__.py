@@ -17,7 +17,7 @@ from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
-           "profile_read", "release"]
+           "profile_read", "release", "workspace_size", "get_limits", "set_limits"]
 
 
 def _torch():
@@ -44,20 +44,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
 
 
-def eigh_tridiagonal(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigvals_only=False,
-                     stream=None, return_info=False):
-    """Eigenpairs of the symmetric tridiagonal matrix (diagonal d, off-diagonal e).
-
-    select: "a" all, "i" indices il..iu (1-based, inclusive), "v" values in (vl, vu].
-    Returns w (ascending, float64, on the GPU) and Z (n x m column-major view:
-    a tensor of shape (n, m) whose columns are the eigenvectors), plus the info
-    dict when return_info is set.
-    """
-    torch = _torch()
-    lib = _lib.load()
-    d = _as_dev(d)
-    n = d.numel()
-    e = _as_dev(e, d.device) if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+def _range(select, il, iu, vl, vu, n):
     rng = MrrrRange()
     if select == "a":
         rng.kind = _lib.MRRR_ALL
@@ -72,12 +59,46 @@ def eigh_tridiagonal(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigva
         m = n
     else:
         raise ValueError("select must be 'a', 'i' or 'v'")
+    return rng, m
+
+
+def workspace_size(n, select="a", il=None, iu=None, vl=None, vu=None):
+    """Bytes of caller workspace mrrr_step_ws suggests for this problem size."""
+    rng, _ = _range(select, il, iu, vl, vu, int(n))
+    return int(_lib.load().mrrr_workspace_size(int(n), rng))
+
+
+def eigh_tridiagonal(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigvals_only=False,
+                     stream=None, return_info=False, work=None):
+    """Eigenpairs of the symmetric tridiagonal matrix (diagonal d, off-diagonal e).
+
+    select: "a" all, "i" indices il..iu (1-based, inclusive), "v" values in (vl, vu].
+    work: optional device tensor used as the solver's whole workspace
+    (mrrr_step_ws; nothing is allocated by the library; see workspace_size).
+    Returns w (ascending, float64, on the GPU) and Z (n x m column-major view:
+    a tensor of shape (n, m) whose columns are the eigenvectors), plus the info
+    dict when return_info is set.
+    """
+    torch = _torch()
+    lib = _lib.load()
+    d = _as_dev(d)
+    n = d.numel()
+    e = _as_dev(e, d.device) if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+    rng, m = _range(select, il, iu, vl, vu, n)
     w = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
     Zbuf = None if eigvals_only else torch.empty((max(m, 1), max(n, 1)), dtype=torch.float64, device=d.device)
     info = MrrrInfo()
-    rc = lib.mrrr_step(n, _ptr(d), _ptr(e), rng, _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(info),
-                       _stream_ptr(stream))
-    _lib.check(rc)
+    if work is None:
+        rc = lib.mrrr_step(n, _ptr(d), _ptr(e), rng, _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(info),
+                           _stream_ptr(stream))
+        _lib.check(rc)
+    else:
+        info_dev = torch.zeros(ctypes.sizeof(MrrrInfo) // 8, dtype=torch.int64, device=d.device)
+        rc = lib.mrrr_step_ws(n, _ptr(d), _ptr(e), rng, _ptr(w), _ptr(Zbuf), max(n, 1), _ptr(work),
+                              work.numel() * work.element_size(), _ptr(info_dev), _stream_ptr(stream))
+        _lib.check(rc)
+        host = info_dev.cpu().numpy()  # kept alive across the copy
+        ctypes.memmove(ctypes.addressof(info), host.ctypes.data, ctypes.sizeof(MrrrInfo))
     mm = int(info.m) if n > 0 else 0
     w = w[:mm]
     Z = None if Zbuf is None else Zbuf[:mm, :n].t()
@@ -200,10 +221,6 @@ def eigh_tridiagonal_backward_batched(w, Z, sizes, gw=None, gZ=None, stream=None
     return gd[:acc], ge[:acc]
 
 
-class _MRRRFunction:
-    pass
-
-
 def _make_function():
     torch = _torch()
 
@@ -263,6 +280,26 @@ def set_tuning(grid_density=None, refine_wave_slots=None, vec_wave_slots=None, v
         t.vec_ckpt_min_n = int(vec_ckpt_min_n)
     if lib.mrrr_set_tuning(ctypes.byref(t)) != 0:
         raise ValueError("tuning value out of range")
+
+
+def get_limits():
+    t = _lib.MrrrLimits()
+    _lib.check(_lib.load().mrrr_get_limits(ctypes.byref(t)))
+    return {"max_depth": t.max_depth, "child_growth_limit": t.child_growth_limit}
+
+
+def set_limits(max_depth=None, child_growth_limit=None):
+    """Lower the representation tree's depth limit or set a hard limit on the
+    element growth of child representations (tests of the status paths)."""
+    lib = _lib.load()
+    t = _lib.MrrrLimits()
+    _lib.check(lib.mrrr_get_limits(ctypes.byref(t)))
+    if max_depth is not None:
+        t.max_depth = int(max_depth)
+    if child_growth_limit is not None:
+        t.child_growth_limit = float(child_growth_limit)
+    if lib.mrrr_set_limits(ctypes.byref(t)) != 0:
+        raise ValueError("limit out of range")
 
 
 def profile(enable=True):

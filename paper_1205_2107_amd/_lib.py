@@ -10,10 +10,12 @@ LIB_PATH = os.path.join(_HERE, "libmrrr.so")
 
 MRRR_ALL, MRRR_INDEX, MRRR_VALUE = 0, 1, 2
 COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singletons", "twisted",
-                 "fallbacks", "child_reject", "workspace_mb", "wave_solves")
+                 "fallbacks", "child_reject", "workspace_mb", "wave_solves", "pool_rows", "ambiguous_left",
+                 "workspace_bytes")
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
-           "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string")
+           "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
+           "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits")
 KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt")
 
 
@@ -37,6 +39,11 @@ class MrrrTuning(ctypes.Structure):
     _fields_ = [("grid_density", ctypes.c_int32), ("refine_wave_slots", ctypes.c_int32),
                 ("vec_wave_slots", ctypes.c_int32), ("vec_ckpt_min_run", ctypes.c_int32),
                 ("vec_ckpt_min_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class MrrrLimits(ctypes.Structure):
+    _fields_ = [("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("child_growth_limit", ctypes.c_double)]
 
 
 class MrrrKernelTime(ctypes.Structure):
@@ -66,6 +73,14 @@ def load():
     PI64 = ctypes.POINTER(ctypes.c_int64)
     lib.mrrr_step.restype = ctypes.c_int
     lib.mrrr_step.argtypes = [I64, P, P, MrrrRange, P, P, I64, ctypes.POINTER(MrrrInfo), P]
+    lib.mrrr_workspace_size.restype = ctypes.c_size_t
+    lib.mrrr_workspace_size.argtypes = [I64, MrrrRange]
+    lib.mrrr_step_ws.restype = ctypes.c_int
+    lib.mrrr_step_ws.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, ctypes.c_size_t, P, P]
+    lib.mrrr_get_limits.restype = ctypes.c_int
+    lib.mrrr_get_limits.argtypes = [ctypes.POINTER(MrrrLimits)]
+    lib.mrrr_set_limits.restype = ctypes.c_int
+    lib.mrrr_set_limits.argtypes = [ctypes.POINTER(MrrrLimits)]
     lib.mrrr_step_batched.restype = ctypes.c_int
     lib.mrrr_step_batched.argtypes = [I64, PI64, PI64, P, P, P, P, PI64, ctypes.POINTER(MrrrInfo), P]
     lib.mrrr_step_backward.restype = ctypes.c_int

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -72,6 +73,13 @@ struct Workspace {
   // which runs beside the stored-vector kernel; fork and join events
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // arena mode: every buffer is carved from one caller-provided region
+  // [abase, abase + acap) by a bump pointer; nothing is allocated.  The most
+  // recently carved buffer can grow in place.
+  char* abase = nullptr;
+  size_t acap = 0, aused = 0;
+  void* alast = nullptr;
+  bool no_fork = false;  // run both eigenvector kernels on the caller's stream
   size_t total_bytes() const {
     const DevBuf* all[] = {&problems, &poff, &sprob, &ds, &es, &flag, &excl, &tiles, &total, &bstart, &sblk, &blocks,
                            &goff, &nodes, &pool, &gcnt, &lo, &hi, &clo, &chi, &snode, &sflag, &scol, &val, &runflag,
@@ -112,9 +120,47 @@ static Workspace* workspace_for_current_device(int* dev_out) {
   return it->second;
 }
 
+constexpr size_t kAlign = 256;
+static size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// arena mode: a region of the caller's workspace (no allocation); keep copies
+// the old contents into a new region unless the buffer is the last one carved,
+// which grows in place
+static int carve(Workspace& W, DevBuf& b, size_t bytes, hipStream_t st, bool keep) {
+  bytes = align_up(std::max<size_t>(bytes, 1));
+  if (b.p && b.p == W.alast) {
+    const size_t start = (size_t)((char*)b.p - W.abase);
+    if (start + bytes > W.acap)
+      return fail(MRRR_ERR_CAPACITY, "workspace of %zu bytes exhausted (needs at least %zu)", W.acap, start + bytes);
+    W.aused = start + bytes;
+    b.bytes = bytes;
+    return 0;
+  }
+  const size_t start = align_up(W.aused);
+  if (start + bytes > W.acap)
+    return fail(MRRR_ERR_CAPACITY, "workspace of %zu bytes exhausted (needs at least %zu)", W.acap, start + bytes);
+  void* p = W.abase + start;
+  if (keep && b.p && b.bytes) {
+    hipError_t e = hipMemcpyAsync(p, b.p, b.bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(MRRR_ERR_HIP, "workspace copy failed: %s", hipGetErrorString(e));
+  }
+  b.p = p;
+  b.bytes = bytes;
+  W.aused = start + bytes;
+  W.alast = p;
+  return 0;
+}
+
+// bytes still free in the arena
+static size_t arena_free(const Workspace& W) {
+  const size_t u = align_up(W.aused);
+  return u < W.acap ? W.acap - u : 0;
+}
+
 // grow-only device buffer; contents are not preserved unless keep is set
-static int ensure(DevBuf& b, size_t bytes, hipStream_t st, bool keep = false) {
+static int ensure(Workspace& W, DevBuf& b, size_t bytes, hipStream_t st, bool keep = false) {
   if (bytes <= b.bytes && b.p) return 0;
+  if (W.abase) return carve(W, b, bytes, st, keep);
   size_t nb = std::max(bytes, b.bytes + b.bytes / 4);
   nb = std::max<size_t>(nb, 256);
   void* p = nullptr;
@@ -154,7 +200,13 @@ struct Report {
   int levels = 0;
   int nodes = 0;
   size_t ws_bytes = 0;
+  int64_t ambiguous_left = 0;  // pairs classified from unrefined brackets after three refinements
+  int depth_stop = 0;          // the level loop stopped at its depth guard
 };
+
+// limits the caller may lower (tests use them to force the status paths)
+static mrrr_limits g_limits = {kMaxDepth, 0, 0.0};
+static std::mutex g_limits_mu;
 
 // Solve a list of problems (packed into slot space) on one stream.
 static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, const double* e, double* w, double* Z,
@@ -168,6 +220,11 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     tune = g_tune;
   }
   const int G = tune.grid_density;
+  mrrr_limits lim;
+  {
+    std::lock_guard<std::mutex> lk(g_limits_mu);
+    lim = g_limits;
+  }
   std::vector<int64_t> poff(nprob + 1, 0);
   for (int p = 0; p < nprob; ++p) poff[p + 1] = poff[p] + probs[p].n;
   const int64_t ntot = poff[nprob];
@@ -180,9 +237,9 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   if (slots == 0) slots = (ntot <= 32768) ? 16 : (ntot <= 131072 ? 32 : 64);
   const int lanes = 64 / slots;
   double grid_work = 0.0;
-#define ENS(buf, bytes)                                          \
-  do {                                                           \
-    if ((rc = ensure(W.buf, (size_t)(bytes), st)) != 0) return rc; \
+#define ENS(buf, bytes)                                             \
+  do {                                                              \
+    if ((rc = ensure(W, W.buf, (size_t)(bytes), st)) != 0) return rc; \
   } while (0)
   ENS(problems, sizeof(Problem) * nprob);
   ENS(poff, sizeof(int64_t) * (nprob + 1));
@@ -221,15 +278,61 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipGetLastError());
   rep->nblk = nblk;
+  const bool arena = W.abase != nullptr;
   ENS(bstart, sizeof(int64_t) * (nblk + 1));
   ENS(sblk, sizeof(int32_t) * ntot);
   ENS(blocks, sizeof(Block) * nblk);
   ENS(goff, sizeof(int64_t) * (nblk + 1));
-  // node table: roots first; grows per level
-  ENS(nodes, sizeof(Node) * (size_t)std::max<int64_t>(nblk + 16, 2 * (int64_t)nblk));
-  // pool: roots aligned with slots plus room for children (grown on demand)
+  // node table: roots first; grows per level (in arena mode sized once for
+  // nblk + ntot nodes: every child holds at least two eigenvalues of its parent)
+  ENS(nodes, sizeof(Node) * (size_t)(arena ? (int64_t)nblk + ntot + 16
+                                           : std::max<int64_t>(nblk + 16, 2 * (int64_t)nblk)));
+  // per-slot arrays, the count grid and the cluster list: sizes known now
+  const int64_t gtot = (int64_t)G * ntot + nblk;
+  ENS(gcnt, sizeof(int32_t) * gtot);
+  ENS(lo, sizeof(double) * ntot);
+  ENS(hi, sizeof(double) * ntot);
+  ENS(clo, sizeof(int32_t) * ntot);
+  ENS(chi, sizeof(int32_t) * ntot);
+  ENS(snode, sizeof(int32_t) * ntot);
+  ENS(sflag, sizeof(uint32_t) * ntot);
+  ENS(scol, sizeof(int64_t) * ntot);
+  ENS(val, sizeof(double) * ntot);
+  ENS(sgap, sizeof(double) * ntot);
+  ENS(runflag, sizeof(int32_t) * ntot);
+  ENS(runid, sizeof(int32_t) * ntot);
+  ENS(runs, sizeof(int64_t) * (ntot + 1));
+  ENS(vrid, sizeof(int32_t) * ntot);
+  ENS(cflag, sizeof(int32_t) * ntot);
+  ENS(cid, sizeof(int32_t) * ntot);
+  ENS(cstart, sizeof(int64_t) * (ntot + 1));
+  const int max_clusters = (int)std::min<int64_t>(ntot / 2 + 1, INT32_MAX / 2);
+  if (Z != nullptr) ENS(clusters, sizeof(Cluster) * (size_t)max_clusters);
+  int64_t nmax_prob = 1;
+  for (auto& p : probs) nmax_prob = std::max<int64_t>(nmax_prob, p.n);
+  int vslots = tune.vec_wave_slots;
+  if (vslots == 0) vslots = 32;
+  // arena mode: what the eigenvector phase needs at least after the tree
+  // (chunk lists, one chunk of each kernel's scratch, the sort fix-up), kept
+  // free while the pool grows
+  const int64_t nch_all = (ntot + vslots - 1) / vslots;
+  const size_t vec_reserve =
+      (Z == nullptr) ? align_up(sizeof(int32_t) * nprob)
+                     : 8 * kAlign + align_up(sizeof(int32_t) * nch_all) + align_up(sizeof(int32_t) * (nch_all + 1)) +
+                           align_up(sizeof(int64_t) * (nch_all + 1)) +
+                           align_up(sizeof(double) * 4 * (size_t)vslots * (size_t)nmax_prob) +
+                           align_up(sizeof(double) * 4 * (size_t)vslots * (size_t)((nmax_prob + kSeg - 1) / kSeg)) +
+                           align_up(sizeof(int32_t) * nprob) + 2 * align_up(sizeof(int64_t) * ntot);
+  // pool: roots aligned with slots plus room for children (grown on demand;
+  // in arena mode it is carved last, so it grows in place)
   size_t pool_rows = (size_t)ntot + (size_t)std::max<int64_t>(4 * 1024, ntot / 2);
-  if (W.pool.bytes / sizeof(Rep) > pool_rows) pool_rows = W.pool.bytes / sizeof(Rep);
+  if (arena) {
+    pool_rows = (size_t)ntot + (Z != nullptr ? (size_t)kChildSpecFew * (size_t)nmax_prob : 0);
+    const size_t room = arena_free(W) > vec_reserve ? arena_free(W) - vec_reserve : 0;
+    pool_rows = std::max<size_t>((size_t)ntot, std::min(pool_rows, room / sizeof(Rep)));
+  } else if (W.pool.bytes / sizeof(Rep) > pool_rows) {
+    pool_rows = W.pool.bytes / sizeof(Rep);
+  }
   ENS(pool, sizeof(Rep) * pool_rows);
   launch_blocks(st, dP, P_<int64_t>(W.poff), P_<int32_t>(W.flag), P_<int32_t>(W.excl), ntot, nblk,
                 P_<int32_t>(W.sprob), P_<int64_t>(W.bstart), P_<int32_t>(W.sblk), P_<Block>(W.blocks));
@@ -247,20 +350,6 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     go[nblk] = (int64_t)G * ntot + nblk;
     HIP_TRY(hipMemcpyAsync(W.goff.p, go.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, st));
   }
-  const int64_t gtot = (int64_t)G * ntot + nblk;
-  ENS(gcnt, sizeof(int32_t) * gtot);
-  ENS(lo, sizeof(double) * ntot);
-  ENS(hi, sizeof(double) * ntot);
-  ENS(clo, sizeof(int32_t) * ntot);
-  ENS(chi, sizeof(int32_t) * ntot);
-  ENS(snode, sizeof(int32_t) * ntot);
-  ENS(sflag, sizeof(uint32_t) * ntot);
-  ENS(scol, sizeof(int64_t) * ntot);
-  ENS(val, sizeof(double) * ntot);
-  ENS(sgap, sizeof(double) * ntot);
-  ENS(runflag, sizeof(int32_t) * ntot);
-  ENS(runid, sizeof(int32_t) * ntot);
-  ENS(runs, sizeof(int64_t) * (ntot + 1));
   Block* dB = P_<Block>(W.blocks);
   Rep* dpool = P_<Rep>(W.pool);
 
@@ -278,10 +367,6 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   // depends only on the node, not on the other problems of a batch.  The root
   // level refines each eigenvalue on its own points (shared points there
   // changed the geometric matrix's tree for the worse), so it needs no chunks.
-  ENS(vrid, sizeof(int32_t) * ntot);
-  ENS(cflag, sizeof(int32_t) * ntot);
-  ENS(cid, sizeof(int32_t) * ntot);
-  ENS(cstart, sizeof(int64_t) * (ntot + 1));
   auto refine_flagged = [&](bool need_col, bool share) -> int {
     launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_NEEDS_REFINE, need_col,
                        P_<int32_t>(W.snode), 64 / lanes, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
@@ -317,10 +402,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   } else {
     // 6-7. representation tree, level by level
     int node_base = nblk;
-    int64_t nmax_prob = 1;
-    for (auto& p : probs) nmax_prob = std::max<int64_t>(nmax_prob, p.n);
-    int max_clusters = (int)std::min<int64_t>(ntot / 2 + 1, INT32_MAX / 2);
-    ENS(clusters, sizeof(Cluster) * (size_t)max_clusters);
+    const size_t node_cap = W.nodes.bytes / sizeof(Node);
     for (int level = 0;; ++level) {
       // classification; pairs whose decision the bracket widths could flip are
       // refined (validated, full accuracy) and classified again
@@ -336,13 +418,20 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
         HIP_TRY(hipMemcpyAsync(&amb, (char*)W.counters.p + offsetof(Counters, ambiguous), sizeof(int32_t),
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (amb == 0 || round >= 3) break;
+        if (amb == 0) break;
+        if (round >= 3) {
+          // still ambiguous after three refinements: classified from the
+          // brackets as they are (counted, not an error)
+          rep->ambiguous_left += amb;
+          break;
+        }
         if ((rc = refine_flagged(false, kShareLevels)) != 0) return rc;
       }
       launch_cls_compact(st, ntot, P_<int32_t>(W.runflag), P_<int32_t>(W.runid), P_<int64_t>(W.runs));
       launch_cls_runs(st, dB, P_<Node>(W.nodes), nruns, P_<int64_t>(W.runs), P_<int32_t>(W.sblk),
                       P_<int32_t>(W.snode), P_<double>(W.lo), P_<double>(W.hi), P_<int64_t>(W.scol),
-                      P_<uint32_t>(W.sflag), P_<double>(W.sgap), P_<Cluster>(W.clusters), max_clusters, dC);
+                      P_<uint32_t>(W.sflag), P_<double>(W.sgap), P_<Cluster>(W.clusters), max_clusters, dC,
+                      lim.max_depth);
       launch_clear_active(st, ntot, P_<uint32_t>(W.sflag));
       Counters hc;
       HIP_TRY(hipMemcpyAsync(&hc, W.counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -351,17 +440,40 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       rep->levels = level + 1;
       const int ncl = std::min(hc.nclusters, max_clusters);
       if (ncl == 0) break;
+      if (level > lim.max_depth + 2) {
+        // the depth test of the classification makes this unreachable; kept
+        // as a guard so the loop always ends
+        rep->depth_stop = 1;
+        break;
+      }
       // capacity for the new nodes and the speculative child regions of every
       // cluster (two with masked stores, four in the branch-free form, every
       // candidate's when the regions stay small: no second pass)
-      if ((rc = ensure(W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
+      if (arena && (size_t)(node_base + ncl) > node_cap)
+        return fail(MRRR_ERR_CAPACITY, "node table of %zu entries exhausted", node_cap);
+      if ((rc = ensure(W, W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
       const bool masked = ncl >= kChildMaskedFrom || nmax_prob >= kChildFewMaxN;
       const bool all = !masked && nmax_prob < kChildAllMaxN &&
                        (size_t)kChildSpecAll * (size_t)hc.cluster_rows <= (size_t)kChildAllMaxRows;
-      const int spec = masked ? kChildSpecMany : (all ? kChildSpecAll : kChildSpecFew);
-      const size_t need_rows = (size_t)hc.pool_used + (size_t)ntot + (size_t)spec * (size_t)hc.cluster_rows;
+      int spec = masked ? kChildSpecMany : (all ? kChildSpecAll : kChildSpecFew);
+      const size_t used_rows = (size_t)std::max<unsigned long long>(hc.pool_used, (unsigned long long)ntot);
+      auto need_for = [&](int sp) { return used_rows + (size_t)sp * (size_t)hc.cluster_rows; };
+      if (arena) {
+        // the pool grows in place up to what the eigenvector phase must keep
+        // free; fewer speculative regions when the rest does not fit (the
+        // values do not depend on how many candidates store speculatively)
+        const size_t pool_start = (size_t)((char*)W.pool.p - W.abase);
+        const size_t room_rows =
+            (W.acap > vec_reserve + pool_start) ? (W.acap - vec_reserve - pool_start) / sizeof(Rep) : 0;
+        if (need_for(spec) > room_rows && spec == kChildSpecAll) spec = kChildSpecFew;
+        if (need_for(spec) > room_rows && spec == kChildSpecFew && nmax_prob < kChildFewMaxN) spec = kChildSpecMany;
+        if (need_for(spec) > room_rows)
+          return fail(MRRR_ERR_CAPACITY, "workspace of %zu bytes too small for the representation tree", W.acap);
+      }
+      const size_t need_rows = need_for(spec);
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
-        if ((rc = ensure(W.pool, need_rows * sizeof(Rep) + (W.pool.bytes / 2), st, true)) != 0) return rc;
+        if ((rc = ensure(W, W.pool, need_rows * sizeof(Rep) + (arena ? 0 : W.pool.bytes / 2), st, true)) != 0)
+          return rc;
         dpool = P_<Rep>(W.pool);
       }
       const unsigned long long pool_cap = W.pool.bytes / sizeof(Rep);
@@ -373,7 +485,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       }
       prof.begin(MRRR_K_CHILD);
       launch_child(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<double>(W.lo),
-                   P_<double>(W.hi), dpool, pool_cap, dC, spec);
+                   P_<double>(W.hi), dpool, pool_cap, dC, spec, lim.child_growth_limit);
       prof.end();
       launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
                    P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
@@ -382,7 +494,6 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       HIP_TRY(hipMemsetAsync((char*)W.counters.p + offsetof(Counters, cluster_rows), 0, sizeof(unsigned long long),
                              st));
       node_base += ncl;
-      if (level > kMaxDepth + 2) break;
     }
     rep->nodes = node_base - nblk;
     // singletons of child nodes: validated, full-accuracy brackets in their
@@ -397,12 +508,6 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     //    consecutive slots per wavefront, four work vectors in memory).  Both
     //    compute the same values.  Eigenvectors per wavefront: tuning, 32 by
     //    default.
-    int vslots = tune.vec_wave_slots;
-    if (vslots == 0) vslots = 32;
-    ENS(vrid, sizeof(int32_t) * ntot);
-    ENS(cflag, sizeof(int32_t) * ntot);
-    ENS(cid, sizeof(int32_t) * ntot);
-    ENS(cstart, sizeof(int64_t) * (ntot + 1));
     launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_SINGLETON, true,
                        P_<int32_t>(W.snode), vslots, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
                        P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
@@ -427,8 +532,12 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     // by their largest block), planned and uploaded before either kernel
     // starts: a transfer queued while the checkpointing kernel fills the chip
     // would wait for free compute units
-    const int64_t nch = (ntot + vslots - 1) / vslots;
+    const int64_t nch = nch_all;
     ENS(chunkrows, sizeof(int32_t) * nch);
+    if (arena) {
+      ENS(chunks, sizeof(int32_t) * (nch + 1));
+      ENS(chunkoff, sizeof(int64_t) * (nch + 1));
+    }
     launch_chunk_rows(st, dB, ntot, P_<int32_t>(W.sblk), P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), vslots,
                       P_<int32_t>(W.chunkrows));
     std::vector<int32_t> rows(nch);
@@ -441,9 +550,30 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
         act.push_back((int32_t)c);
         maxper = std::max<int64_t>(maxper, 4 * vslots * (int64_t)rows[c]);
       }
+    // scratch budgets: a quarter of the device each, or in arena mode what is
+    // left of the workspace (less the sort fix-up), shared by the two kernels
+    size_t sbudget = scratch_budget(), ckbudget = scratch_budget();
+    if (arena) {
+      const size_t tail = 4 * kAlign + align_up(sizeof(int32_t) * nprob) + 2 * align_up(sizeof(int64_t) * ntot);
+      const size_t fr = arena_free(W) > tail ? arena_free(W) - tail : 0;
+      const size_t sb = (size_t)stride * sizeof(double);
+      const size_t stneed = act.empty() ? 0 : align_up((size_t)maxper * sizeof(double)) + kAlign;
+      if (fr < stneed + (nchunks > 0 ? sb + kAlign : 0))
+        return fail(MRRR_ERR_CAPACITY, "workspace of %zu bytes too small for the eigenvector scratch", W.acap);
+      // the checkpointing kernel takes up to half of what is left (at least
+      // one chunk's checkpoints), the stored-vector kernel the rest
+      size_t ck = 0;
+      if (nchunks > 0) {
+        const size_t cap = fr - stneed - kAlign;
+        const size_t want = act.empty() ? cap : std::min(cap, std::max(sb, fr / 2));
+        ck = std::min<size_t>((size_t)nchunks, std::max<size_t>(1, want / sb)) * sb;
+      }
+      ckbudget = ck;
+      sbudget = fr - (ck ? align_up(ck) + kAlign : 0);
+    }
     // batches of chunks whose scratch fits the budget; offsets relative to
     // the scratch base, which every batch reuses
-    const size_t budget = std::max(scratch_budget(), (size_t)maxper * sizeof(double));
+    const size_t budget = std::max(sbudget, (size_t)maxper * sizeof(double));
     std::vector<int64_t> aoff(act.size());
     std::vector<size_t> bstart_h{0};
     int64_t used = 0, used_max = 0;
@@ -465,12 +595,22 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       HIP_TRY(hipMemcpyAsync(W.chunks.p, act.data(), sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(W.chunkoff.p, aoff.data(), sizeof(int64_t) * act.size(), hipMemcpyHostToDevice, st));
     }
-    const size_t ckbudget = std::max(scratch_budget(), (size_t)stride * sizeof(double));
-    const int64_t cmax = std::max<int64_t>(1, (int64_t)(ckbudget / (sizeof(double) * (size_t)stride)));
+    const int64_t cmax = std::max<int64_t>(
+        1, (int64_t)(std::max(ckbudget, (size_t)stride * sizeof(double)) / (sizeof(double) * (size_t)stride)));
     if (nchunks > 0) ENS(ckscratch, sizeof(double) * (size_t)(std::min<int64_t>(nchunks, cmax) * stride));
     HIP_TRY(hipStreamSynchronize(st));  // the uploads have read the host vectors
     bool forked = false;
-    if (nchunks > 0) {
+    if (nchunks > 0 && W.no_fork) {
+      prof.begin(MRRR_K_VECTORS_CKPT);
+      for (int64_t c0 = 0; c0 < nchunks; c0 += cmax) {
+        const int64_t nc = std::min<int64_t>(cmax, nchunks - c0);
+        launch_vectors(st, dP, dB, P_<Node>(W.nodes), P_<int64_t>(W.cstart) + c0, (int)nc, ntot, P_<int32_t>(W.vrid),
+                       P_<int32_t>(W.sblk), P_<int32_t>(W.snode), P_<int64_t>(W.scol), P_<double>(W.lo),
+                       P_<double>(W.hi), P_<double>(W.sgap), dpool, P_<double>(W.ds), P_<double>(W.ckscratch),
+                       stride, w, Z, dC, vslots);
+      }
+      prof.end();
+    } else if (nchunks > 0) {
       if (!W.aux) HIP_TRY(hipStreamCreateWithFlags(&W.aux, hipStreamNonBlocking));
       if (!W.ev_fork) HIP_TRY(hipEventCreateWithFlags(&W.ev_fork, hipEventDisableTiming));
       if (!W.ev_join) HIP_TRY(hipEventCreateWithFlags(&W.ev_join, hipEventDisableTiming));
@@ -517,55 +657,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipGetLastError());
   rep->c = hc;
-  rep->ws_bytes = W.total_bytes();
-  // diagnostics: MRRR_DEBUG_DUMP=<file> writes the per-slot tree state
-  if (const char* path = getenv("MRRR_DEBUG_DUMP")) {
-    const int nnodes = nblk + rep->nodes;
-    std::vector<int32_t> hn(ntot);
-    std::vector<uint32_t> hf(ntot);
-    std::vector<double> hl(ntot), hh(ntot), hg(ntot);
-    std::vector<Node> nodes(nnodes);
-    HIP_TRY(hipMemcpy(hg.data(), W.sgap.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hn.data(), W.snode.p, sizeof(int32_t) * ntot, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hf.data(), W.sflag.p, sizeof(uint32_t) * ntot, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hl.data(), W.lo.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hh.data(), W.hi.p, sizeof(double) * ntot, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(nodes.data(), W.nodes.p, sizeof(Node) * nnodes, hipMemcpyDeviceToHost));
-    if (FILE* f = fopen(path, "wb")) {
-      const int64_t hdr[3] = {ntot, nnodes, (int64_t)sizeof(Node)};
-      fwrite(hdr, sizeof(hdr), 1, f);
-      fwrite(hn.data(), sizeof(int32_t), ntot, f);
-      fwrite(hf.data(), sizeof(uint32_t), ntot, f);
-      fwrite(hl.data(), sizeof(double), ntot, f);
-      fwrite(hh.data(), sizeof(double), ntot, f);
-      fwrite(nodes.data(), sizeof(Node), nnodes, f);
-      fwrite(hg.data(), sizeof(double), ntot, f);
-      // representation rows (D, L, LD, LLD) of the leaf nodes of the slots
-      // listed in MRRR_DEBUG_DUMP_SLOTS (comma separated)
-      std::vector<int> want;
-      if (const char* nl = getenv("MRRR_DEBUG_DUMP_SLOTS")) {
-        for (const char* q = nl; *q;) {
-          const long long sl = atoll(q);
-          if (sl >= 0 && sl < ntot) want.push_back(hn[sl]);
-          while (*q && *q != ',') ++q;
-          if (*q == ',') ++q;
-        }
-      }
-      std::sort(want.begin(), want.end());
-      want.erase(std::unique(want.begin(), want.end()), want.end());
-      for (int k : want) {
-        if (k < 0 || k >= nnodes || nodes[k].rep < 0) continue;
-        Block hb;
-        HIP_TRY(hipMemcpy(&hb, (Block*)W.blocks.p + nodes[k].blk, sizeof(Block), hipMemcpyDeviceToHost));
-        std::vector<Rep> rows(hb.n);
-        HIP_TRY(hipMemcpy(rows.data(), (Rep*)W.pool.p + nodes[k].rep, sizeof(Rep) * hb.n, hipMemcpyDeviceToHost));
-        const int64_t h2[2] = {k, hb.n};
-        fwrite(h2, sizeof(h2), 1, f);
-        fwrite(rows.data(), sizeof(Rep), hb.n, f);
-      }
-      fclose(f);
-    }
-  }
+  rep->ws_bytes = W.abase ? W.aused : W.total_bytes();
   if (prof.on) {
     const double vr = (double)(hc.vec_rows - hc.ckpt_vec_rows), ze = (double)(hc.z_entries - hc.ckpt_z_entries);
     const double work[MRRR_K_COUNT] = {grid_work, 4.0 * (double)hc.sturm_steps, 5.0 * (double)hc.child_steps,
@@ -581,6 +673,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     }
   }
   if (hc.grid_fail) return fail(MRRR_ERR_HIP, "internal: Sturm grid did not bracket the spectrum");
+  if (rep->depth_stop && hc.status == 0) rep->c.status = MRRR_ERR_DEPTH;
   return 0;
 #undef ENS
 }
@@ -601,17 +694,15 @@ static void fill_info(mrrr_info* info, const Problem& p, const Report& r) {
   info->counters[MRRR_CNT_CHILD_REJECT] = (int64_t)r.c.child_reject;
   info->counters[MRRR_CNT_WORKSPACE_MB] = (int64_t)(r.ws_bytes >> 20);
   info->counters[MRRR_CNT_WAVE_SOLVES] = (int64_t)r.c.wave_solves;
+  info->counters[MRRR_CNT_POOL_ROWS] = (int64_t)r.c.pool_used;
+  info->counters[MRRR_CNT_AMBIGUOUS_LEFT] = r.ambiguous_left;
+  info->counters[MRRR_CNT_WORKSPACE_BYTES] = (int64_t)r.ws_bytes;
 }
 
-}  // namespace mrrr
+static_assert(sizeof(mrrr_info) == sizeof(InfoWords), "mrrr_info is stored as 18 words");
 
-using namespace mrrr;
-
-extern "C" {
-
-int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z, int64_t ldz,
-              mrrr_info* info, void* stream) {
-  if (info) memset(info, 0, sizeof(*info));
+static int check_step_args(int64_t n, const double* d, const double* e, mrrr_range range, const double* w,
+                           const double* Z, int64_t ldz) {
   if (n < 0) return fail(-1, "n < 0");
   if (n > 0 && !d) return fail(-2, "d is NULL");
   if (n > 1 && !e) return fail(-3, "e is NULL");
@@ -622,6 +713,14 @@ int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, dou
   if (n > 0 && !w) return fail(-5, "w is NULL");
   if (Z && ldz < std::max<int64_t>(1, n)) return fail(-7, "ldz < max(1, n)");
   if (n > INT32_MAX / 8) return fail(-1, "n too large");
+  return 0;
+}
+
+// one problem; arena (may be NULL): carve every buffer from [work, work +
+// work_bytes) instead of the library's workspace
+static int step_impl(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
+                     int64_t ldz, void* work, size_t work_bytes, bool no_fork, mrrr_info* info, hipStream_t stream) {
+  if (info) memset(info, 0, sizeof(*info));
   if (n == 0) return 0;
   int dev = 0;
   Workspace* W = workspace_for_current_device(&dev);
@@ -640,12 +739,145 @@ int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, dou
   p.vl = range.vl;
   p.vu = range.vu;
   Report r;
-  int rc = solve(*W, probs, d, e, w, Z, (hipStream_t)stream, &r);
+  int rc;
+  if (work) {
+    // a workspace of this call only; the library's second stream and events
+    // are borrowed for the concurrent eigenvector kernels
+    Workspace A;
+    A.abase = static_cast<char*>(work);
+    A.acap = work_bytes;
+    A.no_fork = no_fork;
+    A.aux = W->aux;
+    A.ev_fork = W->ev_fork;
+    A.ev_join = W->ev_join;
+    rc = solve(A, probs, d, e, w, Z, stream, &r);
+    W->aux = A.aux;
+    W->ev_fork = A.ev_fork;
+    W->ev_join = A.ev_join;
+  } else {
+    rc = solve(*W, probs, d, e, w, Z, stream, &r);
+  }
   if (rc != 0) return rc;
   if (info) fill_info(info, probs[0], r);
   const int st = probs[0].status ? probs[0].status : r.c.status;
   if (st) fail(st, "%s", mrrr_status_string(st));
   return st;
+}
+
+// the per-row buffers of one problem of order n as solve() carves them (nblk
+// taken as n), the eigenvector phase's minimum, and the pool and scratch
+// allowances of mrrr_workspace_size
+static size_t workspace_bytes(int64_t n, int64_t m, bool vectors, const mrrr_tuning& t) {
+  const int G = t.grid_density;
+  const int vs = t.vec_wave_slots ? t.vec_wave_slots : 32;
+  const int64_t nb = n;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += align_up(std::max<size_t>(x, 1)) + kAlign; };
+  add(sizeof(Problem));
+  add(sizeof(int64_t) * 2);
+  add(sizeof(int32_t) * n);                   // sprob
+  add(sizeof(double) * n);                    // ds
+  add(sizeof(double) * n);                    // es
+  add(sizeof(int32_t) * n);                   // flag
+  add(sizeof(int32_t) * n);                   // excl
+  add(sizeof(int32_t) * (n / 1024 + 2));      // tiles
+  add(sizeof(int32_t) * 4);                   // total
+  add(sizeof(Counters));
+  add(sizeof(int64_t) * (nb + 1));            // bstart
+  add(sizeof(int32_t) * n);                   // sblk
+  add(sizeof(Block) * nb);
+  add(sizeof(int64_t) * (nb + 1));            // goff
+  add(sizeof(Node) * (size_t)(nb + n + 16));  // nodes
+  add(sizeof(int32_t) * (size_t)(G * n + nb));  // count grid
+  add(sizeof(double) * n * 2);                // lo, hi
+  add(sizeof(int32_t) * n * 2);               // clo, chi
+  add(sizeof(int32_t) * n);                   // snode
+  add(sizeof(uint32_t) * n);                  // sflag
+  add(sizeof(int64_t) * n);                   // scol
+  add(sizeof(double) * n * 2);                // val, sgap
+  add(sizeof(int32_t) * n * 2);               // runflag, runid
+  add(sizeof(int64_t) * (n + 1));             // runs
+  add(sizeof(int32_t) * n * 3);               // vrid, cflag, cid
+  add(sizeof(int64_t) * (n + 1));             // cstart
+  if (vectors) add(sizeof(Cluster) * (size_t)(n / 2 + 1));
+  // pool: roots, speculative candidates of one level, children
+  const size_t rows = (size_t)n + (vectors ? (size_t)(kChildSpecAll + MRRR_WS_CHILD_ROWS_PER_N) * (size_t)n : 0);
+  add(sizeof(Rep) * rows);
+  if (vectors) {
+    const int64_t nch = (n + vs - 1) / vs;
+    add(sizeof(int32_t) * nch);
+    add(sizeof(int32_t) * (nch + 1));
+    add(sizeof(int64_t) * (nch + 1));
+    // every wanted pair's checkpoints at once (checkpointing kernel) and the
+    // stored work vectors of up to 4096 pairs
+    add(sizeof(double) * 4 * (size_t)(m + vs) * (size_t)((n + kSeg - 1) / kSeg));
+    add(sizeof(double) * 4 * (size_t)std::min<int64_t>(m + vs, 4096) * (size_t)n);
+  }
+  add(sizeof(int32_t));  // sort check
+  add(sizeof(int64_t) * n);
+  add(sizeof(double) * n);
+  return b;
+}
+
+}  // namespace mrrr
+
+using namespace mrrr;
+
+extern "C" {
+
+int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z, int64_t ldz,
+              mrrr_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  int rc = check_step_args(n, d, e, range, w, Z, ldz);
+  if (rc != 0) return rc;
+  return step_impl(n, d, e, range, w, Z, ldz, nullptr, 0, false, info, (hipStream_t)stream);
+}
+
+size_t mrrr_workspace_size(int64_t n, mrrr_range range) {
+  if (n < 0 || n > INT32_MAX / 8 || range.kind < 0 || range.kind > 2) return 0;
+  if (range.kind == MRRR_INDEX && n > 0 && (range.il < 1 || range.il > range.iu || range.iu > n)) return 0;
+  if (n == 0) return kAlign;
+  mrrr_tuning t;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    t = g_tune;
+  }
+  const int64_t m = range.kind == MRRR_INDEX ? range.iu - range.il + 1 : n;
+  return workspace_bytes(n, m, true, t);
+}
+
+int mrrr_step_ws(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z, int64_t ldz,
+                 void* work, size_t work_bytes, mrrr_info* info_dev, void* stream) {
+  int rc = check_step_args(n, d, e, range, w, Z, ldz);
+  if (rc != 0) return rc;
+  if (work && work_bytes < kAlign) return fail(-9, "work_bytes too small");
+  mrrr_info info;
+  rc = step_impl(n, d, e, range, w, Z, ldz, work, work_bytes, false, &info, (hipStream_t)stream);
+  if (rc < 0) return rc;
+  if (info_dev) {
+    if (rc != 0 && info.status == 0) info.status = rc;
+    launch_store_info(reinterpret_cast<InfoWords*>(info_dev), *reinterpret_cast<const InfoWords*>(&info),
+                      (hipStream_t)stream);
+    const hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return fail(MRRR_ERR_HIP, "info store failed: %s", hipGetErrorString(e2));
+  }
+  return rc;
+}
+
+int mrrr_get_limits(mrrr_limits* l) {
+  if (!l) return -1;
+  std::lock_guard<std::mutex> lk(g_limits_mu);
+  *l = g_limits;
+  return 0;
+}
+
+int mrrr_set_limits(const mrrr_limits* l) {
+  if (!l) return -1;
+  if (l->max_depth < 1 || l->max_depth > kMaxDepth) return -1;
+  if (!(l->child_growth_limit >= 0.0) || !std::isfinite(l->child_growth_limit)) return -1;
+  std::lock_guard<std::mutex> lk(g_limits_mu);
+  g_limits = *l;
+  return 0;
 }
 
 // ---------------------------------------------------------------------------

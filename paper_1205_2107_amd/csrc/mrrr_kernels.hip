@@ -902,7 +902,7 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
                            const int32_t* __restrict__ snode, const double* __restrict__ lo,
                            const double* __restrict__ hi, const int64_t* __restrict__ scol,
                            uint32_t* __restrict__ sflag, double* __restrict__ sgap, Cluster* __restrict__ clusters,
-                           int max_clusters, Counters* __restrict__ C) {
+                           int max_clusters, Counters* __restrict__ C, int max_depth) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nruns) return;
   const int64_t s = runs[r];
@@ -924,7 +924,7 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
     }
     return;
   }
-  if (nd.depth + 1 > kMaxDepth) {
+  if (nd.depth + 1 > max_depth) {
     set_status(C, 2);
     for (int64_t q = s; q <= e; ++q)
       if (scol[q] >= 0) {
@@ -1002,7 +1002,7 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
                                               int node_base, const Cluster* __restrict__ clusters,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
                                               Rep* __restrict__ pool, unsigned long long pool_cap,
-                                              Counters* __restrict__ C) {
+                                              Counters* __restrict__ C, double growth_limit) {
   __shared__ double st[2 * 4 * kSG];
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
@@ -1095,6 +1095,9 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
         pick = k;
       }
   }
+  // optional hard limit on the element growth (caller's setting): without an
+  // acceptable candidate the cluster gets no child (status 1)
+  if (pick >= 0 && growth_limit > 0.0 && !(gr[pick] <= growth_limit * (blk.gu - blk.gl))) pick = -1;
   const long long off =
       uniform_ll((pick < 0 || base < 0) ? -1 : base + (pick < kSpec ? pick : 0) * (long long)n);
   bool v;
@@ -2666,27 +2669,27 @@ void launch_cls_compact(hipStream_t st, int64_t ntot, const int32_t* runflag, co
 void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, const int64_t* runs,
                      const int32_t* sblk, const int32_t* snode, const double* lo, const double* hi,
                      const int64_t* scol, uint32_t* sflag, double* sgap, Cluster* clusters, int max_clusters,
-                     Counters* C) {
+                     Counters* C, int max_depth) {
   if (nruns == 0) return;
   hipLaunchKernelGGL(k_cls_runs, GRID1(nruns, 64), 0, st, B, N, nruns, runs, sblk, snode, lo, hi, scol, sflag,
-                     sgap, clusters, max_clusters, C);
+                     sgap, clusters, max_clusters, C, max_depth);
 }
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
-                  int spec) {
+                  int spec, double growth_limit) {
   // a lone or few wavefronts are latency-bound (branch-free stores), a full
   // chip is issue-bound (masked stores)
   static_assert(kChildSpecAll == kChildCand, "every candidate");
   if (spec == kChildSpecMany)
     hipLaunchKernelGGL((k_child<true, kChildSpecMany>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base,
-                       clusters, lo, hi, pool, pool_cap, C);
+                       clusters, lo, hi, pool, pool_cap, C, growth_limit);
   else if (spec == kChildSpecFew)
     hipLaunchKernelGGL((k_child<false, kChildSpecFew>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
-                       node_base, clusters, lo, hi, pool, pool_cap, C);
+                       node_base, clusters, lo, hi, pool, pool_cap, C, growth_limit);
   else
     hipLaunchKernelGGL((k_child<false, kChildSpecAll>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
-                       node_base, clusters, lo, hi, pool, pool_cap, C);
+                       node_base, clusters, lo, hi, pool, pool_cap, C, growth_limit);
 }
 
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
@@ -2770,6 +2773,14 @@ void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t*
                      double* tmp, double* Z) {
   hipLaunchKernelGGL(k_sort_problem, dim3(nprob), dim3(64), 0, st, P, bad, w, perm);
   if (Z != nullptr) hipLaunchKernelGGL(k_permute_cols, dim3(nprob), dim3(256), 0, st, P, bad, perm, tmp, Z);
+}
+
+__global__ void k_store_info(InfoWords* __restrict__ dst, InfoWords v) {
+  if (threadIdx.x < 18) dst->w[threadIdx.x] = v.w[threadIdx.x];
+}
+
+void launch_store_info(InfoWords* dst, InfoWords v, hipStream_t st) {
+  hipLaunchKernelGGL(k_store_info, dim3(1), dim3(64), 0, st, dst, v);
 }
 
 void launch_values_only(hipStream_t st, const Problem* P, const Block* B, const Node* N, int64_t ntot,

@@ -31,10 +31,10 @@ void launch_cls_compact(hipStream_t st, int64_t ntot, const int32_t* runflag, co
 void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, const int64_t* runs,
                      const int32_t* sblk, const int32_t* snode, const double* lo, const double* hi,
                      const int64_t* scol, uint32_t* sflag, double* sgap, Cluster* clusters, int max_clusters,
-                     Counters* C);
+                     Counters* C, int max_depth);
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
-                  int spec);
+                  int spec, double growth_limit);
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
                   int32_t* snode, uint32_t* sflag, double* sgap);
@@ -62,5 +62,12 @@ void launch_sort_fix(hipStream_t st, const Problem* P, int nprob, const int32_t*
 void launch_values_only(hipStream_t st, const Problem* P, const Block* B, const Node* N, int64_t ntot,
                         const int32_t* sblk, const int32_t* snode, const int64_t* scol, const double* lo,
                         const double* hi, const double* ds, double* w);
+
+// the report of a call (mrrr_info, 18 words) stored to device memory by a
+// kernel that takes it by value
+struct InfoWords {
+  int64_t w[18];
+};
+void launch_store_info(InfoWords* dst, InfoWords v, hipStream_t st);
 
 }  // namespace mrrr

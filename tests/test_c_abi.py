@@ -100,3 +100,57 @@ def test_tuning_roundtrip():
     for ok in (64, 4096, 0):
         t.vec_ckpt_min_n = ok
         assert lib.mrrr_set_tuning(ctypes.byref(t)) == 0
+
+
+def test_workspace_size_is_host_only_and_monotone():
+    """mrrr_workspace_size needs no device: 0 for invalid arguments, growing
+    with the order, smaller for a narrow index range than for all pairs"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    r = _lib.MrrrRange()
+    r.kind = _lib.MRRR_ALL
+    assert lib.mrrr_workspace_size(-1, r) == 0
+    sizes = [lib.mrrr_workspace_size(n, r) for n in (1, 10, 100, 1000, 20000)]
+    assert all(a < b for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] < 64 << 30
+    r.kind = _lib.MRRR_INDEX
+    r.il, r.iu = 5, 4
+    assert lib.mrrr_workspace_size(100, r) == 0
+    r.il, r.iu = 1, 10
+    sub = lib.mrrr_workspace_size(20000, r)
+    assert 0 < sub < sizes[-1]
+    r.kind = 9
+    assert lib.mrrr_workspace_size(10, r) == 0
+
+
+def test_workspace_entry_point_argument_checks():
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    r = _lib.MrrrRange()
+    r.kind = _lib.MRRR_ALL
+    fake = ctypes.c_void_p(256)
+    assert lib.mrrr_step_ws(-1, None, None, r, None, None, 1, None, 0, None, None) == -1
+    assert lib.mrrr_step_ws(5, fake, fake, r, fake, fake, 4, fake, 1 << 20, None, None) == -7
+    assert lib.mrrr_step_ws(5, fake, fake, r, fake, fake, 5, fake, 16, None, None) == -9
+    assert lib.mrrr_step_ws(0, None, None, r, None, None, 1, fake, 1 << 20, None, None) == 0
+
+
+def test_limits_round_trip_and_validation():
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    old = _lib.MrrrLimits()
+    assert lib.mrrr_get_limits(ctypes.byref(old)) == 0
+    assert old.max_depth == 64 and old.child_growth_limit == 0.0
+    bad = _lib.MrrrLimits()
+    for md, gl in [(0, 0.0), (65, 0.0), (10, -1.0), (10, float("nan")), (10, float("inf"))]:
+        bad.max_depth, bad.child_growth_limit = md, gl
+        assert lib.mrrr_set_limits(ctypes.byref(bad)) == -1
+    new = _lib.MrrrLimits()
+    new.max_depth, new.child_growth_limit = 3, 1.5
+    try:
+        assert lib.mrrr_set_limits(ctypes.byref(new)) == 0
+        got = _lib.MrrrLimits()
+        lib.mrrr_get_limits(ctypes.byref(got))
+        assert got.max_depth == 3 and got.child_growth_limit == 1.5
+    finally:
+        lib.mrrr_set_limits(ctypes.byref(old))
