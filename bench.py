@@ -1,24 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X MRRR tridiagonal eigensolver (FP64, one GPU).
 
-Step = one pass of the whole solver over one batch of synthetic input: the full
-spectrum (all eigenvalues and eigenvectors) of three order-20000 tridiagonals --
-random U(-1,1) entries (seed 2001), the "1-2-1" Toeplitz matrix, and a spectrum
-geometrically spaced in [1e-8, 1] (seed 2003) -- solved together by one call of
-the batched entry point (one set of launches for the three problems; launch
-shapes from the autotuner, chosen during the untimed warm-up).  Metric: FP64
-eigenpairs per second (60000 eigenpairs per step), inputs resident in HBM,
-outputs preallocated by the caching allocator, stream synchronized around the
-timed region.  The latency of one single-problem call per type is reported
-beside it (measured after the timed region).
+Step = one pass of the whole solver over the single-tridiagonal workload: the
+full spectrum (all eigenvalues and eigenvectors) of three order-20000
+tridiagonals -- random U(-1,1) entries (seed 2001), the "1-2-1" Toeplitz matrix,
+and a spectrum geometrically spaced in [1e-8, 1] (seed 2003) -- each solved by
+its own single-problem call (mrrr_step).  Metric: FP64 eigenpairs per second
+(60000 eigenpairs per step), inputs resident in HBM, outputs from the caching
+allocator, stream synchronized around the timed region.  Every call is also
+timed on its own (each call synchronizes its stream); the median per type is
+reported beside the value.
 
 Also reported on the same JSON line:
   roofline      the dominant kernel's achieved rate from HIP events recorded by
                 the library on the launch stream over the timed region
                 (algorithmic work / event time) against the MI355X peak
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the workload
+  cpu_baseline  the CPU oracle (single thread, pinned to one host core) on a
+                bounded sample of the workload, with the host CPU model
+  three_in_one_call  the same three problems solved together by one call of the
+                batched entry point (launch shapes from its autotuner)
   batched       solves/s of the batched entry point on 4096 mixed problems (sizes
                 log-uniform in [32, 2048]) and of a loop of single-problem calls
+  backward      the differentiation workload: 256 problems of order 512
+                (batched) and one of order 8192, forward and hand-written FP64
+                MFMA backward, against a loop of single-problem calls
 """
 import argparse
 import json
@@ -46,18 +51,51 @@ def make_inputs(n):
             ("geometric_1e-8", *W.geometric(n, W.SEEDS["c2_geometric"]))]
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
 def cpu_baseline(n):
     """Oracle (single-threaded C, as it stands) on a bounded sample: the 1500
-    smallest eigenpairs of the random n = 20000 matrix."""
+    smallest eigenpairs of the random n = 20000 matrix, the process pinned to
+    one host core while it runs."""
     import oracle
     from paper_1205_2107_amd import workloads as W
     d, e = W.random_uniform(n, W.SEEDS["c2_random"])
     k = 1500
-    t0 = time.perf_counter()
-    w, Z, st = oracle.mrrr(d, e, kind=oracle.RANGE_INDEX, il=1, iu=k)
-    dt = time.perf_counter() - t0
+    model, logical, usable = host_cpu()
+    keep = None
+    pinned = None
+    try:
+        keep = os.sched_getaffinity(0)
+        pinned = min(keep)
+        os.sched_setaffinity(0, {pinned})
+    except (AttributeError, OSError):
+        pinned = None
+    try:
+        t0 = time.perf_counter()
+        w, Z, st = oracle.mrrr(d, e, kind=oracle.RANGE_INDEX, il=1, iu=k)
+        dt = time.perf_counter() - t0
+    finally:
+        if keep is not None:
+            os.sched_setaffinity(0, keep)
     return {"value": k / dt, "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"random n={n} (seed 2001), eigenpairs 1..{k} (il..iu), {dt:.1f} s on 1 host thread"}
+            "sample": f"random n={n} (seed 2001), eigenpairs 1..{k} (il..iu), {dt:.1f} s on 1 host thread",
+            "host_cpu": model, "host_logical_cpus": logical, "host_cpus_usable": usable,
+            "pinned_core": pinned}
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1205_2107_amd", "csrc", "mrrr_kernels.hip")
@@ -148,6 +186,91 @@ def batched_leg(torch, M, count, loop_count):
             "speedup_vs_looped": (count / tb) / (loop_count / tl)}
 
 
+def median(xs):
+    xs = sorted(xs)
+    k = len(xs)
+    return 0.5 * (xs[(k - 1) // 2] + xs[k // 2]) if k else 0.0
+
+
+def backward_leg(torch, M, reps=5, loop_count=64):
+    """Differentiation workload: 256 problems of order 512 (separated spectra)
+    through the batched forward and the batched FP64-MFMA backward, one problem
+    of order 8192; a loop of single-problem forward + backward calls over the
+    first loop_count problems of the batch as the looped baseline.  The
+    backward work is 4 n^3 flops per problem (two n x n x n products)."""
+    from paper_1205_2107_amd import workloads as W
+    out = {}
+    nb, count = 512, 256
+    probs = [W.separated(nb, W.SEEDS["c5"] + k) for k in range(count)]
+    d, e, ns, off = W.pack(probs)
+    dt = torch.tensor(d, device="cuda")
+    et = torch.tensor(e, device="cuda")
+    g = torch.Generator(device="cpu").manual_seed(W.SEEDS["c5"])
+    gw = torch.randn(count * nb, generator=g, dtype=torch.float64).cuda()
+    gZ = torch.randn(count * nb * nb, generator=g, dtype=torch.float64).cuda()
+    wb, Zb, zoff = M.eigh_tridiagonal_batched(dt, et, ns)
+    M.eigh_tridiagonal_backward_batched(wb, Zb, ns, gw, gZ)
+    torch.cuda.synchronize()
+    tf, tbw = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        wb, Zb, zoff = M.eigh_tridiagonal_batched(dt, et, ns)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        M.eigh_tridiagonal_backward_batched(wb, Zb, ns, gw, gZ)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tbw.append(t2 - t1)
+    flops = 4.0 * nb ** 3 * count
+    out["batched_256x512"] = {"forward_s": median(tf), "backward_s": median(tbw),
+                              "backward_tflops": flops / median(tbw) / 1e12,
+                              "backward_frac_of_fp64_mfma_peak": flops / median(tbw) / 1e12 / PEAK_FP64_MATRIX_TFLOPS,
+                              "solves_per_s": count / (median(tf) + median(tbw))}
+    # looped: single forward + single backward per problem
+    singles = []
+    for k in range(loop_count):
+        singles.append((torch.tensor(probs[k][0], device="cuda"), torch.tensor(probs[k][1], device="cuda"),
+                        gw[k * nb:(k + 1) * nb], gZ[k * nb * nb:(k + 1) * nb * nb].reshape(nb, nb).t()))
+    for a, b, c, G in singles[:4]:
+        w1, Z1 = M.eigh_tridiagonal(a, b)
+        M.eigh_tridiagonal_backward(w1, Z1, c, G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b, c, G in singles:
+        w1, Z1 = M.eigh_tridiagonal(a, b)
+        M.eigh_tridiagonal_backward(w1, Z1, c, G)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    out["batched_256x512"]["looped_solves_per_s"] = loop_count / tl
+    out["batched_256x512"]["speedup_vs_looped"] = out["batched_256x512"]["solves_per_s"] / (loop_count / tl)
+    # one problem of order 8192
+    n8 = 8192
+    d8, e8 = W.separated(n8, W.SEEDS["c5"])
+    d8t, e8t = torch.tensor(d8, device="cuda"), torch.tensor(e8, device="cuda")
+    gw8 = torch.randn(n8, generator=g, dtype=torch.float64).cuda()
+    gZ8 = torch.randn(n8, n8, generator=g, dtype=torch.float64).cuda()
+    w8, Z8 = M.eigh_tridiagonal(d8t, e8t)
+    M.eigh_tridiagonal_backward(w8, Z8, gw8, gZ8)
+    torch.cuda.synchronize()
+    tf8, tb8 = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        w8, Z8 = M.eigh_tridiagonal(d8t, e8t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        M.eigh_tridiagonal_backward(w8, Z8, gw8, gZ8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf8.append(t1 - t0)
+        tb8.append(t2 - t1)
+    f8 = 4.0 * n8 ** 3
+    out["single_8192"] = {"forward_s": median(tf8), "backward_s": median(tb8),
+                          "backward_tflops": f8 / median(tb8) / 1e12,
+                          "backward_frac_of_fp64_mfma_peak": f8 / median(tb8) / 1e12 / PEAK_FP64_MATRIX_TFLOPS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,10 +279,11 @@ def main():
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--looped-count", type=int, default=512)
     ap.add_argument("--profile-once", action="store_true",
-                    help="autotune, then the step twice (for a profiler run); no JSON")
+                    help="the step twice after one warm-up step (for a profiler run); no JSON")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="copy BYTES between two device buffers (counter calibration); no JSON")
     args = ap.parse_args()
@@ -185,49 +309,47 @@ def main():
     log(f"[bench] generating inputs n={n}")
     inputs = make_inputs(n)
     names = [name for name, _, _ in inputs]
-    d_all, e_all, ns, _ = W.pack([(d, e) for _, d, e in inputs])
-    d_dev = torch.tensor(d_all, device="cuda")
-    e_dev = torch.tensor(e_all, device="cuda")
+    dev = [(torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda")) for _, d, e in inputs]
     torch.cuda.synchronize()
+
+    def step(times=None):
+        infos = []
+        for k, (dd, ee) in enumerate(dev):
+            t0 = time.perf_counter()
+            w, Z, info = M.eigh_tridiagonal(dd, ee, return_info=True)  # synchronizes its stream
+            if times is not None:
+                times[k].append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+            del w, Z
+        return infos
+
     if args.profile_once:
-        # the launch shapes the timed steps use: the same autotuning first
-        M.autotune_batched(d_dev, e_dev, ns)
-        M.eigh_tridiagonal_batched(d_dev, e_dev, ns)
+        step()
         torch.cuda.synchronize()
-        M.eigh_tridiagonal_batched(d_dev, e_dev, ns)
+        step()
+        step()
         torch.cuda.synchronize()
-        log("[bench] profiled one step (twice, after autotuning)")
+        log("[bench] profiled the step twice (after one warm-up step)")
         return
-    log("[bench] warmup (autotuning the launch shapes for this batch)")
-    tuning = M.autotune_batched(d_dev, e_dev, ns)
+    log("[bench] warmup")
     for _ in range(args.warmup):
-        M.eigh_tridiagonal_batched(d_dev, e_dev, ns)
+        step()
     torch.cuda.synchronize()
     M.profile(True)
+    times = [[] for _ in dev]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        w, Z, zoff, infos = M.eigh_tridiagonal_batched(d_dev, e_dev, ns, return_info=True)
+        infos = step(times)
         log(f"[bench] step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = M.profile_read()
     M.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    pairs_per_step = int(ns.sum())
+    pairs_per_step = n * len(dev)
     value = pairs_per_step / (ms_per_step * 1e-3)
-    # single-problem latency per type (after the timed region)
-    per_type = {}
-    for name, d, e in inputs:
-        dd = torch.tensor(d, device="cuda")
-        ee = torch.tensor(e, device="cuda")
-        M.eigh_tridiagonal(dd, ee)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        M.eigh_tridiagonal(dd, ee)
-        torch.cuda.synchronize()
-        per_type[name] = (time.perf_counter() - ts) * 1e3
-        del dd, ee
+    per_type = {name: median(times[k]) for k, name in enumerate(names)}
     out = {
         "metric": "FP64 eigenpairs/s at n=20k full spectrum (random, 1-2-1, geometric types)",
         "value": value,
@@ -241,19 +363,43 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"STEP full spectrum, three tridiagonals of order {n} per step, one batched call",
-                   "n": n, "types": names, "tuning": tuning,
-                   "single_call_ms_per_type": per_type,
-                   "tree": {"levels": infos[0]["levels"], "nodes": infos[0]["nodes"],
-                            "max_depth": infos[0]["max_depth"]}},
+        "config": {"workload": f"STEP full spectrum, three single tridiagonals of order {n} per step "
+                               "(one mrrr_step call each)",
+                   "n": n, "types": names,
+                   "median_call_ms_per_type": per_type,
+                   "calls_per_type": args.steps,
+                   "tree": {name: {"levels": infos[k]["levels"], "nodes": infos[k]["nodes"],
+                                   "max_depth": infos[k]["max_depth"]} for k, name in enumerate(names)}},
         "roofline": roofline(prof),
         "kernels": {k: {"ms_per_step": v["ms"] / args.steps, "launches": v["launches"],
                         "tflops": (v["work"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
                     for k, v in prof.items()},
     }
+    # the same three problems in one batched call
+    log("[bench] three problems in one batched call")
+    d_all, e_all, ns, _ = W.pack([(d, e) for _, d, e in inputs])
+    d_dev = torch.tensor(d_all, device="cuda")
+    e_dev = torch.tensor(e_all, device="cuda")
+    tuning = M.autotune_batched(d_dev, e_dev, ns)
+    tb = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.eigh_tridiagonal_batched(d_dev, e_dev, ns)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+    out["three_in_one_call"] = {"ms": median(tb) * 1e3, "eigenpairs_per_s": pairs_per_step / median(tb),
+                                "tuning": tuning}
+    del d_dev, e_dev
+    torch.cuda.empty_cache()
     if not args.no_batched:
         log("[bench] batched leg")
         out["batched"] = batched_leg(torch, M, args.batched_count, args.looped_count)
+        torch.cuda.empty_cache()
+    if not args.no_backward:
+        log("[bench] backward leg")
+        out["backward"] = backward_leg(torch, M)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n)

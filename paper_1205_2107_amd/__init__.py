@@ -226,19 +226,33 @@ def _make_function():
 
     class MRRRFunction(torch.autograd.Function):
         """(d, e) -> (w, Z) by the GPU MRRR solver; backward by the GPU adjoint
-        kernels.  Requires distinct eigenvalues for the eigenvector term."""
+        kernels.  Requires distinct eigenvalues for the eigenvector term.
+
+        MRRRFunction.apply(d, e, recompute): with recompute set, only d, e and
+        w are kept for the backward (O(n) memory instead of the n x n
+        eigenvectors), which solves again for Z; the solver is deterministic,
+        so the recomputed Z and the gradients equal those of the saved Z bit
+        for bit."""
 
         @staticmethod
-        def forward(ctx, d, e):
+        def forward(ctx, d, e, recompute=False):
             w, Z = eigh_tridiagonal(d, e)
-            ctx.save_for_backward(w, Z)
+            ctx.recompute = bool(recompute)
+            if ctx.recompute:
+                ctx.save_for_backward(d, e, w)
+            else:
+                ctx.save_for_backward(w, Z)
             return w, Z
 
         @staticmethod
         def backward(ctx, gw, gZ):
-            w, Z = ctx.saved_tensors
+            if ctx.recompute:
+                d, e, w = ctx.saved_tensors
+                _, Z = eigh_tridiagonal(d.detach(), e.detach())
+            else:
+                w, Z = ctx.saved_tensors
             gd, ge = eigh_tridiagonal_backward(w, Z, gw, gZ)
-            return gd, ge
+            return gd, ge, None
 
     return MRRRFunction
 

@@ -1341,6 +1341,12 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
 // -d gamma_r / d lam comes with the transforms and no solve is needed.
 __device__ __forceinline__ double dstep(double w, double dx) { return fma(w * w, dx, -1.0); }
 
+// the write-back address and entry mask of a lane's segment, parked in LDS
+__device__ __forceinline__ void zp_lds_store(double** zp, uint32_t* zm, int lane, double* p, uint32_t m) {
+  zp[lane] = p;
+  zm[lane] = m;
+}
+
 __device__ __forceinline__ int wave_max(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
@@ -1658,12 +1664,18 @@ __device__ inline double twist_derivative(bool go, int role, const Rep* __restri
 //    where a z is zero the row of L D L^T - lam I gives the next one from the
 //    one before.  Accumulates ||z||^2 and the signed entry of largest
 //    magnitude (ties: smaller row) of the lane's half; with kWrite, stores
-//    z * scale into Zc (z_r by the caller).
+//    z * scale into Zc (z_r by the caller): each lane parks the (up to) 8
+//    entries of its segment in LDS (zt, with the address of the segment's
+//    first entry in zaddr and a mask of the entries it owns in zm), and the
+//    wavefront writes them back column segment by column segment, 8 lanes
+//    per segment (64 contiguous bytes each, 8 segments per store).
 template <int kPairSlots, bool kMayGuard, bool kWrite>
 __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, int n, double pivmin, bool guard,
                                   double lam, double xlast, int r, const double* __restrict__ SC,
                                   const double* __restrict__ PC, int c, double* __restrict__ lds,
-                                  double* __restrict__ Zc, double scale, double& nrm_out, double& zbest_out) {
+                                  double* __restrict__ Zc, double scale, double& nrm_out, double& zbest_out,
+                                  double* __restrict__ zt = nullptr, double** __restrict__ zaddr = nullptr,
+                                  uint32_t* __restrict__ zm = nullptr) {
   const int nseg = (n + kSeg - 1) / kSeg;
   const int klast = (n - 2) / kSeg;  // segment of row n-2
   const bool has = go && (role ? r <= n - 2 : r >= 1);
@@ -1704,6 +1716,8 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
         else
           quotients(std::false_type{});
         // rows in solve order: descending (role 0), ascending (role 1)
+        double zv[kSeg];
+        uint32_t msk = 0;
 #pragma unroll
         for (int u = kSeg - 1; u >= 0; --u) {
           const int o = role ? kSeg - 1 - u : u;
@@ -1724,13 +1738,30 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
             }
           }
           zn = isfinite(zn) ? zn : 0.0;
+          zv[o] = zn * scale;
           if (act) {
-            if (kWrite) Zc[role ? row + 1 : row] = zn * scale;
+            msk |= 1u << o;
             zp = zc;
             zc = zn;
             nrm += zn * zn;
             if (role ? fabs(zn) > fabs(zbest) : fabs(zn) >= fabs(zbest)) zbest = zn;
           }
+        }
+        if (kWrite) {
+          // entry o of the lane's segment is row k kSeg + o (role 0) or
+          // k kSeg + o + 1 (role 1) of its column
+          const int lane = threadIdx.x & 63;
+#pragma unroll
+          for (int o = 0; o < kSeg; o += 2)
+            *reinterpret_cast<double2*>(zt + lane * kSeg + o) = make_double2(zv[o], zv[o + 1]);
+          zp_lds_store(zaddr, zm, lane, Zc + k * kSeg + role, msk);
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < 64 / kSeg; ++i) {
+            const int q = i * kSeg + (lane >> 3), u = lane & (kSeg - 1);
+            if ((zm[q] >> u) & 1u) zaddr[q][u] = zt[q * kSeg + u];
+          }
+          __syncthreads();
         }
       });
   nrm_out = nrm;
@@ -1846,6 +1877,9 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   __shared__ int s_n[kPairSlots];
   __shared__ int64_t s_lrow0[kPairSlots];
   __shared__ int64_t s_pn[kPairSlots];
+  __shared__ double s_zt[64 * kSeg];  // staged eigenvector entries of the write pass
+  __shared__ double* s_zp[64];
+  __shared__ uint32_t s_zm[64];
   const int lane = threadIdx.x;
   const int c = lane >> 1;
   const int role = lane & 1;
@@ -1911,7 +1945,7 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
     double nrm_d, zb_d;
     if (n > 1)
       solve_pass<kPairSlots, true, true>(solve, role, R, n, pivmin, g_last, lam_last, R[n - 1].D - lam_last, r, SC,
-                                         PC, cs, lds, Zc, scale, nrm_d, zb_d);
+                                         PC, cs, lds, Zc, scale, nrm_d, zb_d, s_zt, s_zp, s_zm);
     if (act && role) Zc[solve ? r : 0] = scale;  // z_r = 1 (n = 1: the unit vector)
     if (n > 1) {
       // the signed entry of largest magnitude (ties: smaller row) decides the

@@ -237,3 +237,41 @@ def test_generators():
     probs = W.batched_mix(200, 4001)
     ns = np.array([p[0].shape[0] for p in probs])
     assert ns.min() >= 32 and ns.max() <= 2048
+
+
+def _exact_eig(d, e, dps=50):
+    """Eigenpairs of the tridiagonal to 50 decimal digits (mpmath's symmetric
+    eigensolver in multiprecision), rounded to doubles, ascending."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = dps
+    n = len(d)
+    A = mpmath.zeros(n, n)
+    for i in range(n):
+        A[i, i] = mpmath.mpf(float(d[i]))
+        if i + 1 < n:
+            A[i, i + 1] = A[i + 1, i] = mpmath.mpf(float(e[i]))
+    E, Q = mpmath.eigsy(A)
+    w = np.array([float(x) for x in E])
+    V = np.array([[float(Q[i, j]) for j in range(n)] for i in range(n)])
+    order = np.argsort(w)
+    return w[order], V[:, order]
+
+
+EXACT_CASES = [("wilkinson21", lambda: W.wilkinson(21)), ("glued42", lambda: W.glued_wilkinson(42, 7)),
+               ("graded20", lambda: (2.0 ** -np.arange(20.0), 2.0 ** -np.arange(0.5, 19.5))),
+               ("geometric40", lambda: W.geometric(40, 9)), ("random30", lambda: W.random_uniform(30, 5))]
+
+
+@pytest.mark.parametrize("case", EXACT_CASES, ids=lambda c: c[0])
+def test_oracle_vs_multiprecision(case):
+    # the exact eigenpairs (to 50 digits) meet the oracle within the method's
+    # error bounds: eigenvalues within 2 n eps ||T||_1, eigenvector groups
+    # within the Davis-Kahan bound (Sec. 2.3, Eq. Tresnorm / Eq. Torthogo)
+    from common import compare_vectors
+    d, e = case[1]()
+    w, Z, st = oracle.mrrr(d, e)
+    we, Ve = _exact_eig(d, e)
+    assert st == 0
+    assert np.abs(w - we).max() <= eig_tol(d, e)
+    worst, checked, _ = compare_vectors(d, e, we, Ve, Z)
+    assert checked > 0 and worst <= 1.0
