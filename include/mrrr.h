@@ -137,6 +137,29 @@ int mrrr_step_ws(int64_t n, const double* d, const double* e, mrrr_range range, 
                  int64_t ldz, void* work, size_t work_bytes, mrrr_info* info_dev, void* stream);
 
 /*
+ * mrrr_step_noalloc -- mrrr_step_ws whose workspace is a fixed device array
+ * inside the library, for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  The call makes no hipMalloc / hipFree or other allocating call
+ * and uses one stream (no second stream for the eigenvector kernels).
+ *   n          0 .. MRRR_NOALLOC_MAX_N; larger n returns -1          [arg 1]
+ *   d, e, range, w, Z, ldz, info_dev, stream   as for mrrr_step_ws   [args 2-9]
+ * The array (MRRR_NOALLOC_SCRATCH_BYTES, 256-byte aligned) is held on each
+ * device the library runs this entry point on until the process ends; its
+ * device address is taken once per device, on the first call there.  Every
+ * call on a device uses the same array: calls that overlapped in time on one
+ * device would race.  The library serializes its calls per device and each
+ * call returns only after its work on `stream` has finished, so calls through
+ * this library do not overlap; the array keeps the last call's contents and
+ * each call initializes what it reads.  A tree whose representations do not
+ * fit returns MRRR_ERR_CAPACITY.
+ */
+#define MRRR_NOALLOC_MAX_N 1024
+#define MRRR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mrrr_step_noalloc(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
+                      int64_t ldz, mrrr_info* info_dev, void* stream);
+
+/*
  * Limits of the representation tree.  Lowering them makes the solver report
  * the corresponding status instead of going on (used by the tests of those
  * paths):

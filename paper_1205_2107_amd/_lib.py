@@ -15,7 +15,7 @@ COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singl
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
-           "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits")
+           "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc")
 KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt")
 
 
@@ -77,6 +77,8 @@ def load():
     lib.mrrr_workspace_size.argtypes = [I64, MrrrRange]
     lib.mrrr_step_ws.restype = ctypes.c_int
     lib.mrrr_step_ws.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, ctypes.c_size_t, P, P]
+    lib.mrrr_step_noalloc.restype = ctypes.c_int
+    lib.mrrr_step_noalloc.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, P]
     lib.mrrr_get_limits.restype = ctypes.c_int
     lib.mrrr_get_limits.argtypes = [ctypes.POINTER(MrrrLimits)]
     lib.mrrr_set_limits.restype = ctypes.c_int

@@ -1110,3 +1110,60 @@ const char* mrrr_status_string(int code) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: the workspace is a file-scope device array.  In
+// host code the array's name is only a host-side stand-in; its device address
+// on each GPU is taken once, with that device current, by hipGetSymbolAddress,
+// and only that address is passed to the solver.
+
+namespace mrrr {
+
+static __device__ __align__(256) unsigned char scratch[MRRR_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static std::map<int, void*> g_noalloc_ptr;
+
+// device address of `scratch` on the current device (set up on the first call
+// on each device)
+static int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(MRRR_ERR_NO_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(dev);
+  if (it == g_noalloc_ptr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(MRRR_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    it = g_noalloc_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
+}  // namespace mrrr
+
+extern "C" int mrrr_step_noalloc(int64_t n, const double* d, const double* e, mrrr_range range, double* w,
+                                 double* Z, int64_t ldz, mrrr_info* info_dev, void* stream) {
+  int rc = check_step_args(n, d, e, range, w, Z, ldz);
+  if (rc != 0) return rc;
+  if (n > MRRR_NOALLOC_MAX_N)
+    return fail(-1, "n = %lld exceeds the allocation-free limit of %d rows", (long long)n, MRRR_NOALLOC_MAX_N);
+  void* ptr = nullptr;
+  if (n > 0 && (rc = noalloc_scratch(&ptr)) != 0) return rc;
+  mrrr_info info;
+  // one stream (no second stream for the eigenvector kernels), every buffer
+  // carved from the array
+  rc = step_impl(n, d, e, range, w, Z, ldz, ptr, MRRR_NOALLOC_SCRATCH_BYTES, true, &info, (hipStream_t)stream);
+  if (rc < 0) return rc;
+  if (info_dev) {
+    if (rc != 0 && info.status == 0) info.status = rc;
+    launch_store_info(reinterpret_cast<InfoWords*>(info_dev), *reinterpret_cast<const InfoWords*>(&info),
+                      (hipStream_t)stream);
+    const hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return fail(MRRR_ERR_HIP, "info store failed: %s", hipGetErrorString(e2));
+  }
+  return rc;
+}
