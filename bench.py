@@ -135,6 +135,29 @@ def measured_traffic(kernel):
         return None
 
 
+def measured_issue(kernel):
+    """Issued FP64 fraction, instruction-mix ceiling and VALU occupancy of
+    `kernel` from the committed SQ-counter summary (profiles/valu_counters_n20000.md),
+    or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "valu_counters_n20000.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k.strip("`")] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    sym = KERNEL_SYMBOL.get(kernel, kernel)
+    try:
+        return {"issued_frac": float(fields[f"{sym}.issued_frac"]), "mix_ceiling": float(fields[f"{sym}.mix_ceiling"]),
+                "valu_busy": float(fields[f"{sym}.valu_busy"])}
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(prof):
     """dominant kernel by event time; ALU-bound kernels against the FP64 vector
     peak, the eigenvector kernels (whose algorithmic bytes are the Z entries
@@ -151,6 +174,9 @@ def roofline(prof):
         ach = p["work"] / (p["ms"] * 1e-3) / 1e12
         out.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS})
+    # the issued measure beside the algorithmic one: FP64 VALU flops from SQ
+    # counters, the ceiling the instruction mix sets, the SIMD share issuing VALU
+    out["issue"] = measured_issue(name)
     return out
 
 
