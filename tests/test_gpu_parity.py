@@ -2,9 +2,12 @@
 
 Bars (tests/common.py): eigenvalues within 2 n eps ||T||_1 of the oracle,
 eigenvectors within the Davis-Kahan bound of the oracle's (group-wise), residual
-and orthogonality within 10 n eps.  Full-size cases are checked on sampled
-eigenvalues (plain Sturm bisection on T), closed forms and invariants.
+and orthogonality within 10 n eps.  Full-size cases compare every eigenvalue
+with the oracle's stored values (tests/golden/, written by the oracle alone),
+eigenvectors with oracle index windows, plus closed forms and invariants.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -51,6 +54,18 @@ def assert_parity(d, e, w, Z, wo, Zo, full_w=None, sel=None):
         assert worst <= 1.0
         assert residual_ratio(d, e, w, Z) <= 10.0
         assert orth_ratio(Z) <= 10.0
+        assert sign_rule_holds(Z)
+
+
+def sign_rule_holds(Z):
+    """The largest-magnitude entry of every column is positive.  The solver
+    takes the sign from the unnormalized vector, so where two entries of
+    opposite sign agree in magnitude to rounding (glued Wilkinson vectors)
+    either may be the positive one: an entry within 8 ulps of the column's
+    largest magnitude must be positive."""
+    A = np.abs(Z)
+    top = A >= A.max(axis=0, keepdims=True) * (1.0 - 8.0 * EPS)
+    return bool(np.all(np.any(top & (Z > 0), axis=0)))
 
 
 def small_cases():
@@ -269,6 +284,13 @@ def test_repeatable(M):
 # full size: n = 20000, the three spectrum types of the benchmark
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    return np.load(os.path.join(GOLDEN, f"eigvals_{name}.npy"), allow_pickle=False)
+
+
 def gpu_metrics(d, e, w, Z):
     """residual and orthogonality ratios computed on the GPU in FP64 panels"""
     n = len(d)
@@ -288,7 +310,17 @@ def gpu_metrics(d, e, w, Z):
         G = Zp.t() @ Z
         G[:, c0:c0 + step] -= torch.eye(Zp.shape[1], dtype=torch.float64, device="cuda")
         orth = max(orth, float(G.abs().max()))
-    return res / (n * EPS * tn), orth / (max(n, 1.0 / 1e-3) * EPS)
+    return res / (n * EPS * tn), orth / (max(n, 1.0 / 1e-3) * EPS)  # n eps from n = 1000 on
+
+
+GOLDEN_OF = {"random": "c2_random_n20000", "toeplitz": "c2_toeplitz_n20000", "geometric": "c2_geometric_n20000",
+             "glued_1": "glued1_n20000"}
+
+
+def oracle_metric(name, key):
+    import json
+    with open(os.path.join(GOLDEN, "oracle_metrics.json")) as f:
+        return json.load(f)[name][key]
 
 
 # glued_1: glued Wilkinson blocks whose short last block holds an isolated
@@ -296,8 +328,10 @@ def gpu_metrics(d, e, w, Z):
 # the twist search must still find the vector's peak in the last rows.  The
 # matrix also holds pairs of eigenvalues equal to the last bit inside clusters
 # of ~950 whose child representations can only be had with large element
-# growth (LAPACK's dstemr stops on it without a suitable representation): the
-# residual bound holds, orthogonality (about 15 n eps) is allowed 20 n eps there.
+# growth (LAPACK's dstemr stops on it without a suitable representation).  The
+# oracle itself ends above 10 n eps in orthogonality there (its figure is
+# stored in tests/golden/oracle_metrics.json); the GPU is held to that figure
+# with a margin of 1.5.
 @pytest.mark.parametrize("kind", ["random", "toeplitz", "geometric", "glued_1"])
 def test_full_size_n20000(M, kind):
     n = 20000
@@ -316,12 +350,16 @@ def test_full_size_n20000(M, kind):
     wn = w.cpu().numpy()
     assert np.all(np.diff(wn) >= 0)
     r, o = gpu_metrics(d, e, w, Z)
-    assert r <= 10.0 and o <= (20.0 if kind == "glued_1" else 10.0)
+    bar = max(10.0, 1.5 * oracle_metric("glued1_n20000", "orth")) if kind == "glued_1" else 10.0
+    assert r <= 10.0 and o <= bar, (r, o)
+    # every eigenvalue against the oracle's
     tol = eig_tol(d, e)
-    idx = np.unique(np.r_[1, 2, n // 3, n // 2, n - 1, n, np.random.default_rng(0).integers(1, n + 1, 14)])
-    for j in idx:
-        lo, hi = oracle.bisect_T(d, e, int(j))
-        assert lo - tol <= wn[j - 1] <= hi + tol
+    wo = golden(GOLDEN_OF[kind])
+    assert np.abs(wn - wo).max() <= tol
+    # the largest entry of every column is positive (sign rule; near-ties as in sign_rule_holds)
+    A = Z.abs()
+    top = A >= A.max(dim=0, keepdim=True).values * (1.0 - 8.0 * EPS)
+    assert bool((top & (Z > 0)).any(dim=0).all())
     if kind == "toeplitz":
         k = np.arange(1, n + 1)
         lam = 4.0 * np.sin(k * np.pi / (2 * (n + 1))) ** 2
@@ -370,10 +408,7 @@ def test_full_size_c3_glued_subset(M):
     r, o = gpu_metrics(d, e, w, Z)
     assert r <= 10.0 and o <= 10.0
     wn = w.cpu().numpy()
-    tol = eig_tol(d, e)
-    for j in [il, il + 1, (il + iu) // 2, iu - 1, iu]:
-        lo, hi = oracle.bisect_T(d, e, j)
-        assert lo - tol <= wn[j - il] <= hi + tol
+    assert np.abs(wn - golden("c3_glued_n60000")[il - 1:iu]).max() <= eig_tol(d, e)
 
 
 def test_full_size_c3_glued_full_spectrum(M):
@@ -389,10 +424,7 @@ def test_full_size_c3_glued_full_spectrum(M):
         assert r <= 10.0 and o <= 10.0
         wn = w.cpu().numpy()
         assert np.all(np.diff(wn) >= 0)
-        tol = eig_tol(d, e)
-        for j in [1, 2, n // 3, n // 2, 2 * n // 3, n - 1, n]:
-            lo, hi = oracle.bisect_T(d, e, j)
-            assert lo - tol <= wn[j - 1] <= hi + tol
+        assert np.abs(wn - golden("c3_glued_n60000")).max() <= eig_tol(d, e)
     finally:
         del dt, et
         torch.cuda.empty_cache()
@@ -673,3 +705,68 @@ def test_backward_full_size_c5(M):
     sc = float(rd.abs().max())
     assert float((gd - rd).abs().max()) <= 1e-10 * sc
     assert float((ge - re).abs().max()) <= 1e-10 * sc
+    # against the oracle's dense adjoint on the oracle's own decomposition
+    wo, Vo, st = oracle.mrrr(d, e)
+    Zh = Z.cpu().numpy()
+    sg = np.sign((Vo * Zh).sum(0))
+    od, oe = oracle.dense_adjoint(wo, Vo, gw.cpu().numpy(), gV.cpu().numpy() * sg[None, :])
+    ref = np.concatenate([od, oe])
+    got = np.concatenate([gd.cpu().numpy(), ge.cpu().numpy()])
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_backward_recompute_equals_saved(M):
+    # the recomputing backward (d, e and w kept, Z solved again) gives the
+    # saved-Z gradients bit for bit, and both match the oracle's adjoint
+    n = 96
+    d, e = W.separated(n, 777)
+    rng = np.random.default_rng(3)
+    c = torch.tensor(rng.standard_normal(n), device="cuda")
+    G = torch.tensor(rng.standard_normal((n, n)), device="cuda")
+    grads = []
+    for rec in (False, True):
+        dt = torch.tensor(d, device="cuda", requires_grad=True)
+        et = torch.tensor(e, device="cuda", requires_grad=True)
+        w, Z = M.MRRRFunction.apply(dt, et, rec)
+        ((c * w).sum() + (G * Z).sum()).backward()
+        grads.append((dt.grad.cpu().numpy(), et.grad.cpu().numpy(), Z.detach().cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    wo, Vo, st = oracle.mrrr(d, e)
+    sg = np.sign((Vo * grads[0][2]).sum(0))
+    od, oe = oracle.dense_adjoint(wo, Vo, c.cpu().numpy(), G.cpu().numpy() * sg[None, :])
+    ref = np.concatenate([od, oe])
+    got = np.concatenate([grads[1][0], grads[1][1]])
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_backward_batched_c5_shape_vs_oracle(M):
+    # the differentiation workload's batch: 256 problems of order 512
+    # (separated spectra), batched forward and batched FP64-MFMA backward,
+    # every problem against the oracle's dense adjoint on the oracle's own
+    # decomposition (normwise 1e-6, the spec bar)
+    from concurrent.futures import ThreadPoolExecutor
+    nb, count = 512, 256
+    probs = [W.separated(nb, W.SEEDS["c5"] + k) for k in range(count)]
+    d, e, ns, off = W.pack(probs)
+    wb, Zb, zoff = M.eigh_tridiagonal_batched(torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda"), ns)
+    g = torch.Generator(device="cpu").manual_seed(W.SEEDS["c5"])
+    gw = torch.randn(count * nb, generator=g, dtype=torch.float64)
+    gZ = torch.randn(count * nb * nb, generator=g, dtype=torch.float64)
+    gd, ge = M.eigh_tridiagonal_backward_batched(wb, Zb, ns, gw.cuda(), gZ.cuda())
+    gd, ge, Zh = gd.cpu().numpy(), ge.cpu().numpy(), Zb.cpu().numpy()
+    gwn, gZn = gw.numpy(), gZ.numpy()
+
+    def check(b):
+        p = probs[b]
+        wo, Vo, st = oracle.mrrr(p[0], p[1])  # releases the GIL: threads run in parallel
+        Z = Zh[zoff[b]:zoff[b] + nb * nb].reshape(nb, nb).T
+        G = gZn[zoff[b]:zoff[b] + nb * nb].reshape(nb, nb).T
+        sg = np.sign((Vo * Z).sum(0))
+        od, oe = oracle.dense_adjoint(wo, Vo, gwn[off[b]:off[b] + nb], G * sg[None, :])
+        ref = np.concatenate([od, oe])
+        got = np.concatenate([gd[off[b]:off[b] + nb], ge[off[b]:off[b] + nb - 1]])
+        return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        errs = list(ex.map(check, range(count)))
+    assert max(errs) <= 1e-6, max(errs)
