@@ -1264,12 +1264,14 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   // resid / gap bounds the sine of the angle between z and the eigenvector
   // (gap theorem); otherwise stop once the correction is within 2 eps |lambda|
   // (two to four ulps: a further solve would only move lambda by rounding;
-  // LAPACK's dlarrv uses the same tolerance).  At the rounding floor (a solve that does not halve the
-  // smallest residual so far: away from the floor the iteration converges
-  // much faster than that; or the iteration cap) the solve with the smallest
-  // residual is kept: the current one if it is that, else it is repeated.
+  // LAPACK's dlarrv uses the same tolerance).  The floor test: the first
+  // correction must halve the residual and every later one cut the smallest
+  // residual so far by 32 (Rayleigh quotient iteration converges cubically
+  // above the rounding floor, so a smaller cut means the floor is reached).
+  // There, or at the iteration cap, the solve with the smallest residual is
+  // kept: the current one if it is that, else it is repeated.
   const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 2.0 * kEps * fabs(lam);
-  const bool progress = resid < 0.5 * V.resid;
+  const bool progress = resid < (it >= 1 ? 0.03125 : 0.5) * V.resid;
   const bool improved = resid < V.resid;
   if (improved) {
     V.resid = resid;
@@ -1340,6 +1342,21 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
 // below the twist, in Horner form, so ||z||^2 = -(d s_r + d p_r + 1) =
 // -d gamma_r / d lam comes with the transforms and no solve is needed.
 __device__ __forceinline__ double dstep(double w, double dx) { return fma(w * w, dx, -1.0); }
+
+// LDS hand-off between the lanes of a workgroup of one wavefront: its LDS
+// operations complete in order, so waiting for them and keeping the compiler
+// from moving memory operations across is enough; unlike __syncthreads this
+// does not wait for the wavefront's outstanding global stores
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// staged eigenvector entries: entry o of lane l at zt[o * kZtStride + l]; the
+// stride keeps both the lane-wise writes and the segment-wise reads free of
+// bank conflicts
+constexpr int kZtStride = 68;
 
 // the write-back address and entry mask of a lane's segment, parked in LDS
 __device__ __forceinline__ void zp_lds_store(double** zp, uint32_t* zm, int lane, double* p, uint32_t m) {
@@ -1752,16 +1769,15 @@ __device__ inline void solve_pass(bool go, int role, const Rep* __restrict__ R, 
           // k kSeg + o + 1 (role 1) of its column
           const int lane = threadIdx.x & 63;
 #pragma unroll
-          for (int o = 0; o < kSeg; o += 2)
-            *reinterpret_cast<double2*>(zt + lane * kSeg + o) = make_double2(zv[o], zv[o + 1]);
+          for (int o = 0; o < kSeg; ++o) zt[o * kZtStride + lane] = zv[o];
           zp_lds_store(zaddr, zm, lane, Zc + k * kSeg + role, msk);
-          __syncthreads();
+          wave_lds_sync();
 #pragma unroll
           for (int i = 0; i < 64 / kSeg; ++i) {
             const int q = i * kSeg + (lane >> 3), u = lane & (kSeg - 1);
-            if ((zm[q] >> u) & 1u) zaddr[q][u] = zt[q * kSeg + u];
+            if ((zm[q] >> u) & 1u) zaddr[q][u] = zt[u * kZtStride + q];
           }
-          __syncthreads();
+          wave_lds_sync();
         }
       });
   nrm_out = nrm;
@@ -1864,7 +1880,7 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
 // singletons per slot, -1 elsewhere), so every lane works on the same
 // representation.  Checkpoints of chunk ci at scratch + ci * stride.
 template <int kPairSlots>
-__global__ void __launch_bounds__(64, 2) k_vectors(
+__global__ void __launch_bounds__(64, 1) k_vectors(
     const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
     const int64_t* __restrict__ cstart, int nchunks, int64_t ntot, const int32_t* __restrict__ rid,
     const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const int64_t* __restrict__ scol,
@@ -1877,7 +1893,7 @@ __global__ void __launch_bounds__(64, 2) k_vectors(
   __shared__ int s_n[kPairSlots];
   __shared__ int64_t s_lrow0[kPairSlots];
   __shared__ int64_t s_pn[kPairSlots];
-  __shared__ double s_zt[64 * kSeg];  // staged eigenvector entries of the write pass
+  __shared__ double s_zt[kSeg * kZtStride];  // staged eigenvector entries of the write pass
   __shared__ double* s_zp[64];
   __shared__ uint32_t s_zm[64];
   const int lane = threadIdx.x;
