@@ -302,6 +302,23 @@ int mrrr_profile_enable(int on);
 int mrrr_profile_reset(void);
 int mrrr_profile_read(int kernel, mrrr_kernel_time* out); /* -1 on a bad kernel id */
 
+/* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
+ * caller-given operands (no solve; for tests of their rounding).  a, b: device
+ * arrays of n doubles; out: device array of 4 n doubles, written as
+ *   out[i]         v_rcp_f64(b[i]), the hardware reciprocal approximation;
+ *   out[n + i]     that after one Newton-Raphson step r + r (1 - b r): the
+ *                  reciprocal of the Sturm counts, the twisted transforms and
+ *                  the Rayleigh-quotient correction;
+ *   out[2n + i]    after two steps: the multipliers of child representations
+ *                  (stationary qds, Sec. 3.1.1 child step);
+ *   out[3n + i]    a[i] / b[i] from the two-step reciprocal, the product and
+ *                  one residual correction: the eigenvector recurrence across
+ *                  a zero pivot.
+ * Enqueued on stream (NULL: the default stream) without synchronising.
+ * Returns 0; -1 when n < 0 or n > 2^31; -2 on a null pointer with n > 0;
+ * MRRR_ERR_HIP when the launch fails. */
+int mrrr_probe_division(int64_t n, const double* a, const double* b, double* out, void* stream);
+
 /* Free the calling device's workspace (the next call allocates again). */
 int mrrr_release(void);
 

@@ -17,7 +17,7 @@ from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
-           "profile_read", "release", "workspace_size", "get_limits", "set_limits"]
+           "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division"]
 
 
 def _torch():
@@ -336,3 +336,19 @@ def profile_read():
 
 def release():
     _lib.check(_lib.load().mrrr_release())
+
+
+def probe_division(a, b, stream=None):
+    """The kernels' reciprocal and quotient forms on device operands a, b (same
+    length): returns (v_rcp_f64(b), one Newton step, two steps, a / b) as
+    device tensors, computed by the library's probe kernel."""
+    torch = _torch()
+    a = _as_dev(a)
+    b = _as_dev(b, a.device)
+    if a.shape != b.shape or a.dim() != 1:
+        raise ValueError("a and b must be 1-D of one length")
+    n = a.numel()
+    out = torch.empty(4 * n, dtype=torch.float64, device=a.device)
+    with torch.cuda.device(a.device):
+        _lib.check(_lib.load().mrrr_probe_division(n, _ptr(a), _ptr(b), _ptr(out), _stream_ptr(stream)))
+    return out[:n], out[n:2 * n], out[2 * n:3 * n], out[3 * n:]

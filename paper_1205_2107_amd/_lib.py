@@ -15,7 +15,8 @@ COUNTER_NAMES = ("blocks", "nodes", "levels", "sturm_steps", "qds_steps", "singl
 EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_backward_batched",
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
-           "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc")
+           "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc",
+           "mrrr_probe_division")
 KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt")
 
 
@@ -79,6 +80,8 @@ def load():
     lib.mrrr_step_ws.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, ctypes.c_size_t, P, P]
     lib.mrrr_step_noalloc.restype = ctypes.c_int
     lib.mrrr_step_noalloc.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, P]
+    lib.mrrr_probe_division.restype = ctypes.c_int
+    lib.mrrr_probe_division.argtypes = [I64, P, P, P, P]
     lib.mrrr_get_limits.restype = ctypes.c_int
     lib.mrrr_get_limits.argtypes = [ctypes.POINTER(MrrrLimits)]
     lib.mrrr_set_limits.restype = ctypes.c_int

@@ -187,6 +187,7 @@ static T* P_(DevBuf& b) {
 
 // scratch budget for the eigenvector kernel (bytes): a quarter of the device
 constexpr bool kShareLevels = true, kShareLeaf = true;
+constexpr int64_t kFillMinBlock = 4096;  // mean block size from which the root refinement is persistent
 
 static size_t scratch_budget() {
   size_t fr = 0, tot = 0;
@@ -383,10 +384,35 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     prof.end();
     return 0;
   };
-  prof.begin(MRRR_K_REFINE);
-  launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool, P_<double>(W.lo),
-                P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi), P_<uint32_t>(W.sflag), dC, lanes);
-  prof.end();
+  // root level: every slot is flagged, so the node runs are the blocks.  With
+  // large blocks and more chunks than SIMDs the refinement runs as persistent
+  // wavefronts (one per SIMD) whose lane groups claim the eigenvalues of their
+  // block one at a time (the split buffers, free since the blocks were formed,
+  // hold the claim counters and cursor); small blocks (a batch of small
+  // problems) keep one wavefront per chunk, which hides latency better there.
+  // Both give the same values.
+  const int simds = device_simds();
+  if (ntot < (int64_t)kFillMinBlock * nblk || ntot / (64 / lanes) <= simds) {
+    prof.begin(MRRR_K_REFINE);
+    launch_refine(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                  P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                  P_<uint32_t>(W.sflag), dC, lanes);
+    prof.end();
+  } else {
+    launch_node_chunks(st, ntot, P_<uint32_t>(W.sflag), P_<int64_t>(W.scol), F_NEEDS_REFINE, false,
+                       P_<int32_t>(W.snode), 64 / lanes, P_<int32_t>(W.runflag), P_<int32_t>(W.runid),
+                       P_<int32_t>(W.tiles), P_<int32_t>(W.total), P_<int32_t>(W.vrid), P_<int64_t>(W.runs),
+                       P_<int32_t>(W.cflag), P_<int32_t>(W.cid), P_<int64_t>(W.cstart));
+    int32_t nrc = 0;
+    HIP_TRY(hipMemcpyAsync(&nrc, W.total.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    prof.begin(MRRR_K_REFINE);
+    launch_refine_fill(st, dB, P_<Node>(W.nodes), ntot, P_<int32_t>(W.sblk), P_<int32_t>(W.snode), dpool,
+                       P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
+                       P_<uint32_t>(W.sflag), dC, lanes, P_<int64_t>(W.cstart), P_<int32_t>(W.vrid),
+                       P_<int64_t>(W.runs), nrc, P_<int32_t>(W.flag), P_<int32_t>(W.excl), simds);
+    prof.end();
+  }
   // problem table after the root pass: VALUE counts, block counts
   HIP_TRY(hipMemcpyAsync(probs.data(), W.problems.p, sizeof(Problem) * nprob, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -862,6 +888,16 @@ int mrrr_step_ws(int64_t n, const double* d, const double* e, mrrr_range range, 
     if (e2 != hipSuccess) return fail(MRRR_ERR_HIP, "info store failed: %s", hipGetErrorString(e2));
   }
   return rc;
+}
+
+int mrrr_probe_division(int64_t n, const double* a, const double* b, double* out, void* stream) {
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(-1, "n out of range");
+  if (n == 0) return 0;
+  if (!a || !b || !out) return fail(-2, "null pointer");
+  launch_probe_division((hipStream_t)stream, n, a, b, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MRRR_ERR_HIP, "probe launch failed: %s", hipGetErrorString(e));
+  return 0;
 }
 
 int mrrr_get_limits(mrrr_limits* l) {

@@ -9,6 +9,8 @@
 //   clusters         k_child, k_shift L_c D_c L_c^T = L D L^T - sigma_c I (stationary qds)
 //   singletons       k_vectors        twisted factorization + Rayleigh correction,
 //                    z written to column-major Z through an LDS transpose
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "mrrr_dev.h"
@@ -226,11 +228,13 @@ __device__ inline double wg_reduce(double v, double* sh, int op) {  // op 0 min,
   return r;
 }
 
+constexpr int kRootChunk = 1024;  // rows of the root factorization staged at a time
+
 __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __restrict__ B, Node* __restrict__ N,
                                               const double* __restrict__ ds, const double* __restrict__ es,
                                               Rep* __restrict__ pool, Counters* __restrict__ C, int grid_density) {
   __shared__ double sh[256];
-  __shared__ double s_sigma;
+  __shared__ double s_d[kRootChunk + 1], s_e[kRootChunk + 1], s_D[kRootChunk], s_L[kRootChunk];
   __shared__ int s_ok;
   __shared__ int s_cnt[2];
   const int b = blockIdx.x;
@@ -272,32 +276,56 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
   }
   const int left = (pr.kind == 0) || (pr.kind == 1 && pr.nblk > 1) || (wl + wu <= n + 1);
   Rep* R = pool + blk.row0;
-  if (threadIdx.x == 0) {
-    double delta = 4.0 * (double)n * kEps * fmax(fabs(gl), fabs(gu));
-    if (!(delta > 0.0)) delta = pivmin;
-    int ok = 0;
-    double sigma = 0.0;
-    for (int tries = 0; tries < 64 && !ok; ++tries) {
-      sigma = left ? gl - delta : gu + delta;
-      ok = 1;
-      double Dp = d[0] - sigma;
-      for (int i = 0; i + 1 < n; ++i) {
-        const double L = e[i] / Dp;
-        R[i].D = Dp;
-        R[i].L = L;
-        if (!isfinite(Dp) || !isfinite(L) || (left ? !(Dp > 0.0) : !(Dp < 0.0))) ok = 0;
-        Dp = (d[i + 1] - sigma) - L * e[i];
+  // L0 D0 L0^T = T - sigma I, one row after the other (thread 0), on chunks
+  // of kRootChunk rows that the whole workgroup stages through LDS: the
+  // serial chain then waits on LDS, not on a memory round trip per row
+  double delta = 4.0 * (double)n * kEps * fmax(fabs(gl), fabs(gu));
+  if (!(delta > 0.0)) delta = pivmin;
+  double sigma = 0.0;
+  for (int tries = 0; tries < 64; ++tries) {
+    sigma = left ? gl - delta : gu + delta;
+    // the pivots must keep the sign of the definite side and stay finite;
+    // sgn * Dp is exact, and a NaN fails the comparison
+    const double sgn = left ? 1.0 : -1.0;
+    bool ok = true;
+    double Dp = 0.0;
+    for (int c0 = 0; c0 < n; c0 += kRootChunk) {
+      // rows c0 .. c0 + m - 1, plus the next chunk's first diagonal entry
+      const int m = min(kRootChunk, n - c0);
+      for (int i = threadIdx.x; i <= m; i += blockDim.x) {
+        s_d[i] = (c0 + i < n) ? d[c0 + i] : 0.0;
+        s_e[i] = (c0 + i + 1 < n) ? e[c0 + i] : 0.0;
       }
-      R[n - 1].D = Dp;
-      R[n - 1].L = 0.0;
-      if (!isfinite(Dp) || (left ? !(Dp > 0.0) : !(Dp < 0.0))) ok = 0;
-      delta *= 2.0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        if (c0 == 0) Dp = s_d[0] - sigma;
+        const int mi = (c0 + m < n) ? m : m - 1;  // rows with an off-diagonal entry
+#pragma unroll 4
+        for (int i = 0; i < mi; ++i) {
+          const double L = s_e[i] / Dp;
+          s_D[i] = Dp;
+          s_L[i] = L;
+          ok = ok & isfinite(Dp) & isfinite(L) & (sgn * Dp > 0.0);
+          Dp = (s_d[i + 1] - sigma) - L * s_e[i];
+        }
+        if (mi < m) {  // the last row of the block
+          s_D[mi] = Dp;
+          s_L[mi] = 0.0;
+          ok = ok & isfinite(Dp) & (sgn * Dp > 0.0);
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        R[c0 + i].D = s_D[i];
+        R[c0 + i].L = s_L[i];
+      }
+      __syncthreads();
     }
-    s_sigma = sigma;
-    s_ok = ok;
+    if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
+    __syncthreads();
+    delta *= 2.0;
+    if (s_ok) break;
   }
-  __syncthreads();
-  const double sigma = s_sigma;
   if (!s_ok) set_status(C, 1);
   // deterministic relative perturbation of the root, then the products
   const uint64_t seed = (uint64_t)blk.lrow0;
@@ -348,25 +376,6 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
 // ---------------------------------------------------------------------------
 // 3. eigenvalue brackets: a grid of Sturm counts per block, then one lane per
 //    eigenvalue picks its grid cell
-
-__global__ void __launch_bounds__(64) k_grid(const Block* __restrict__ B, int nblk, const int64_t* __restrict__ goff,
-                                             int64_t gtot, const Rep* __restrict__ pool, int32_t* __restrict__ gcnt) {
-  const int64_t t0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int64_t t = t0 < gtot ? t0 : gtot - 1;  // tail lanes repeat the last point
-  const int b = find_segment(goff, nblk, t);
-  const Block blk = B[b];
-  const int k = (int)(t - goff[b]);
-  const double x = grid_point(blk.glo, blk.ghi, k, blk.gP);
-  const int b0 = __shfl(b, 0, 64);
-  int c;
-  if (__ballot(b != b0) == 0) {
-    const Rep* R = wave_uniform(pool + blk.row0);
-    c = sturm_count(R, __builtin_amdgcn_readfirstlane(blk.n), x, blk.pivmin);
-  } else {
-    c = sturm_count(pool + blk.row0, blk.n, x, blk.pivmin);
-  }
-  if (t0 < gtot) gcnt[t0] = c;
-}
 
 __global__ void k_assign(const Block* __restrict__ B, const int64_t* __restrict__ goff, int64_t ntot,
                          const int32_t* __restrict__ sblk, const int32_t* __restrict__ gcnt, double* __restrict__ lo,
@@ -600,6 +609,47 @@ __device__ inline int staged_count_deriv(const double* __restrict__ Rd, int n, d
   return c;
 }
 
+// Sturm count as sturm_count (same arithmetic, bit for bit) for a wavefront
+// whose lanes share the representation; the last row's LLD is 0, so its
+// update of s is harmless
+__device__ inline int staged_count(const double* __restrict__ Rd, int n, double tau, double pivmin,
+                                   double* __restrict__ st) {
+  double s = -tau;
+  int c = 0;
+  staged_rows(Rd, n, st, [&](int, double D, double, double, double LLD) {
+    double dp = D + s;
+    dp = (fabs(dp) < pivmin) ? -pivmin : dp;
+    c += (dp < 0.0) ? 1 : 0;
+    double t = s * rcp_nr1(dp);
+    t = (t != t) ? 1.0 : t;
+    s = fma(t, LLD, -tau);
+  });
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// 3. eigenvalue brackets (continued): the grid of Sturm counts per block
+
+__global__ void __launch_bounds__(64) k_grid(const Block* __restrict__ B, int nblk, const int64_t* __restrict__ goff,
+                                             int64_t gtot, const Rep* __restrict__ pool, int32_t* __restrict__ gcnt) {
+  const int64_t t0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t t = t0 < gtot ? t0 : gtot - 1;  // tail lanes repeat the last point
+  const int b = find_segment(goff, nblk, t);
+  const Block blk = B[b];
+  const int k = (int)(t - goff[b]);
+  const double x = grid_point(blk.glo, blk.ghi, k, blk.gP);
+  const int b0 = __shfl(b, 0, 64);
+  int c;
+  if (__ballot(b != b0) == 0) {
+    __shared__ double st[2 * 4 * kSG];
+    c = staged_count(reinterpret_cast<const double*>(pool + blk.row0), __builtin_amdgcn_readfirstlane(blk.n), x,
+                     blk.pivmin, st);
+  } else {
+    c = sturm_count(pool + blk.row0, blk.n, x, blk.pivmin);
+  }
+  if (t0 < gtot) gcnt[t0] = c;
+}
+
 template <int L>
 __device__ inline long long refine_sweeps(EigState& S, bool act, const Rep* __restrict__ R, int n, double pivmin,
                                           int k, int gbase, double* __restrict__ st, bool vonly, bool share_ok) {
@@ -742,6 +792,119 @@ __global__ void __launch_bounds__(64) k_refine(const Block* __restrict__ B, cons
   }
   // each lane evaluated its own points: count all of them
   if (act) atomicAdd(&C->sturm_steps, (unsigned long long)steps);
+}
+
+// Refinement by persistent wavefronts over node runs (maximal runs of
+// flagged slots of one node; at the root level, whole blocks).  A wavefront
+// starts on the run of its chunk; its lane groups claim that run's eigenvalues
+// one at a time from the run's counter, and a group whose eigenvalue has
+// converged writes it back and claims the next.  Once the run has nothing
+// left to claim and every group is idle, the wavefront takes the next chunk
+// from a global cursor and moves to its run.  Every eigenvalue is refined on
+// its own L points exactly as in k_refine without shared points (the same
+// points, counts and updates in the same order), so its result does not
+// depend on which wavefront or group took it; only the load balance differs.
+// claim: one counter per run, zero on entry; cursor: gridDim.x on entry.
+template <int L>
+__global__ void __launch_bounds__(64) k_refine_fill(const Block* __restrict__ B, const Node* __restrict__ N,
+                                                    int64_t ntot, const int32_t* __restrict__ sblk,
+                                                    const int32_t* __restrict__ snode, const Rep* __restrict__ pool,
+                                                    double* __restrict__ lo_a, double* __restrict__ hi_a,
+                                                    int32_t* __restrict__ clo_a, int32_t* __restrict__ chi_a,
+                                                    uint32_t* __restrict__ sflag, Counters* __restrict__ C,
+                                                    const int64_t* __restrict__ cstart, const int32_t* __restrict__ rid,
+                                                    const int64_t* __restrict__ rstart, int nchunks,
+                                                    int32_t* __restrict__ claim, int32_t* __restrict__ cursor) {
+  __shared__ double st[2 * 4 * kSG];
+  const int lane = threadIdx.x;
+  const int k = lane % L, gbase = lane - k;
+  long long steps = 0;
+  int c = blockIdx.x;
+  while (c < nchunks) {
+    const int q = __builtin_amdgcn_readfirstlane(rid[cstart[c]]);
+    const int64_t r0 = rstart[q];
+    const Block blk = B[sblk[r0]];
+    const Node nd = N[snode[r0]];
+    const Rep* R = pool + nd.rep;
+    const int n = __builtin_amdgcn_readfirstlane(blk.n);
+    EigState S;
+    int64_t s = -1;        // this group's slot, -1 when idle
+    bool open = true;      // the run may still hold unclaimed eigenvalues
+    int sweeps = 0;
+    for (;;) {
+      // settle (every lane runs this loop; the groups diverge only inside):
+      // write back converged eigenvalues (or those at the sweep cap) and claim
+      // the run's next ones until every group holds one that needs a sweep or
+      // the run has none left for it
+      for (;;) {
+        if (s >= 0 && (S.done || sweeps >= kMaxSweeps)) {
+          if (k == 0) {
+            lo_a[s] = S.lo;
+            hi_a[s] = S.hi;
+            clo_a[s] = S.clo;
+            chi_a[s] = S.chi;
+            uint32_t fl = sflag[s] & ~F_NEEDS_REFINE;
+            if (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) fl |= F_ACCURATE;
+            sflag[s] = fl;
+          }
+          s = -1;
+        }
+        const bool want = s < 0 && open;
+        if (__ballot(want) == 0) break;
+        if (want) {
+          int idx = 0;
+          if (k == 0) idx = atomicAdd(&claim[q], 1);
+          idx = __shfl(idx, gbase, 64);
+          const int64_t t = r0 + idx;
+          if (t < ntot && rid[t] == q) {
+            s = t;
+            S.lo = lo_a[s];
+            S.hi = hi_a[s];
+            S.clo = clo_a[s];
+            S.chi = chi_a[s];
+            S.glo = NAN;
+            S.ghi = NAN;
+            S.j = (int)(s - blk.row0) + 1;
+            S.pad = fmax(fmax(S.hi - S.lo, 4.0 * kEps * fmax(fabs(S.lo), fabs(S.hi))), blk.pivmin);
+            S.done = (S.clo >= 0 && S.chi >= 0 && bracket_converged(S.lo, S.hi)) ? 1 : 0;
+            sweeps = 0;
+          } else {
+            open = false;
+          }
+        }
+      }
+      if (__ballot(s >= 0) == 0) break;
+      const bool need = s >= 0;
+      const double p = need ? next_point<L>(S, k, 0, 1) : 0.0;
+      double gv;
+      const int cnt = staged_count_deriv(reinterpret_cast<const double*>(R), n, p, blk.pivmin, st, &gv);
+      if (need) steps += n;
+      double pq[L], gq[L];
+      int cq[L];
+#pragma unroll
+      for (int u = 0; u < L; ++u) {
+        pq[u] = __shfl(p, gbase + u, 64);
+        cq[u] = __shfl(cnt, gbase + u, 64);
+        gq[u] = __shfl(gv, gbase + u, 64);
+      }
+      if (need) {
+        update_state<L>(S, pq, cq, gq, false);
+        ++sweeps;
+      }
+    }
+    // the run is exhausted for this wavefront: the next chunk's run
+    int nc = 0;
+    if (lane == 0) nc = atomicAdd(cursor, 1);
+    c = __shfl(nc, 0, 64);
+  }
+  if (steps) atomicAdd(&C->sturm_steps, (unsigned long long)steps);
+}
+
+// claim counters of k_refine_fill cleared, its cursor set to the grid size
+__global__ void k_fill_init(int64_t nclaim, int32_t* __restrict__ claim, int32_t* __restrict__ cursor, int grid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nclaim) claim[i] = 0;
+  if (i == 0) *cursor = grid;
 }
 
 // singletons whose bracket is not at full accuracy in their leaf's frame
@@ -1035,8 +1198,10 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   const uint32_t regoff = (uint32_t)(lane < kSpec ? lane : 0) * (uint32_t)n * (uint32_t)sizeof(Rep);
   const int span = (kSpec - 1) * n * (int)sizeof(Rep) + kSG * (int)sizeof(Rep);
   // pass 1: growth of every candidate (rows 0 .. n-2; the last row has no L)
-  double sv = -sigma, gmax = 0.0;
-  bool fin = true;
+  // chk: x * 0 is NaN exactly when x is infinite or NaN, so chk stays 0
+  // while every pivot and multiplier is finite (a check kept off the
+  // recurrence's dependency chain)
+  double sv = -sigma, gmax = 0.0, chk = 0.0;
   __amdgpu_buffer_rsrc_t r0 = raw_rsrc(reg0, 0);
   staged_rows_g(
       Rd, n, n - 1, st,
@@ -1061,8 +1226,10 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
           bstore2(r0, o + 16, ld, lld);
         }
         sv = fma(lp * L, sv, -sigma);
-        fin = fin && isfinite(dp) && isfinite(lp);
+        chk = fma(dp, 0.0, chk);
+        chk = fma(lp, 0.0, chk);
       });
+  bool fin = isfinite(chk);
   {
     const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
     gmax = fmax(gmax, fabs(dp));
@@ -1879,8 +2046,8 @@ __device__ inline int pair_rqi(bool solve, int role, const Rep* __restrict__ R, 
 // node (cstart[ci] is the chunk's first slot; rid: run of equal-node
 // singletons per slot, -1 elsewhere), so every lane works on the same
 // representation.  Checkpoints of chunk ci at scratch + ci * stride.
-template <int kPairSlots>
-__global__ void __launch_bounds__(64, 1) k_vectors(
+template <int kPairSlots, int kWavesPerSimd>
+__global__ void __launch_bounds__(64, kWavesPerSimd) k_vectors(
     const Problem* __restrict__ P, const Block* __restrict__ B, const Node* __restrict__ N,
     const int64_t* __restrict__ cstart, int nchunks, int64_t ntot, const int32_t* __restrict__ rid,
     const int32_t* __restrict__ sblk, const int32_t* __restrict__ snode, const int64_t* __restrict__ scol,
@@ -2631,6 +2798,22 @@ __global__ void k_values_only(const Problem* __restrict__ P, const Block* __rest
 
 #define GRID1(n, t) dim3((unsigned)(((n) + (t)-1) / (t))), dim3(t)
 
+// SIMDs of the current device (four per compute unit on CDNA), cached per device
+static int simd_count() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+  cache[dev] = 4 * cu;
+  return 4 * cu;
+}
+
+
 void launch_prep(hipStream_t st, Problem* P, int nprob, const int64_t* poff, int64_t ntot, const double* d,
                  const double* e, int32_t* sprob, double* ds, double* es, int32_t* flag) {
   if (ntot == 0) return;
@@ -2693,6 +2876,26 @@ void launch_refine(hipStream_t st, const Block* B, const Node* N, int64_t ntot, 
     hipLaunchKernelGGL(k_refine<1>, dim3(ch ? (unsigned)nchunks : g1), dim3(64), 0, st, B, N, ntot, sblk, snode, pool,
                        lo, hi, clo, chi, sflag, C, v, cstart, rid, nchunks, share ? 1 : 0);
 }
+
+void launch_refine_fill(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
+                        const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
+                        uint32_t* sflag, Counters* C, int lanes, const int64_t* cstart, const int32_t* rid,
+                        const int64_t* rstart, int nchunks, int32_t* claim, int32_t* cursor, int max_waves) {
+  if (nchunks <= 0 || ntot <= 0) return;
+  const int grid = std::max(1, std::min(nchunks, max_waves));
+  hipLaunchKernelGGL(k_fill_init, GRID1(ntot, 256), 0, st, ntot, claim, cursor, grid);
+  if (lanes >= 4)
+    hipLaunchKernelGGL(k_refine_fill<4>, dim3(grid), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi,
+                       sflag, C, cstart, rid, rstart, nchunks, claim, cursor);
+  else if (lanes == 2)
+    hipLaunchKernelGGL(k_refine_fill<2>, dim3(grid), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi,
+                       sflag, C, cstart, rid, rstart, nchunks, claim, cursor);
+  else
+    hipLaunchKernelGGL(k_refine_fill<1>, dim3(grid), dim3(64), 0, st, B, N, ntot, sblk, snode, pool, lo, hi, clo, chi,
+                       sflag, C, cstart, rid, rstart, nchunks, claim, cursor);
+}
+
+int device_simds() { return simd_count(); }
 
 void launch_mark_leaf(hipStream_t st, int64_t ntot, const int64_t* scol, uint32_t* sflag) {
   hipLaunchKernelGGL(k_mark_leaf, GRID1(ntot, 256), 0, st, ntot, scol, sflag);
@@ -2767,14 +2970,41 @@ void launch_node_chunks(hipStream_t st, int64_t ntot, const uint32_t* sflag, con
   hipLaunchKernelGGL(k_vec_cstart, GRID1(ntot, 256), 0, st, ntot, cflag, cid, cstart);
 }
 
+// the reciprocal and quotient forms of the kernels on caller-given operands
+__global__ void k_probe_division(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                 double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = b[i];
+  out[i] = __builtin_amdgcn_rcp(x);
+  out[n + i] = rcp_nr1(x);
+  out[2 * n + i] = rcp_nr2(x);
+  out[3 * n + i] = div_nr(a[i], x);
+}
+
+void launch_probe_division(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_probe_division, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, b, out);
+}
+
 void launch_vectors(hipStream_t st, const Problem* P, const Block* B, const Node* N, const int64_t* cstart,
                     int nchunks, int64_t ntot, const int32_t* rid, const int32_t* sblk, const int32_t* snode,
                     const int64_t* scol, const double* lo, const double* hi, const double* sgap, const Rep* pool,
                     const double* ds, double* scratch, int64_t stride, double* w, double* Z, Counters* C, int slots) {
   if (nchunks == 0) return;
-#define MRRR_VEC(SL)                                                                                               \
-  hipLaunchKernelGGL(k_vectors<SL>, dim3(nchunks), dim3(64), 0, st, P, B, N, cstart, nchunks, ntot, rid, sblk, snode, \
-                     scol, lo, hi, sgap, pool, ds, scratch, stride, w, Z, C)
+  // the kernel's full register budget (one wavefront per SIMD) while the
+  // launch has no more wavefronts than the device has SIMDs; half of it (two
+  // per SIMD, some spilling) once wavefronts would otherwise wait for a SIMD
+  const bool wide = nchunks > simd_count();
+#define MRRR_VEC(SL)                                                                                              \
+  do {                                                                                                            \
+    if (wide)                                                                                                     \
+      hipLaunchKernelGGL((k_vectors<SL, 2>), dim3(nchunks), dim3(64), 0, st, P, B, N, cstart, nchunks, ntot, rid,   \
+                         sblk, snode, scol, lo, hi, sgap, pool, ds, scratch, stride, w, Z, C);                        \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_vectors<SL, 1>), dim3(nchunks), dim3(64), 0, st, P, B, N, cstart, nchunks, ntot, rid,   \
+                         sblk, snode, scol, lo, hi, sgap, pool, ds, scratch, stride, w, Z, C);                        \
+  } while (0)
   if (slots == 8)
     MRRR_VEC(8);
   else if (slots == 16)

@@ -68,6 +68,12 @@ void launch_values_only(hipStream_t st, const Problem* P, const Block* B, const 
 struct InfoWords {
   int64_t w[18];
 };
+void launch_refine_fill(hipStream_t st, const Block* B, const Node* N, int64_t ntot, const int32_t* sblk,
+                        const int32_t* snode, const Rep* pool, double* lo, double* hi, int32_t* clo, int32_t* chi,
+                        uint32_t* sflag, Counters* C, int lanes, const int64_t* cstart, const int32_t* rid,
+                        const int64_t* rstart, int nchunks, int32_t* claim, int32_t* cursor, int max_waves);
+int device_simds();
+void launch_probe_division(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_store_info(InfoWords* dst, InfoWords v, hipStream_t st);
 
 }  // namespace mrrr

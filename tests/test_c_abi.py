@@ -154,3 +154,13 @@ def test_limits_round_trip_and_validation():
         assert got.max_depth == 3 and got.child_growth_limit == 1.5
     finally:
         lib.mrrr_set_limits(ctypes.byref(old))
+
+
+def test_division_probe_argument_checks():
+    """the arithmetic probe rejects bad sizes and null operands on the host"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    assert lib.mrrr_probe_division(-1, None, None, None, None) == -1
+    assert lib.mrrr_probe_division((1 << 31) + 1, None, None, None, None) == -1
+    assert lib.mrrr_probe_division(4, None, None, None, None) == -2
+    assert lib.mrrr_probe_division(0, None, None, None, None) == 0

@@ -451,6 +451,26 @@ def test_batched_vs_oracle_and_looped(M):
         assert np.array_equal(Z, Zl)
 
 
+@pytest.mark.parametrize("kind", ["toeplitz", "geometric"])
+def test_persistent_root_refinement_equals_chunked(M, kind):
+    # an order-20000 problem alone takes the persistent root-level refinement
+    # (one large block, more chunks than SIMDs); next to forty problems of
+    # order 64 in one batch (mean block size below the threshold) it takes one
+    # wavefront per chunk.  Each eigenvalue gets the same points either way,
+    # so both calls give the same eigenpairs bit for bit
+    n = 20000
+    big = W.toeplitz(n) if kind == "toeplitz" else W.geometric(n, W.SEEDS["c2_geometric"])
+    small = [W.random_uniform(64, 7000 + k) for k in range(40)]
+    w1, Z1 = M.eigh_tridiagonal(torch.tensor(big[0], device="cuda"), torch.tensor(big[1], device="cuda"))
+    d, e, ns, off = W.pack([big] + small)
+    wb, Zb, zoff = M.eigh_tridiagonal_batched(torch.tensor(d, device="cuda"), torch.tensor(e, device="cuda"), ns)
+    z0 = int(zoff[0])
+    assert torch.equal(wb[:n], w1)
+    assert torch.equal(Zb[z0:z0 + n * n].view(n, n).t(), Z1)
+    del Z1, Zb
+    torch.cuda.empty_cache()
+
+
 def test_batched_degenerate_members(M):
     # orders 1 and 2, a diagonal member (all off-diagonals zero), a member
     # that splits into several blocks and ordinary ones in one batched call:
