@@ -11,6 +11,8 @@ never touches it, and it shares no code with the GPU library.
 * ``count_T``        -- Sturm count on T.
 * ``dense_adjoint``  -- (grad_w, grad_Z) -> (grad_d, grad_e) by the dense formula
                         (see ``adjoint.py``).
+* ``apply_q``        -- Stage 5 back-transformation Y = Q Z, one Householder
+                        reflector at a time (see ``backtransform.py``).
 """
 import ctypes
 import os
@@ -19,6 +21,7 @@ import subprocess
 import numpy as np
 
 from .adjoint import dense_adjoint  # noqa: F401
+from .backtransform import apply_q  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrrr_oracle.c")

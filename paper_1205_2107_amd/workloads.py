@@ -17,6 +17,10 @@ the "1-2-1" and "Wilkinson" matrices) plus random and prescribed-spectrum types.
 * ``separated``        spectrum sort(U(-1,1)) + 1e-3 * i (gaps >= 1e-3)
 * ``batched_mix``      sizes log-uniform in [32, 2048]; 60% random, 20% 1-2-1,
                        20% glued Wilkinson
+* ``reflectors``       n - 1 Householder reflectors in the storage of a lower
+                       tridiagonal reduction (input of the back-transformation):
+                       v_i has a unit entry at row i + 1, zeros above, entries
+                       U(-1, 1) / sqrt(n - i - 1) below; tau_i = 2 / (v_i^T v_i)
 """
 import ctypes
 import os
@@ -158,3 +162,22 @@ def pack(problems):
         d[o:o + nb] = p[0]
         e[o:o + nb - 1] = p[1][: nb - 1]
     return d, e, ns, off
+
+
+def reflectors(n, seed, fill=0.0):
+    """(V, tau) for n - 1 Householder reflectors H_i = I - tau_i v_i v_i^T,
+    i = 0 .. n - 2, stored as a lower tridiagonal reduction stores them: V is
+    n x n with v_i[i + 2:] in V[i + 2:, i]; v_i[i + 1] = 1 and v_i[:i + 1] = 0
+    are implicit.  Every other entry of V (on and above the first
+    subdiagonal, and the last column) is set to ``fill`` (NaN in tests that
+    check it is never read).  tau_i = 2 / (v_i^T v_i), so each H_i is an exact
+    reflection up to the rounding of tau_i."""
+    rng = np.random.default_rng(seed)
+    V = np.full((n, n), fill, dtype=np.float64)
+    tau = np.zeros(max(n - 1, 0))
+    for i in range(n - 1):
+        k = n - i - 2
+        below = rng.uniform(-1.0, 1.0, k) / np.sqrt(max(k + 1, 1))
+        V[i + 2:, i] = below
+        tau[i] = 2.0 / (1.0 + float(below @ below))
+    return V, tau
