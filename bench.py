@@ -24,6 +24,9 @@ Also reported on the same JSON line:
   backward      the differentiation workload: 256 problems of order 512
                 (batched) and one of order 8192, forward and hand-written FP64
                 MFMA backward, against a loop of single-problem calls
+  backtransform the Stage 5 back-transformation Y = Q Z (FP64 MFMA, compact-WY
+                blocks of 64 reflectors) at n = m = 20000, against the FP64
+                matrix peak
 """
 import argparse
 import json
@@ -297,6 +300,31 @@ def backward_leg(torch, M, reps=5, loop_count=64):
     return out
 
 
+def backtransform_leg(torch, M, n, reps=3):
+    """Stage 5 back-transformation Y = Q Z at n = m (the eigenvectors of one
+    order-n problem): synthetic reflectors of a lower tridiagonal reduction
+    (seeded; the reduction itself is not built), Z normal random, resident on
+    the device.  Algorithmic work 2 n^2 m flops (reflector application)."""
+    from paper_1205_2107_amd import workloads as W
+    V, tau = W.reflectors(n, W.SEEDS["c2_random"])
+    Vd = torch.tensor(V.T, device="cuda").t()  # column-major on the device
+    del V
+    g = torch.Generator(device="cpu").manual_seed(W.SEEDS["c2_random"])
+    Z = torch.randn((n, n), generator=g, dtype=torch.float64).cuda().t()
+    M.backtransform(Vd, tau, Z)  # warm-up (in place; the values stay finite and orthogonally transformed)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        M.backtransform(Vd, tau, Z)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = median(ts)
+    flops = 2.0 * n * n * n
+    return {"n": n, "m": n, "seconds": t, "tflops": flops / t / 1e12,
+            "frac_of_fp64_mfma_peak": flops / t / 1e12 / PEAK_FP64_MATRIX_TFLOPS, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +334,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-backtransform", action="store_true")
+    ap.add_argument("--only-backtransform", action="store_true",
+                    help="only the back-transformation leg (for a profiler run); prints its JSON")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--looped-count", type=int, default=512)
     ap.add_argument("--profile-once", action="store_true",
@@ -323,6 +354,10 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.n
+    if args.only_backtransform:
+        log("[bench] back-transformation leg only")
+        print(json.dumps({"backtransform": backtransform_leg(torch, M, n)}), flush=True)
+        return
     if args.copy_calib:
         src = torch.ones(args.copy_calib // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -425,6 +460,10 @@ def main():
     if not args.no_backward:
         log("[bench] backward leg")
         out["backward"] = backward_leg(torch, M)
+        torch.cuda.empty_cache()
+    if not args.no_backtransform:
+        log("[bench] back-transformation leg")
+        out["backtransform"] = backtransform_leg(torch, M, n)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -282,6 +282,9 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
  *   MRRR_K_VECTORS_CKPT  twisted factorizations, checkpointing kernel (long
  *                   runs of one node's singletons in large blocks); work and
  *                   bytes counted as for MRRR_K_VECTORS
+ *   MRRR_K_BACKTRANSFORM  mrrr_backtransform (all its launches as one):
+ *                   work = 4 K nb m flops per block of nb reflectors over
+ *                   its K rows (about 2 n^2 m in all)
  * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
 #define MRRR_K_GRID 0
 #define MRRR_K_REFINE 1
@@ -289,7 +292,8 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
 #define MRRR_K_VECTORS 3
 #define MRRR_K_BACKWARD 4
 #define MRRR_K_VECTORS_CKPT 5
-#define MRRR_K_COUNT 6
+#define MRRR_K_BACKTRANSFORM 6
+#define MRRR_K_COUNT 7
 
 typedef struct {
   int64_t launches;
@@ -301,6 +305,28 @@ typedef struct {
 int mrrr_profile_enable(int on);
 int mrrr_profile_reset(void);
 int mrrr_profile_read(int kernel, mrrr_kernel_time* out); /* -1 on a bad kernel id */
+
+/* Stage 5 back-transformation (Sec. 1.2, stage 5: the eigenvectors of the
+ * dense symmetric M are Y = Q Z after a lower tridiagonal reduction
+ * T = Q^T M Q), on FP64 matrix cores.  Q = H_0 H_1 ... H_{n-2},
+ * H_i = I - tau_i v_i v_i^T, with v_i[0..i] = 0, v_i[i+1] = 1 and
+ * v_i[i+2..n-1] = V[(i+2..n-1) + i ldv]: the storage a lower reduction
+ * (LAPACK's dsytrd with uplo 'L') leaves.  Entries of V on or above the
+ * first subdiagonal are not read.
+ *   V    device, n x (n - 1) used of n x ldv column-major, read-only;
+ *   tau  device, n - 1 doubles, read-only;
+ *   Z    device, n x m column-major (leading dimension ldz), overwritten
+ *        with Q Z.
+ * Applied in blocks of 64 reflectors in compact WY form (I - V_b T_b V_b^T),
+ * last block first.  The library keeps a grow-only workspace per process
+ * (64 x 64 doubles per block plus 64 x m); calls are serialized by a lock and
+ * synchronize the stream before returning.  Returns 0; -1 (n < 0 or
+ * n > 2^31), -2 (m), -3 (V null with n > 2), -4 (ldv < max(1, n)), -5 (tau
+ * null with n > 1), -6 (Z null with n, m > 0), -7 (ldz < max(1, n));
+ * MRRR_ERR_CAPACITY when the workspace cannot be allocated; MRRR_ERR_HIP on a
+ * failed launch.  n <= 1 or m == 0 leaves Z as it is. */
+int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const double* tau, double* Z,
+                       int64_t ldz, void* stream);
 
 /* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
  * caller-given operands (no solve; for tests of their rounding).  a, b: device

@@ -9,15 +9,19 @@ memory and the stream; every step of the solver runs in the HIP kernels of
     w, Z = eigh_tridiagonal(d, e, select="v", vl=-1.0, vu=1.0)
     w, Z, zoff = eigh_tridiagonal_batched(d, e, sizes)  # packed problems
     w, Z = MRRRFunction.apply(d, e)                    # differentiable
+    Y = backtransform(V, tau, Z)                       # Stage 5: Y = Q Z
 """
 import ctypes
+
+import numpy as np
 
 from . import _lib
 from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
-           "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division"]
+           "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division",
+           "backtransform"]
 
 
 def _torch():
@@ -336,6 +340,39 @@ def profile_read():
 
 def release():
     _lib.check(_lib.load().mrrr_release())
+
+
+def backtransform(V, tau, Z, stream=None):
+    """Stage 5 back-transformation: Y = Q Z for the n - 1 Householder
+    reflectors of a lower tridiagonal reduction (V n x n holding v_i[i+2:] in
+    V[i+2:, i], tau of length n - 1), on the GPU.  Z (n x m) is overwritten
+    when it is a column-major float64 device tensor (e.g. the eigenvectors
+    eigh_tridiagonal returns); otherwise a column-major copy is transformed.
+    Returns the transformed tensor."""
+    torch = _torch()
+    Zd = Z if torch.is_tensor(Z) else torch.as_tensor(np.asarray(Z), dtype=torch.float64)
+    if Zd.dim() != 2:
+        raise ValueError("Z must be 2-D")
+    n, m = Zd.shape
+    dev = Zd.device if Zd.is_cuda else torch.device("cuda")
+    if not (Zd.is_cuda and Zd.dtype == torch.float64 and (Zd.numel() == 0 or
+                                                           (Zd.stride(0) == 1 and Zd.stride(1) >= max(1, n)))):
+        Zd = Zd.to(device=dev, dtype=torch.float64).t().contiguous().t()
+    Vt = V if torch.is_tensor(V) else torch.as_tensor(np.asarray(V), dtype=torch.float64)
+    if Vt.dim() != 2 or Vt.shape[0] != n or (n > 1 and Vt.shape[1] < n - 1):
+        raise ValueError("V must be n x (n - 1) or larger")
+    if not (Vt.is_cuda and Vt.dtype == torch.float64 and (Vt.numel() == 0 or
+                                                           (Vt.stride(0) == 1 and Vt.stride(1) >= max(1, n)))):
+        Vt = Vt.to(device=dev, dtype=torch.float64).t().contiguous().t()
+    t = _as_dev(tau, dev)
+    if n > 1 and t.numel() < n - 1:
+        raise ValueError("tau must hold n - 1 entries")
+    ldv = max(1, n, Vt.stride(1) if Vt.numel() > 0 else 1)
+    ldz = max(1, n, Zd.stride(1) if Zd.numel() > 0 else 1)
+    with torch.cuda.device(dev):
+        _lib.check(_lib.load().mrrr_backtransform(n, m, _ptr(Vt), ldv, _ptr(t), _ptr(Zd), ldz,
+                                                   _stream_ptr(stream)))
+    return Zd
 
 
 def probe_division(a, b, stream=None):

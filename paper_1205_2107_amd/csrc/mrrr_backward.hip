@@ -243,7 +243,6 @@ __global__ void k_bwd_reduce(const Prob* __restrict__ probs, int nprob, const in
 // ---------------------------------------------------------------------------
 // host side
 
-static thread_local std::string g_err;
 static std::mutex g_mu;
 static void* g_ws = nullptr;
 static size_t g_ws_bytes = 0;
@@ -255,7 +254,7 @@ static int grow(size_t bytes) {
   g_ws_bytes = 0;
   size_t nb = std::max(bytes, (size_t)1 << 20);
   if (hipMalloc(&g_ws, nb) != hipSuccess) {
-    g_err = "hipMalloc failed for the backward workspace";
+    mrrr::set_last_error("hipMalloc failed for the backward workspace");
     return MRRR_ERR_CAPACITY;
   }
   g_ws_bytes = nb;
@@ -304,7 +303,7 @@ static int run(std::vector<Prob>& probs, hipStream_t st) {
   if (hipMemcpyAsync(dP, probs.data(), sizeof(Prob) * np, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(dT, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(dR, rowoff.data(), sizeof(int64_t) * (np + 1), hipMemcpyHostToDevice, st) != hipSuccess) {
-    g_err = "hipMemcpyAsync failed";
+    mrrr::set_last_error("hipMemcpyAsync failed");
     return MRRR_ERR_HIP;
   }
   const unsigned nt = (unsigned)tiles.size();
@@ -323,7 +322,7 @@ static int run(std::vector<Prob>& probs, hipStream_t st) {
   hipError_t e = hipStreamSynchronize(st);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
-    g_err = std::string("backward kernels failed: ") + hipGetErrorString(e);
+    mrrr::set_last_error((std::string("backward kernels failed: ") + hipGetErrorString(e)).c_str());
     return MRRR_ERR_HIP;
   }
   if (prof.on) {

@@ -43,6 +43,8 @@ void prof_add(int kernel, int64_t launches, double ms, double work, double bytes
 static mrrr_tuning g_tune = {4, 0, 0, 0, 0, {0, 0, 0}};
 static std::mutex g_tune_mu;
 
+void set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
 static int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -691,7 +693,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     const double bytes[MRRR_K_COUNT] = {0.0, 0.0, 32.0 * (double)hc.child_steps, 8.0 * ze, 0.0,
                                         8.0 * (double)hc.ckpt_z_entries};
     for (int k = 0; k < MRRR_K_COUNT; ++k) {
-      if (k == MRRR_K_BACKWARD) continue;
+      if (k == MRRR_K_BACKWARD || k == MRRR_K_BACKTRANSFORM) continue;
       double ms;
       int64_t l;
       prof.total(k, &ms, &l);

@@ -9,6 +9,8 @@ namespace mrrr {
 
 bool prof_enabled();
 void prof_add(int kernel, int64_t launches, double ms, double work, double bytes);
+// message returned by mrrr_last_error for the calling thread
+void set_last_error(const char* msg);
 
 // HIP events around launches on one stream; elapsed times are read after the
 // caller has synchronized the stream.

@@ -164,3 +164,20 @@ def test_division_probe_argument_checks():
     assert lib.mrrr_probe_division((1 << 31) + 1, None, None, None, None) == -1
     assert lib.mrrr_probe_division(4, None, None, None, None) == -2
     assert lib.mrrr_probe_division(0, None, None, None, None) == 0
+
+
+def test_backtransform_argument_checks():
+    """the back-transformation rejects bad sizes, pointers and leading
+    dimensions on the host; trivial sizes return at once"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    assert lib.mrrr_backtransform(-1, 1, fake, 1, fake, fake, 1, None) == -1
+    assert lib.mrrr_backtransform(4, -1, fake, 4, fake, fake, 4, None) == -2
+    assert lib.mrrr_backtransform(4, 2, None, 4, fake, fake, 4, None) == -3
+    assert lib.mrrr_backtransform(4, 2, fake, 3, fake, fake, 4, None) == -4
+    assert lib.mrrr_backtransform(4, 2, fake, 4, None, fake, 4, None) == -5
+    assert lib.mrrr_backtransform(4, 2, fake, 4, fake, None, 4, None) == -6
+    assert lib.mrrr_backtransform(4, 2, fake, 4, fake, fake, 3, None) == -7
+    assert lib.mrrr_backtransform(1, 5, None, 1, None, fake, 1, None) == 0
+    assert lib.mrrr_backtransform(6, 0, fake, 6, fake, None, 6, None) == 0
