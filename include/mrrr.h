@@ -102,8 +102,8 @@ int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, dou
  * mrrr_workspace_size -- bytes of caller workspace for mrrr_step_ws on a
  * problem of order n and this range: the per-row arrays (slots, count grid,
  * node table, cluster list), the root representations plus room for child
- * representations of n rows each (MRRR_WS_CHILD_ROWS_PER_N * n rows beyond
- * the speculative candidates of one level), and the eigenvector scratch for
+ * representations of n rows each (MRRR_WS_CHILD_ROWS_PER_N * n rows, with
+ * the checkpoints of their candidate shifts), and the eigenvector scratch for
  * every wanted pair at once.  A smaller workspace also works down to a floor
  * the solver checks as it goes: the eigenvector phase then runs in several
  * launches, and a tree whose representations do not fit returns status

@@ -24,13 +24,10 @@ constexpr double kPertScale = 4.0;     // root perturbation 4 eps u, u in [-1, 1
 constexpr int kMaxRqi = 5;              // Rayleigh-quotient solves per singleton (one more to repeat the best)
 constexpr int kMaxSweeps = 200;        // refinement sweeps per eigenvalue (cap)
 constexpr int kSeg = 8;                 // eigenvector solves: rows per recomputed segment
-constexpr int kChildMaskedFrom = 1024;   // child builds: clusters per launch from which stores are masked
-constexpr int kChildSpecMany = 2;        // speculative child regions per cluster, masked form
-constexpr int kChildSpecFew = 4;         // ... branch-free form
-constexpr int64_t kChildFewMaxN = 1 << 24;  // branch-free form only below this block order
-constexpr int kChildSpecAll = 16;        // ... branch-free form with few clusters: every candidate
-constexpr int64_t kChildAllMaxN = 1 << 22;     // every-candidate form only below this block order
-constexpr int64_t kChildAllMaxRows = 1 << 25;  // ... and while its regions take at most this many rows
+// pool rows a child build takes beyond the child's own n rows: the s_i
+// checkpoints of its 16 candidate shifts every 64 rows (4 doubles per row of
+// the pool)
+__host__ __device__ inline int64_t child_ck_rows(int64_t n) { return 4 * ((n + 63) / 64); }
 constexpr int kCkptMinRun = 16;          // checkpointing eigenvector kernel: equal-node run length ...
 constexpr int kCkptMinN = 256;           // ... and block order from which it is used
 

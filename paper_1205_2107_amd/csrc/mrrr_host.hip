@@ -330,7 +330,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
   // in arena mode it is carved last, so it grows in place)
   size_t pool_rows = (size_t)ntot + (size_t)std::max<int64_t>(4 * 1024, ntot / 2);
   if (arena) {
-    pool_rows = (size_t)ntot + (Z != nullptr ? (size_t)kChildSpecFew * (size_t)nmax_prob : 0);
+    pool_rows = (size_t)ntot + (Z != nullptr ? (size_t)2 * (size_t)nmax_prob : 0);
     const size_t room = arena_free(W) > vec_reserve ? arena_free(W) - vec_reserve : 0;
     pool_rows = std::max<size_t>((size_t)ntot, std::min(pool_rows, room / sizeof(Rep)));
   } else if (W.pool.bytes / sizeof(Rep) > pool_rows) {
@@ -480,25 +480,19 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       if (arena && (size_t)(node_base + ncl) > node_cap)
         return fail(MRRR_ERR_CAPACITY, "node table of %zu entries exhausted", node_cap);
       if ((rc = ensure(W, W.nodes, sizeof(Node) * (size_t)(node_base + ncl), st, true)) != 0) return rc;
-      const bool masked = ncl >= kChildMaskedFrom || nmax_prob >= kChildFewMaxN;
-      const bool all = !masked && nmax_prob < kChildAllMaxN &&
-                       (size_t)kChildSpecAll * (size_t)hc.cluster_rows <= (size_t)kChildAllMaxRows;
-      int spec = masked ? kChildSpecMany : (all ? kChildSpecAll : kChildSpecFew);
+      // pool demand of the level: each cluster's child (its block's n rows)
+      // and the checkpoints of its candidates (child_ck_rows, n / 16 rows)
       const size_t used_rows = (size_t)std::max<unsigned long long>(hc.pool_used, (unsigned long long)ntot);
-      auto need_for = [&](int sp) { return used_rows + (size_t)sp * (size_t)hc.cluster_rows; };
+      const size_t level_rows = (size_t)hc.cluster_rows + (size_t)hc.cluster_rows / 16 + (size_t)8 * (size_t)ncl;
       if (arena) {
-        // the pool grows in place up to what the eigenvector phase must keep
-        // free; fewer speculative regions when the rest does not fit (the
-        // values do not depend on how many candidates store speculatively)
+        // the pool grows in place up to what the eigenvector phase must keep free
         const size_t pool_start = (size_t)((char*)W.pool.p - W.abase);
         const size_t room_rows =
             (W.acap > vec_reserve + pool_start) ? (W.acap - vec_reserve - pool_start) / sizeof(Rep) : 0;
-        if (need_for(spec) > room_rows && spec == kChildSpecAll) spec = kChildSpecFew;
-        if (need_for(spec) > room_rows && spec == kChildSpecFew && nmax_prob < kChildFewMaxN) spec = kChildSpecMany;
-        if (need_for(spec) > room_rows)
+        if (used_rows + level_rows > room_rows)
           return fail(MRRR_ERR_CAPACITY, "workspace of %zu bytes too small for the representation tree", W.acap);
       }
-      const size_t need_rows = need_for(spec);
+      const size_t need_rows = used_rows + level_rows;
       if (need_rows * sizeof(Rep) > W.pool.bytes) {
         if ((rc = ensure(W, W.pool, need_rows * sizeof(Rep) + (arena ? 0 : W.pool.bytes / 2), st, true)) != 0)
           return rc;
@@ -513,7 +507,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
       }
       prof.begin(MRRR_K_CHILD);
       launch_child(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<double>(W.lo),
-                   P_<double>(W.hi), dpool, pool_cap, dC, spec, lim.child_growth_limit);
+                   P_<double>(W.hi), dpool, pool_cap, dC, lim.child_growth_limit);
       prof.end();
       launch_shift(st, dB, P_<Node>(W.nodes), ncl, node_base, P_<Cluster>(W.clusters), P_<int64_t>(W.scol),
                    P_<double>(W.lo), P_<double>(W.hi), P_<int32_t>(W.clo), P_<int32_t>(W.chi),
@@ -829,7 +823,8 @@ static size_t workspace_bytes(int64_t n, int64_t m, bool vectors, const mrrr_tun
   add(sizeof(int64_t) * (n + 1));             // cstart
   if (vectors) add(sizeof(Cluster) * (size_t)(n / 2 + 1));
   // pool: roots, speculative candidates of one level, children
-  const size_t rows = (size_t)n + (vectors ? (size_t)(kChildSpecAll + MRRR_WS_CHILD_ROWS_PER_N) * (size_t)n : 0);
+  const size_t rows =
+      (size_t)n + (vectors ? (size_t)MRRR_WS_CHILD_ROWS_PER_N * (size_t)n + (size_t)child_ck_rows(n) * 32 : 0);
   add(sizeof(Rep) * rows);
   if (vectors) {
     const int64_t nch = (n + vs - 1) / vs;

@@ -41,16 +41,6 @@ __device__ inline void atomic_max_nonneg(uint64_t* addr, double v) {
 
 __device__ inline void set_status(Counters* C, int code) { atomicCAS(&C->status, 0, code); }
 
-// a pointer every lane of the wavefront holds: make it scalar (SGPR) so loads
-// through it become scalar-cache loads shared by the wavefront
-template <class T>
-__device__ __forceinline__ T* wave_uniform(T* p) {
-  const uint64_t v = (uint64_t)p;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (T*)(((uint64_t)hi << 32) | (uint64_t)lo);
-}
-
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
 
 
@@ -287,7 +277,7 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
     // the pivots must keep the sign of the definite side and stay finite;
     // sgn * Dp is exact, and a NaN fails the comparison
     const double sgn = left ? 1.0 : -1.0;
-    bool ok = true;
+    int ok = 1;
     double Dp = 0.0;
     for (int c0 = 0; c0 < n; c0 += kRootChunk) {
       // rows c0 .. c0 + m - 1, plus the next chunk's first diagonal entry
@@ -305,13 +295,13 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
           const double L = s_e[i] / Dp;
           s_D[i] = Dp;
           s_L[i] = L;
-          ok = ok & isfinite(Dp) & isfinite(L) & (sgn * Dp > 0.0);
+          ok &= (int)isfinite(Dp) & (int)isfinite(L) & (int)(sgn * Dp > 0.0);
           Dp = (s_d[i + 1] - sigma) - L * s_e[i];
         }
         if (mi < m) {  // the last row of the block
           s_D[mi] = Dp;
           s_L[mi] = 0.0;
-          ok = ok & isfinite(Dp) & (sgn * Dp > 0.0);
+          ok &= (int)isfinite(Dp) & (int)(sgn * Dp > 0.0);
         }
       }
       __syncthreads();
@@ -321,7 +311,7 @@ __global__ void __launch_bounds__(256) k_root(Problem* __restrict__ P, Block* __
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
+    if (threadIdx.x == 0) s_ok = ok;
     __syncthreads();
     delta *= 2.0;
     if (s_ok) break;
@@ -556,31 +546,12 @@ __device__ inline void staged_rows(const double* __restrict__ Rd, int n, double*
                 [&](int i, int, double D, double L, double LD, double LLD) { body(i, D, L, LD, LLD); });
 }
 
-// Raw buffer resource over bytes [p, p + bytes): a buffer store whose offset
-// lies at or beyond `bytes` is discarded by the hardware range check, so a
-// wavefront can store from a few lanes without branching around the store.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr uint32_t kDropOff = 0x80000000u;  // beyond every resource used here
-
 // a value equal in every lane, made visibly wave-uniform (scalar registers)
 __device__ __forceinline__ long long uniform_ll(long long x) {
   const unsigned long long u = (unsigned long long)x;
   const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
   const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
   return (long long)(((unsigned long long)hi << 32) | lo);
-}
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(void* p, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
-}
-__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t off, double a, double b) {
-  const u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
-  const u32x4 v = {ua.x, ua.y, ub.x, ub.y};
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
-}
-__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t off, double a) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, a), r, (int)off, 0, 0);
 }
 
 // Sturm count plus log-derivative (as sturm_count_deriv) for a wavefront
@@ -1118,14 +1089,18 @@ __global__ void k_cls_runs(const Block* __restrict__ B, const Node* __restrict__
 //    growing geometrically from the end eigenvalue's bracket to half the outer
 //    gap -- by the stationary qds
 //      s_1 = -sigma, D+_i = D_i + s_i, L+_i = LD_i / D+_i, s_{i+1} = L+_i L_i s_i - sigma
-//    over LDS-staged parent rows, keeping the element growth max|D+_i|; the
-//    two closest candidates also store their rows as they go.  The closest
-//    shift whose growth is within the bound wins (ties between the two ends:
-//    the smaller growth); without one, the least growth.  Only when a farther
-//    candidate wins does pass 2 repeat its transform and store it.
+//    over LDS-staged parent rows, keeping the element growth max|D+_i| and
+//    the value of s_i every kSG rows (checkpoints).  The closest shift whose
+//    growth is within the bound wins (ties between the two ends: the smaller
+//    growth); without one, the least growth.  Pass 2 writes the winner's
+//    rows: every lane recomputes the segments of kSG rows that start at its
+//    checkpoints (the same arithmetic from the same s_i, so the rows equal a
+//    sequential pass bit for bit), which takes a 64th of the sequential
+//    chain.
 
 constexpr int kChildLevels = 8;
 constexpr int kChildCand = 2 * kChildLevels;
+static_assert(kChildCand == 16 && kSG == 64, "child checkpoints: 16 candidates every 64 rows (child_ck_rows)");
 
 __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const double* __restrict__ lo,
                                      const double* __restrict__ hi, int cand, bool* valid) {
@@ -1149,18 +1124,24 @@ __device__ inline double child_sigma(const Cluster& cl, const Block& blk, const 
   return side ? h0 + delta : l0 - delta;
 }
 
-// kMasked: the kSpec = 2 closest candidates store their rows, each by its
-// owning lane under an execution mask (few store lanes per instruction:
-// cheaper when many wavefronts share the chip).  Otherwise the kSpec closest
-// candidates (4: levels 0 and 1 at both ends; or all of them) store theirs
-// through one buffer resource whose range check drops the other lanes'
-// stores, which keeps the loop branch-free (faster for a lone wavefront,
-// whose LDS reads then batch across rows) and saves the second pass when one
-// of them wins; the instruction count does not depend on kSpec.  That form
-// needs (kSpec - 1) n rows of 32 bytes to stay below 2^31 bytes (the host
-// picks the masked form for blocks of 2^24 rows or more, and every candidate
-// only below 2^22 rows and with few clusters).
-template <bool kMasked, int kSpec>
+// one row of the stationary qds transform of a child candidate: the pivot,
+// multiplier and products of row i from the parent row (D, L, LD) and s_i;
+// returns s_{i+1}.  Both passes of k_child use it, so pass 2 repeats pass 1
+// bit for bit.
+__device__ __forceinline__ double child_row(double D, double L, double LD, double sv, double sigma, double& dp,
+                                            double& lp, double& ld, double& lld) {
+  dp = D + sv;
+  lp = LD * rcp_nr2(dp);
+  ld = lp * dp;
+  lld = ld * lp;
+  return fma(lp * L, sv, -sigma);
+}
+
+// One wavefront per cluster: lanes 0 .. kChildCand-1 evaluate the candidate
+// shifts (pass 1), then all 64 lanes write the winner's rows from its
+// checkpoints (pass 2).  Pool use per cluster: the child's n rows and, after
+// them, the checkpoints of every candidate (kChildCand x ceil(n / kSG)
+// doubles).
 __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node* __restrict__ N, int nclusters,
                                               int node_base, const Cluster* __restrict__ clusters,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
@@ -1173,75 +1154,45 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   const Node par = N[cl.node];
   const Block blk = B[par.blk];
   const int n = __builtin_amdgcn_readfirstlane(blk.n);
+  const int nseg = (n + kSG - 1) / kSG;
   const double* Rd = reinterpret_cast<const double*>(pool + par.rep);
-  // child-sized regions for the closest candidates (lanes 0 .. kSpec-1), which
-  // store their rows while pass 1 runs; usually one of them wins
-  static_assert(kMasked ? kSpec == 2 : (kSpec >= 2 && kSpec <= kChildCand), "speculative regions");
+  const unsigned long long rows = (unsigned long long)n + (unsigned long long)child_ck_rows(n);
   long long base = -1;
   if (lane == 0) {
-    base = (long long)atomicAdd(&C->pool_used, (unsigned long long)kSpec * (unsigned long long)n);
-    if ((unsigned long long)base + (unsigned long long)kSpec * (unsigned long long)n > pool_cap) {
+    base = (long long)atomicAdd(&C->pool_used, rows);
+    if ((unsigned long long)base + rows > pool_cap) {
       set_status(C, 3);
       base = -1;
     }
   }
   base = uniform_ll(__shfl(base, 0, 64));
+  // checkpoints: ck[cand * nseg + g] = s at row g kSG of candidate cand
+  double* const ck = reinterpret_cast<double*>(pool + (base >= 0 ? base + n : 0));
+  const bool cand_lane = lane < kChildCand;
   bool valid = false;
   double sigma = 0.0;
-  if (lane < kChildCand) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
-  // the speculative regions: region k holds candidate k's rows; without the
-  // mask one buffer resource, rebased at every group, spans all of them
-  char* const reg0 = reinterpret_cast<char*>(pool + (base >= 0 ? base : 0));
-  char* const reg1 = reg0 + (int64_t)n * sizeof(Rep);
-  const bool own0 = base >= 0 && lane == 0, own1 = base >= 0 && lane == 1;
-  const bool own = base >= 0 && lane < kSpec;
-  const uint32_t regoff = (uint32_t)(lane < kSpec ? lane : 0) * (uint32_t)n * (uint32_t)sizeof(Rep);
-  const int span = (kSpec - 1) * n * (int)sizeof(Rep) + kSG * (int)sizeof(Rep);
-  // pass 1: growth of every candidate (rows 0 .. n-2; the last row has no L)
+  if (cand_lane) sigma = child_sigma(cl, blk, lo, hi, lane, &valid);
+  // pass 1: growth and checkpoints of every candidate (rows 0 .. n-2; the last row has no L)
+  double sv = -sigma, gmax = 0.0, chk = 0.0;
   // chk: x * 0 is NaN exactly when x is infinite or NaN, so chk stays 0
   // while every pivot and multiplier is finite (a check kept off the
   // recurrence's dependency chain)
-  double sv = -sigma, gmax = 0.0, chk = 0.0;
-  __amdgpu_buffer_rsrc_t r0 = raw_rsrc(reg0, 0);
   staged_rows_g(
       Rd, n, n - 1, st,
-      [&](int g0) { r0 = raw_rsrc(reg0 + (int64_t)g0 * sizeof(Rep), kMasked ? 0 : span); },
-      [&](int i, int j, double D, double L, double LD, double) {
-        const double dp = D + sv;
+      [&](int g0) {
+        if (cand_lane && base >= 0) ck[lane * nseg + g0 / kSG] = sv;
+      },
+      [&](int, int, double D, double L, double LD, double) {
+        double dp, lp, ld, lld;
+        sv = child_row(D, L, LD, sv, sigma, dp, lp, ld, lld);
         gmax = fmax(gmax, fabs(dp));
-        const double lp = LD * rcp_nr2(dp);
-        const double ld = lp * dp;
-        const double lld = ld * lp;
-        if (kMasked) {
-          if (own0 || own1) {
-            double* q = reinterpret_cast<double*>(own0 ? reg0 : reg1) + 4 * (int64_t)i;
-            q[0] = dp;
-            q[1] = lp;
-            q[2] = ld;
-            q[3] = lld;
-          }
-        } else {
-          const uint32_t o = own ? regoff + (uint32_t)j * sizeof(Rep) : kDropOff;
-          bstore2(r0, o, dp, lp);
-          bstore2(r0, o + 16, ld, lld);
-        }
-        sv = fma(lp * L, sv, -sigma);
         chk = fma(dp, 0.0, chk);
         chk = fma(lp, 0.0, chk);
       });
   bool fin = isfinite(chk);
-  {
-    const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
-    gmax = fmax(gmax, fabs(dp));
-    fin = fin && isfinite(dp);
-    if (own) {
-      double* q = reinterpret_cast<double*>(reg0 + (int64_t)lane * n * sizeof(Rep)) + 4 * (int64_t)(n - 1);
-      q[0] = dp;
-      q[1] = 0.0;
-      q[2] = 0.0;
-      q[3] = 0.0;
-    }
-  }
+  const double dlast = Rd[4 * (int64_t)(n - 1)] + sv;
+  gmax = fmax(gmax, fabs(dlast));
+  fin = fin && isfinite(dlast);
   const double growth = (valid && fin) ? gmax : INFINITY;
   double gr[kChildCand];
 #pragma unroll
@@ -1265,10 +1216,10 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
   // optional hard limit on the element growth (caller's setting): without an
   // acceptable candidate the cluster gets no child (status 1)
   if (pick >= 0 && growth_limit > 0.0 && !(gr[pick] <= growth_limit * (blk.gu - blk.gl))) pick = -1;
-  const long long off =
-      uniform_ll((pick < 0 || base < 0) ? -1 : base + (pick < kSpec ? pick : 0) * (long long)n);
+  const long long off = uniform_ll((pick < 0 || base < 0) ? -1 : base);
   bool v;
   const double sg = (pick >= 0) ? child_sigma(cl, blk, lo, hi, pick, &v) : 0.0;
+  const double dl = __shfl(dlast, pick >= 0 ? pick : 0, 64);
   if (lane == 0) {
     if (forced) atomicAdd(&C->child_reject, 1ull);
     Node nd;
@@ -1298,30 +1249,30 @@ __global__ void __launch_bounds__(64) k_child(const Block* __restrict__ B, Node*
     }
     N[node_base + c] = nd;
   }
-  if (off < 0 || pick < kSpec) return;
-  // pass 2 (a farther candidate won): every lane repeats its transform (the
-  // staging needs the whole wavefront); lanes 0..3 store field q of each row
-  char* const Q = reinterpret_cast<char*>(pool + off);
-  sv = -sg;
-  __amdgpu_buffer_rsrc_t rq = raw_rsrc(Q, 0);
-  staged_rows_g(
-      Rd, n, n - 1, st,
-      [&](int g0) { rq = raw_rsrc(Q + (int64_t)g0 * sizeof(Rep), kSG * (int)sizeof(Rep)); },
-      [&](int i, int j, double D, double L, double LD, double) {
-        const double dp = D + sv;
-        const double lp = LD * rcp_nr2(dp);
-        const double ld = lp * dp;
-        const double val = (lane == 0) ? dp : (lane == 1) ? lp : (lane == 2) ? ld : ld * lp;
-        if (kMasked) {
-          if (lane < 4) reinterpret_cast<double*>(Q)[4 * (int64_t)i + lane] = val;
-        } else {
-          bstore1(rq, lane < 4 ? (uint32_t)(j * 4 + lane) * 8u : kDropOff, val);
-        }
-        sv = fma(lp * L, sv, -sg);
-      });
-  if (lane < 4) {
-    const double dp = Rd[4 * (int64_t)(n - 1)] + sv;
-    reinterpret_cast<double*>(Q)[4 * (int64_t)(n - 1) + lane] = (lane == 0) ? dp : 0.0;
+  if (off < 0) return;
+  // pass 2: lane l writes segments l, l + 64, ... of the winner, each from its checkpoint
+  double* const Q = reinterpret_cast<double*>(pool + off);
+  for (int g = lane; g < nseg; g += 64) {
+    double s2 = ck[pick * nseg + g];
+    const int i0 = g * kSG, i1 = min(i0 + kSG, n - 1);
+#pragma unroll 4
+    for (int i = i0; i < i1; ++i) {
+      const double* row = Rd + 4 * (int64_t)i;
+      double dp, lp, ld, lld;
+      s2 = child_row(row[0], row[1], row[2], s2, sg, dp, lp, ld, lld);
+      double* q = Q + 4 * (int64_t)i;
+      q[0] = dp;
+      q[1] = lp;
+      q[2] = ld;
+      q[3] = lld;
+    }
+  }
+  if (lane == 0) {
+    double* q = Q + 4 * (int64_t)(n - 1);
+    q[0] = dl;
+    q[1] = 0.0;
+    q[2] = 0.0;
+    q[3] = 0.0;
   }
 }
 
@@ -2930,19 +2881,9 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
 
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
-                  int spec, double growth_limit) {
-  // a lone or few wavefronts are latency-bound (branch-free stores), a full
-  // chip is issue-bound (masked stores)
-  static_assert(kChildSpecAll == kChildCand, "every candidate");
-  if (spec == kChildSpecMany)
-    hipLaunchKernelGGL((k_child<true, kChildSpecMany>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base,
-                       clusters, lo, hi, pool, pool_cap, C, growth_limit);
-  else if (spec == kChildSpecFew)
-    hipLaunchKernelGGL((k_child<false, kChildSpecFew>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
-                       node_base, clusters, lo, hi, pool, pool_cap, C, growth_limit);
-  else
-    hipLaunchKernelGGL((k_child<false, kChildSpecAll>), dim3(nclusters), dim3(64), 0, st, B, N, nclusters,
-                       node_base, clusters, lo, hi, pool, pool_cap, C, growth_limit);
+                  double growth_limit) {
+  hipLaunchKernelGGL(k_child, dim3(nclusters), dim3(64), 0, st, B, N, nclusters, node_base, clusters, lo, hi, pool,
+                     pool_cap, C, growth_limit);
 }
 
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,

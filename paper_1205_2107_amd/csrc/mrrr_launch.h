@@ -34,7 +34,7 @@ void launch_cls_runs(hipStream_t st, const Block* B, const Node* N, int nruns, c
                      Counters* C, int max_depth);
 void launch_child(hipStream_t st, const Block* B, Node* N, int nclusters, int node_base, const Cluster* clusters,
                   const double* lo, const double* hi, Rep* pool, unsigned long long pool_cap, Counters* C,
-                  int spec, double growth_limit);
+                  double growth_limit);
 void launch_shift(hipStream_t st, const Block* B, const Node* N, int nclusters, int node_base,
                   const Cluster* clusters, const int64_t* scol, double* lo, double* hi, int32_t* clo, int32_t* chi,
                   int32_t* snode, uint32_t* sflag, double* sgap);
