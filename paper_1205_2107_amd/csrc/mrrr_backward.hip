@@ -85,17 +85,29 @@ __global__ void __launch_bounds__(NT) k_bwd_c(const Prob* __restrict__ probs, co
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
-  // loader: thread t fetches column (t / 4) rows r0 + 4 (t % 4) .. +3
+  // loader: thread t fetches column (t / 4) rows r0 + 4 (t % 4) .. +3; the
+  // next step's operands are fetched into registers while the matrix cores
+  // work on the current ones
   const int lc = t >> 2, lr = (t & 3) * 4;
-  for (int64_t r0 = 0; r0 < n; r0 += TK) {
+  const int64_t ci = i0 + lc, ck = k0 + lc;
+  double ra[4], rb[4];
+  auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t r = r0 + lr + u;
-      const int64_t ci = i0 + lc, ck = k0 + lc;
-      As[lc][lr + u] = (r < n && ci < n) ? pb.V[ci * ld + r] : 0.0;
-      Bs[lc][lr + u] = (r < n && ck < n) ? pb.G[ck * ld + r] : 0.0;
+      ra[u] = (r < n && ci < n) ? pb.V[ci * ld + r] : 0.0;
+      rb[u] = (r < n && ck < n) ? pb.G[ck * ld + r] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int64_t r0 = 0; r0 < n; r0 += TK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[lc][lr + u] = ra[u];
+      Bs[lc][lr + u] = rb[u];
     }
     __syncthreads();
+    if (r0 + TK < n) fetch(r0 + TK);
     mma_step(As, Bs, acc, wr, wc, lane);
     __syncthreads();
   }
@@ -152,15 +164,25 @@ __global__ void __launch_bounds__(NT) k_bwd_band(const Prob* __restrict__ probs,
   const int ar = t >> 4, ai = (t & 15) * 4;
   // B = M[r0.., k0..]: thread t reads column k0 + t / 4, rows r0 + 4 (t % 4) .. +3
   const int bc = t >> 2, brr = (t & 3) * 4;
-  for (int64_t r0 = 0; r0 < n; r0 += TK) {
+  double ra[4], rm[4];
+  auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t i = i0 + ai + u, r = r0 + ar;
-      As[ai + u][ar] = (i < n && r < n) ? pb.V[r * ld + i] : 0.0;
+      ra[u] = (i < n && r < n) ? pb.V[r * ld + i] : 0.0;
       const int64_t rb = r0 + brr + u, kb = k0 + bc;
-      Bs[bc][brr + u] = (rb < n && kb < n) ? pb.M[kb * n + rb] : 0.0;
+      rm[u] = (rb < n && kb < n) ? pb.M[kb * n + rb] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int64_t r0 = 0; r0 < n; r0 += TK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[ai + u][ar] = ra[u];
+      Bs[bc][brr + u] = rm[u];
     }
     __syncthreads();
+    if (r0 + TK < n) fetch(r0 + TK);
     mma_step(As, Bs, acc, wr, wc, lane);
     __syncthreads();
   }
