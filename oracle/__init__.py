@@ -13,6 +13,8 @@ never touches it, and it shares no code with the GPU library.
                         (see ``adjoint.py``).
 * ``apply_q``        -- Stage 5 back-transformation Y = Q Z, one Householder
                         reflector at a time (see ``backtransform.py``).
+* ``tridiagonalize`` -- Stage 3 reduction T = Q^T M Q, one Householder
+                        reflector at a time (see ``tridiagonalize.py``).
 """
 import ctypes
 import os
@@ -22,6 +24,7 @@ import numpy as np
 
 from .adjoint import dense_adjoint  # noqa: F401
 from .backtransform import apply_q  # noqa: F401
+from .tridiagonalize import tridiagonalize  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrrr_oracle.c")
