@@ -1380,15 +1380,20 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   const double slack = 0.25 * V.gap;
   const bool inside = (lamc >= V.lo - slack && lamc <= V.hi + slack);
   // resid / gap bounds the sine of the angle between z and the eigenvector
-  // (gap theorem); otherwise stop once the correction is within 2 eps |lambda|
-  // (two to four ulps: a further solve would only move lambda by rounding;
-  // LAPACK's dlarrv uses the same tolerance).  The floor test: the first
-  // correction must halve the residual and every later one cut the smallest
-  // residual so far by 32 (Rayleigh quotient iteration converges cubically
-  // above the rounding floor, so a smaller cut means the floor is reached).
-  // There, or at the iteration cap, the solve with the smallest residual is
-  // kept: the current one if it is that, else it is repeated.
-  const bool small = resid <= rqi_angle_tol(n) * V.gap || fabs(corr) <= 2.0 * kEps * fabs(lam);
+  // (gap theorem): such a solve is kept.  Once the correction is within
+  // 2 eps |lambda| (two to four ulps, LAPACK's dlarrv tolerance) lambda cannot
+  // improve, but z was solved at the uncorrected lambda and leans towards the
+  // nearest other eigenvector by about |corr| / gap -- up to 2 eps / relgap,
+  // a few thousand ulps for singletons near the classification threshold --
+  // so one more solve at the corrected lambda is kept instead.  The floor
+  // test: the first correction must halve the residual and every later one
+  // cut the smallest residual so far by 32 (Rayleigh quotient iteration
+  // converges cubically above the rounding floor, so a smaller cut means the
+  // floor is reached).  There, or at the iteration cap, the solve with the
+  // smallest residual is kept: the current one if it is that, else it is
+  // repeated.
+  const bool fine = resid <= rqi_angle_tol(n) * V.gap;
+  const bool flat = fabs(corr) <= 2.0 * kEps * fabs(lam);
   const bool progress = resid < (it >= 1 ? 0.03125 : 0.5) * V.resid;
   const bool improved = resid < V.resid;
   if (improved) {
@@ -1397,9 +1402,12 @@ __device__ inline void rqi_commit(VecState& V, bool& conv, bool& last, int it, i
   } else {
     V.stall++;
   }
-  if (last || small) {
+  if (last || fine || (flat && (corr == 0.0 || !inside || it >= kMaxRqi))) {
     conv = true;
     V.lam_out = inside ? lamc : lam;
+  } else if (flat) {
+    V.lam = lamc;
+    last = true;
   } else if (!progress || it + 1 >= kMaxRqi) {
     V.fallback = true;
     if (improved) {

@@ -783,3 +783,24 @@ def test_backward_batched_c5_shape_vs_oracle(M):
     with ThreadPoolExecutor(max_workers=8) as ex:
         errs = list(ex.map(check, range(count)))
     assert max(errs) <= 1e-6, max(errs)
+
+
+@pytest.mark.parametrize("n", [100, 150, 200, 300])
+def test_reduced_dense_matrices_small_orders(M, n):
+    # tridiagonals of small dense random matrices (LAPACK's dsytrd): their
+    # spectra put singletons just above the classification threshold, where a
+    # vector solved at a lambda a few ulps off leans towards its neighbour by
+    # up to 2 eps / relgap -- more than 10 n eps at these orders.  Parity with
+    # the oracle and the bars for every seed.
+    lapack = pytest.importorskip("scipy.linalg.lapack")
+    worst = 0.0
+    for seed in range(6):
+        A = W.dense_symmetric(n, 8800 + 10 * n + seed)
+        c, d, e, tau, info = lapack.dsytrd(A, lower=1)
+        assert info == 0
+        w, Z, _ = gpu_solve(M, d, e)
+        wo, Zo, st = oracle_solve(d, e)
+        assert st == 0
+        assert_parity(d, e, w, Z, wo, Zo)
+        worst = max(worst, orth_ratio(Z))
+    print(f"n={n}: worst orthogonality {worst:.2f} n eps")
