@@ -27,6 +27,9 @@ Also reported on the same JSON line:
   backtransform the Stage 5 back-transformation Y = Q Z (FP64 MFMA, compact-WY
                 blocks of 64 reflectors) at n = m = 20000, against the FP64
                 matrix peak
+  reduce        the Stage 3 reduction of a dense symmetric order-20000 matrix
+                to tridiagonal form (panels of 64 reflectors), against HBM
+                bandwidth for the matrix-vector products that bound it
 """
 import argparse
 import json
@@ -325,6 +328,42 @@ def backtransform_leg(torch, M, n, reps=3):
             "frac_of_fp64_mfma_peak": flops / t / 1e12 / PEAK_FP64_MATRIX_TFLOPS, "reps": reps}
 
 
+def reduce_leg(torch, M, n, reps=2):
+    """Stage 3 reduction T = Q^T M Q of a dense symmetric order-n matrix
+    (lower triangle U(-1, 1), seeded, drawn on the device).  Each call
+    overwrites its input, so every repetition reduces a fresh device copy made
+    outside the timed region.  Work 4 n^3 / 3 flops; HBM bytes of the
+    matrix-vector products (one read of the trailing columns per reflector,
+    sum over i of 8 (n - i - 1)^2) bound it."""
+    from paper_1205_2107_amd import workloads as W
+    lower, full = W.dense_symmetric_device(n, W.SEEDS["c2_random"], "cuda")
+    del full
+    work = torch.empty_like(lower)
+    ts = []
+    prof = []
+    for r in range(reps + 1):
+        work.copy_(lower)
+        torch.cuda.synchronize()
+        if r > 0:
+            M.profile(True)
+        t0 = time.perf_counter()
+        M.tridiagonalize(work)
+        torch.cuda.synchronize()
+        if r > 0:
+            ts.append(time.perf_counter() - t0)
+            prof.append(M.profile_read()["tridiag"])
+            M.profile(False)
+    del work, lower
+    t = median(ts)
+    nn = float(n)
+    flops = 4.0 / 3.0 * nn ** 3
+    symv_bytes = 8.0 * (nn - 1.0) * nn * (2.0 * nn - 1.0) / 6.0
+    return {"n": n, "seconds": t, "gflops": flops / t / 1e9,
+            "symv_bytes": symv_bytes, "symv_gbs_over_call": symv_bytes / t / 1e9,
+            "frac_of_hbm_peak_over_call": symv_bytes / t / 1e9 / PEAK_HBM_GBS,
+            "launches": prof[-1]["launches"] if prof else None, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +374,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-backtransform", action="store_true")
+    ap.add_argument("--no-reduce", action="store_true")
+    ap.add_argument("--only-reduce", action="store_true",
+                    help="only the reduction leg (for a profiler run); prints its JSON")
     ap.add_argument("--only-backtransform", action="store_true",
                     help="only the back-transformation leg (for a profiler run); prints its JSON")
     ap.add_argument("--batched-count", type=int, default=4096)
@@ -354,6 +396,10 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.n
+    if args.only_reduce:
+        log("[bench] reduction leg only")
+        print(json.dumps({"reduce": reduce_leg(torch, M, n)}), flush=True)
+        return
     if args.only_backtransform:
         log("[bench] back-transformation leg only")
         print(json.dumps({"backtransform": backtransform_leg(torch, M, n)}), flush=True)
@@ -464,6 +510,10 @@ def main():
     if not args.no_backtransform:
         log("[bench] back-transformation leg")
         out["backtransform"] = backtransform_leg(torch, M, n)
+        torch.cuda.empty_cache()
+    if not args.no_reduce:
+        log("[bench] reduction leg")
+        out["reduce"] = reduce_leg(torch, M, n)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

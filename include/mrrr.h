@@ -285,6 +285,10 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
  *   MRRR_K_BACKTRANSFORM  mrrr_backtransform (all its launches as one):
  *                   work = 4 K nb m flops per block of nb reflectors over
  *                   its K rows (about 2 n^2 m in all)
+ *   MRRR_K_TRIDIAG  mrrr_tridiagonalize (all its launches as one):
+ *                   work = 4 n^3 / 3 flops; bytes = 8 per entry of the
+ *                   trailing columns the matrix-vector products read
+ *                   (sum over i of (n - i - 1)^2)
  * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
 #define MRRR_K_GRID 0
 #define MRRR_K_REFINE 1
@@ -293,7 +297,8 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
 #define MRRR_K_BACKWARD 4
 #define MRRR_K_VECTORS_CKPT 5
 #define MRRR_K_BACKTRANSFORM 6
-#define MRRR_K_COUNT 7
+#define MRRR_K_TRIDIAG 7
+#define MRRR_K_COUNT 8
 
 typedef struct {
   int64_t launches;
@@ -327,6 +332,33 @@ int mrrr_profile_read(int kernel, mrrr_kernel_time* out); /* -1 on a bad kernel 
  * failed launch.  n <= 1 or m == 0 leaves Z as it is. */
 int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const double* tau, double* Z,
                        int64_t ldz, void* stream);
+
+/* Stage 3 reduction to tridiagonal form (Sec. 1.2, stage 3; Sec. 2.2: the
+ * direct reduction of the dense pipeline): T = Q^T M Q for the real symmetric
+ * M, by Householder reflectors in the storage a lower reduction (LAPACK's
+ * dsytrd with uplo 'L') leaves, so that mrrr_backtransform applies Q.
+ *   A    device, n x n column-major (leading dimension lda).  On entry the
+ *        lower triangle holds M (the strict upper triangle is not read).  On
+ *        return the diagonal holds d, the first subdiagonal e, and
+ *        A[(i+2..n-1) + i lda] the reflector v_i below its unit entry
+ *        (v_i[0..i] = 0, v_i[i+1] = 1); the strict upper triangle is
+ *        overwritten (workspace);
+ *   d    device, n doubles: the diagonal of T;
+ *   e    device, n - 1 doubles: the off-diagonal of T (e_i = beta_i, either
+ *        sign);
+ *   tau  device, n - 1 doubles: H_i = I - tau_i v_i v_i^T (tau_{n-2} = 0).
+ * The reflector of x = (alpha, x_2, ...): beta = -sign(alpha) ||x|| (alpha
+ * = 0 counts as positive), tau = (beta - alpha) / beta, v = x / (alpha -
+ * beta) below the unit entry; H = I (tau = 0, beta = alpha) when x_2.. are
+ * zero.  Blocked in panels of 64 columns (trailing update on FP64 matrix
+ * cores); reductions in a fixed order, so results repeat exactly.  The library
+ * keeps a grow-only workspace (2 x 64 n doubles plus O(n)); calls are
+ * serialized by a lock and synchronize the stream before returning.  Returns
+ * 0; -1 (n < 0 or n > 2^20), -2 (A null with n > 0), -3 (lda < max(1, n)),
+ * -4 (d null with n > 0), -5 (e null with n > 1), -6 (tau null with n > 1);
+ * MRRR_ERR_CAPACITY when the workspace cannot be allocated; MRRR_ERR_HIP on a
+ * failed launch.  Non-finite entries propagate (no status). */
+int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e, double* tau, void* stream);
 
 /* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
  * caller-given operands (no solve; for tests of their rounding).  a, b: device

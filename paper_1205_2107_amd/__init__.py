@@ -21,7 +21,7 @@ from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
            "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division",
-           "backtransform"]
+           "backtransform", "tridiagonalize"]
 
 
 def _torch():
@@ -373,6 +373,33 @@ def backtransform(V, tau, Z, stream=None):
         _lib.check(_lib.load().mrrr_backtransform(n, m, _ptr(Vt), ldv, _ptr(t), _ptr(Zd), ldz,
                                                    _stream_ptr(stream)))
     return Zd
+
+
+def tridiagonalize(A, stream=None):
+    """Stage 3 reduction T = Q^T M Q of the real symmetric M (its lower
+    triangle read), on the GPU.  A (n x n) is overwritten when it is a
+    column-major float64 device tensor; otherwise a column-major copy is
+    reduced.  Returns (d, e, tau, V): T's diagonal and off-diagonal, the
+    reflector scalars, and the reduced matrix V holding v_i[i+2:] in
+    V[i+2:, i] (the input of backtransform; its strict upper triangle is
+    workspace)."""
+    torch = _torch()
+    Ad = A if torch.is_tensor(A) else torch.as_tensor(np.asarray(A), dtype=torch.float64)
+    if Ad.dim() != 2 or Ad.shape[0] != Ad.shape[1]:
+        raise ValueError("A must be square")
+    n = Ad.shape[0]
+    dev = Ad.device if Ad.is_cuda else torch.device("cuda")
+    if not (Ad.is_cuda and Ad.dtype == torch.float64 and (Ad.numel() == 0 or
+                                                           (Ad.stride(0) == 1 and Ad.stride(1) >= max(1, n)))):
+        Ad = Ad.to(device=dev, dtype=torch.float64).t().contiguous().t()
+    d = torch.empty(n, dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 0), dtype=torch.float64, device=dev)
+    tau = torch.empty(max(n - 1, 0), dtype=torch.float64, device=dev)
+    lda = max(1, n, Ad.stride(1) if Ad.numel() > 0 else 1)
+    with torch.cuda.device(dev):
+        _lib.check(_lib.load().mrrr_tridiagonalize(n, _ptr(Ad), lda, _ptr(d), _ptr(e), _ptr(tau),
+                                                    _stream_ptr(stream)))
+    return d, e, tau, Ad
 
 
 def probe_division(a, b, stream=None):

@@ -16,8 +16,8 @@ EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_ba
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
            "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc",
-           "mrrr_probe_division", "mrrr_backtransform")
-KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform")
+           "mrrr_probe_division", "mrrr_backtransform", "mrrr_tridiagonalize")
+KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform", "tridiag")
 
 
 class MrrrRange(ctypes.Structure):
@@ -82,6 +82,8 @@ def load():
     lib.mrrr_step_noalloc.argtypes = [I64, P, P, MrrrRange, P, P, I64, P, P]
     lib.mrrr_backtransform.restype = ctypes.c_int
     lib.mrrr_backtransform.argtypes = [I64, I64, P, I64, P, P, I64, P]
+    lib.mrrr_tridiagonalize.restype = ctypes.c_int
+    lib.mrrr_tridiagonalize.argtypes = [I64, P, I64, P, P, P, P]
     lib.mrrr_probe_division.restype = ctypes.c_int
     lib.mrrr_probe_division.argtypes = [I64, P, P, P, P]
     lib.mrrr_get_limits.restype = ctypes.c_int

@@ -21,6 +21,10 @@ the "1-2-1" and "Wilkinson" matrices) plus random and prescribed-spectrum types.
                        tridiagonal reduction (input of the back-transformation):
                        v_i has a unit entry at row i + 1, zeros above, entries
                        U(-1, 1) / sqrt(n - i - 1) below; tau_i = 2 / (v_i^T v_i)
+* ``dense_symmetric``  dense symmetric M (input of the reduction to tridiagonal
+                       form): lower triangle U(-1, 1), mirrored above (numpy);
+                       ``dense_symmetric_device`` draws the same kind of matrix
+                       on a torch device with torch's seeded generator
 """
 import ctypes
 import os
@@ -181,3 +185,27 @@ def reflectors(n, seed, fill=0.0):
         V[i + 2:, i] = below
         tau[i] = 2.0 / (1.0 + float(below @ below))
     return V, tau
+
+
+def dense_symmetric(n, seed):
+    """n x n symmetric matrix, column-major: entries on and below the diagonal
+    U(-1, 1), mirrored above."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, (n, n))
+    return np.asfortranarray(np.tril(X) + np.tril(X, -1).T)
+
+
+def dense_symmetric_device(n, seed, device):
+    """(lower, full) on a torch device: ``lower`` is column-major with U(-1, 1)
+    entries everywhere (only its lower triangle defines the matrix; the strict
+    upper triangle holds unrelated values, which a reduction must not read),
+    ``full`` the symmetric matrix its lower triangle defines."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    X = torch.rand((n, n), generator=g, device=device, dtype=torch.float64)
+    X.mul_(2.0).sub_(1.0)
+    lower = X.t().contiguous().t()
+    full = torch.tril(X)
+    full += torch.tril(X, -1).t()
+    return lower, full.t().contiguous().t()

@@ -181,3 +181,19 @@ def test_backtransform_argument_checks():
     assert lib.mrrr_backtransform(4, 2, fake, 4, fake, fake, 3, None) == -7
     assert lib.mrrr_backtransform(1, 5, None, 1, None, fake, 1, None) == 0
     assert lib.mrrr_backtransform(6, 0, fake, 6, fake, None, 6, None) == 0
+
+
+def test_tridiagonalize_argument_checks():
+    """the reduction rejects bad sizes, pointers and leading dimensions on the
+    host; n = 0 returns at once"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    assert lib.mrrr_tridiagonalize(-1, fake, 1, fake, fake, fake, None) == -1
+    assert lib.mrrr_tridiagonalize((1 << 20) + 1, fake, (1 << 20) + 1, fake, fake, fake, None) == -1
+    assert lib.mrrr_tridiagonalize(4, None, 4, fake, fake, fake, None) == -2
+    assert lib.mrrr_tridiagonalize(4, fake, 3, fake, fake, fake, None) == -3
+    assert lib.mrrr_tridiagonalize(4, fake, 4, None, fake, fake, None) == -4
+    assert lib.mrrr_tridiagonalize(4, fake, 4, fake, None, fake, None) == -5
+    assert lib.mrrr_tridiagonalize(4, fake, 4, fake, fake, None, None) == -6
+    assert lib.mrrr_tridiagonalize(0, None, 1, None, None, None, None) == 0

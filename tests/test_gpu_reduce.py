@@ -1,0 +1,176 @@
+"""GPU tests of the Stage 3 reduction to tridiagonal form (mrrr_tridiagonalize:
+panels of 64 Householder reflectors, trailing updates on FP64 matrix cores)
+against the oracle's one-reflector-at-a-time reduction
+(oracle/tridiagonalize.py), and of the dense eigensolver it completes on the
+GPU: reduction, tridiagonal eigensolver, back-transformation.
+
+Tolerances.  Householder reduction is backward stable: the computed T is
+Q^T (M + E) Q for an exactly orthogonal Q with ||E|| <= c n eps ||M||.  The
+bars: M = Q T Q^T to 20 n eps ||M||_2 (Q from the GPU's reflectors, applied
+by the oracle), the eigenvalues of T to 2 n eps ||M||_2 of LAPACK's, and,
+since two backward-stable reductions of the same matrix agree to a few
+multiples of that on these well-conditioned random inputs, d, e, tau and the
+reflectors to 100 n eps ||M||_2 of the oracle's (the same bar the oracle meets
+against LAPACK's dsytrd).
+"""
+import numpy as np
+import pytest
+
+from oracle.backtransform import apply_q
+from oracle.tridiagonalize import tridiagonalize
+from paper_1205_2107_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1205_2107_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return pkg
+
+
+def tri(d, e):
+    return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+
+
+def reduce_gpu(M, A, upper=np.nan):
+    """reduce A (its strict upper triangle replaced by ``upper``) on the GPU"""
+    n = A.shape[0]
+    X = np.array(A, order="F")
+    X[np.triu_indices(n, 1)] = upper
+    d, e, tau, V = M.tridiagonalize(torch.tensor(X.T, device="cuda").t())
+    return d.cpu().numpy(), e.cpu().numpy(), tau.cpu().numpy(), V.cpu().numpy()
+
+
+# one panel, a panel plus one column, several panels with a ragged last one
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 66, 129, 200, 333])
+def test_reduction_vs_oracle(M, n):
+    A = W.dense_symmetric(n, 7000 + n)
+    d, e, tau, V = reduce_gpu(M, A)
+    d0, e0, t0, V0 = tridiagonalize(A)
+    norm = np.abs(np.linalg.eigvalsh(A)).max()
+    bar = 100 * max(n, 1) * EPS * norm
+    assert np.abs(d - d0).max() <= bar
+    if n > 1:
+        assert np.abs(e - e0).max() <= bar
+        assert np.abs(tau - t0).max() <= bar
+        assert np.array_equal(np.diag(V, -1), e)
+    assert np.array_equal(np.diag(V), d)
+    low = np.tril(np.ones((n, n), dtype=bool), -2)
+    if low.any():
+        assert np.abs(V[low] - V0[low]).max() <= bar
+    # backward error and spectrum
+    Q = apply_q(V, tau, np.eye(n))
+    assert np.abs(Q @ tri(d, e) @ Q.T - A).max() <= 20 * max(n, 1) * EPS * norm
+    assert np.abs(np.linalg.eigvalsh(tri(d, e)) - np.linalg.eigvalsh(A)).max() <= 2 * max(n, 1) * EPS * norm
+
+
+def test_repeatable_and_leading_dimension(M):
+    # two calls give the same bits; a leading dimension above n changes nothing
+    n = 150
+    A = W.dense_symmetric(n, 7301)
+    r1 = reduce_gpu(M, A)
+    r2 = reduce_gpu(M, A)
+    for a, b in zip(r1[:3], r2[:3]):
+        assert np.array_equal(a, b)
+    big = torch.full((n + 9, n), float("nan"), dtype=torch.float64, device="cuda").t().contiguous().t()
+    big[:n, :] = torch.tensor(A, device="cuda")
+    view = big[:n, :]
+    assert view.stride(1) == n + 9
+    d, e, tau, V = M.tridiagonalize(view)
+    assert V.data_ptr() == view.data_ptr()
+    for a, b in zip((d, e, tau), r1[:3]):
+        assert np.array_equal(a.cpu().numpy(), b)
+    assert torch.isnan(big[n:, :]).all()  # rows beyond n untouched
+
+
+def test_special_inputs(M):
+    rng = np.random.default_rng(7400)
+    n = 140
+    dd, ee = rng.standard_normal(n), rng.standard_normal(n - 1)
+    # a tridiagonal matrix is left as it is (every tail is zero, tau = 0)
+    d, e, tau, V = reduce_gpu(M, tri(dd, ee))
+    assert np.array_equal(d, dd) and np.array_equal(e, ee) and not tau.any()
+    d, e, tau, V = reduce_gpu(M, np.diag(dd))
+    assert np.array_equal(d, dd) and not e.any() and not tau.any()
+    # the all-ones matrix: T = [[1, -sqrt(n-1)], [-sqrt(n-1), n-1]] (+) 0
+    d, e, tau, V = reduce_gpu(M, np.ones((n, n)))
+    r = np.sqrt(n - 1.0)
+    assert abs(d[0] - 1.0) <= 8 * n * EPS and abs(d[1] - (n - 1.0)) <= 8 * n * EPS * n
+    assert abs(e[0] + r) <= 8 * n * EPS and np.abs(e[1:]).max() <= 8 * n * EPS * n
+    assert np.abs(d[2:]).max() <= 8 * n * EPS * n
+    assert abs(tau[0] - (1.0 + 1.0 / r)) <= 8 * EPS
+
+
+def test_power_of_two_scaling_is_exact(M):
+    # norms are formed after scaling by a power of two, so a matrix scaled by
+    # 2^600 or 2^-600 (whose squares over- or underflow) reduces to the same
+    # reflectors and a T scaled by the same power
+    n = 100
+    A = W.dense_symmetric(n, 7500)
+    ref = reduce_gpu(M, A)
+    for s in (2.0 ** 600, 2.0 ** -600):
+        d, e, tau, V = reduce_gpu(M, A * s)
+        assert np.array_equal(d, ref[0] * s) and np.array_equal(e, ref[1] * s)
+        assert np.array_equal(tau, ref[2])
+        low = np.tril(np.ones((n, n), dtype=bool), -2)
+        assert np.array_equal(V[low], ref[3][low])
+
+
+@pytest.mark.parametrize("n", [150, 400, 1000])
+def test_dense_eigensolver_on_gpu(M, n):
+    # reduction, tridiagonal eigensolver and back-transformation, all on the
+    # GPU: eigenpairs of the dense matrix
+    A = W.dense_symmetric(n, 7600 + n)
+    X = np.array(A, order="F")
+    X[np.triu_indices(n, 1)] = np.nan
+    d, e, tau, V = M.tridiagonalize(torch.tensor(X.T, device="cuda").t())
+    w, Z = M.eigh_tridiagonal(d, e)
+    Zn = Z.cpu().numpy()  # before the in-place back-transformation
+    Y = M.backtransform(V, tau, Z).cpu().numpy()
+    wn = w.cpu().numpy()
+    norm1 = np.abs(A).sum(axis=0).max()
+    res = np.linalg.norm(A @ Y - Y * wn[None, :], axis=0).max() / (n * EPS * norm1)
+    # orthogonality: the tridiagonal eigenvectors meet 10 n eps; the
+    # back-transformation moves each column by at most 10 n eps (its parity
+    # bar), which enters Y^T Y twice
+    orth_z = np.abs(Zn.T @ Zn - np.eye(n)).max() / (n * EPS)
+    orth = np.abs(Y.T @ Y - np.eye(n)).max() / (n * EPS)
+    print(f"n={n}: residual {res:.2f} n eps ||M||_1, orthogonality {orth:.2f} n eps (tridiagonal {orth_z:.2f})")
+    assert res <= 10.0 and orth_z <= 10.0 and orth <= orth_z + 20.0, (res, orth_z, orth)
+    assert np.abs(wn - np.linalg.eigvalsh(A)).max() <= 2 * n * EPS * norm1
+
+
+def test_full_size_invariants(M):
+    # n = 20000 (the reduction the dense pipeline runs before the order-20000
+    # tridiagonal solve): trace and Frobenius norm are invariant under Q, the
+    # spectrum is bracketed, sampled eigenpairs of the dense matrix after the
+    # eigensolver and the back-transformation
+    n = 20000
+    lower, full = W.dense_symmetric_device(n, 7700, "cuda")
+    trace = float(torch.diagonal(full).sum())
+    fro = float(torch.linalg.matrix_norm(full))
+    d, e, tau, V = M.tridiagonalize(lower)
+    assert V.data_ptr() == lower.data_ptr()
+    assert torch.isfinite(d).all() and torch.isfinite(e).all() and torch.isfinite(tau).all()
+    assert abs(float(d.sum()) - trace) <= 10 * n * EPS * fro
+    fro_t = float(torch.sqrt((d * d).sum() + 2 * (e * e).sum()))
+    assert abs(fro_t - fro) <= 10 * n * EPS * fro
+    w, Z = M.eigh_tridiagonal(d, e)
+    cols = torch.tensor([0, 1, 777, 10000, 19998, 19999], device="cuda")
+    Y = M.backtransform(V, tau, Z)
+    Ys = Y[:, cols]
+    ws = w[cols]
+    res = torch.linalg.vector_norm(full @ Ys - Ys * ws[None, :], dim=0).max()
+    norm1 = float(full.abs().sum(dim=0).max())
+    assert float(res) <= 10 * n * EPS * norm1
+    orth = float((Ys.t() @ Ys - torch.eye(len(cols), dtype=torch.float64, device="cuda")).abs().max())
+    assert orth <= 10 * n * EPS
+    del lower, full, V, Z, Y
+    torch.cuda.empty_cache()
