@@ -15,6 +15,8 @@ never touches it, and it shares no code with the GPU library.
                         reflector at a time (see ``backtransform.py``).
 * ``tridiagonalize`` -- Stage 3 reduction T = Q^T M Q, one Householder
                         reflector at a time (see ``tridiagonalize.py``).
+* ``ghep``           -- the generalized problem A x = lambda B x through all
+                        six stages (see ``ghep.py``).
 """
 import ctypes
 import os
@@ -25,6 +27,7 @@ import numpy as np
 from .adjoint import dense_adjoint  # noqa: F401
 from .backtransform import apply_q  # noqa: F401
 from .tridiagonalize import tridiagonalize  # noqa: F401
+from . import ghep  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrrr_oracle.c")

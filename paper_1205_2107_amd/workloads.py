@@ -25,6 +25,9 @@ the "1-2-1" and "Wilkinson" matrices) plus random and prescribed-spectrum types.
                        form): lower triangle U(-1, 1), mirrored above (numpy);
                        ``dense_symmetric_device`` draws the same kind of matrix
                        on a torch device with torch's seeded generator
+* ``dense_spd``        symmetric positive definite B = G G^T / n + I with G
+                       having U(-1, 1) entries (condition number about 5);
+                       ``dense_spd_device`` the same on a torch device
 """
 import ctypes
 import os
@@ -209,3 +212,28 @@ def dense_symmetric_device(n, seed, device):
     full = torch.tril(X)
     full += torch.tril(X, -1).t()
     return lower, full.t().contiguous().t()
+
+
+def dense_spd(n, seed):
+    """n x n symmetric positive definite matrix, column-major: G G^T / n + I
+    with G U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    G = rng.uniform(-1.0, 1.0, (n, n))
+    S = G @ G.T / max(n, 1) + np.eye(n)
+    return np.asfortranarray(0.5 * (S + S.T))
+
+
+def dense_spd_device(n, seed, device):
+    """the same kind of matrix as ``dense_spd`` drawn on a torch device with
+    torch's seeded generator (column-major, symmetric)"""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    G = torch.rand((n, n), generator=g, device=device, dtype=torch.float64)
+    G.mul_(2.0).sub_(1.0)
+    S = G @ G.t()
+    del G
+    S.div_(max(n, 1))
+    S.diagonal().add_(1.0)
+    S = 0.5 * (S + S.t())
+    return S.t().contiguous().t()
