@@ -289,6 +289,8 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
  *                   work = 4 n^3 / 3 flops; bytes = 8 per entry of the
  *                   trailing columns the matrix-vector products read
  *                   (sum over i of (n - i - 1)^2)
+ *   MRRR_K_GHEP     mrrr_cholesky (n^3 / 3 flops), mrrr_sygst (2 n^3) and
+ *                   mrrr_trsm_lt (n^2 m), all their launches
  * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
 #define MRRR_K_GRID 0
 #define MRRR_K_REFINE 1
@@ -298,7 +300,8 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
 #define MRRR_K_VECTORS_CKPT 5
 #define MRRR_K_BACKTRANSFORM 6
 #define MRRR_K_TRIDIAG 7
-#define MRRR_K_COUNT 8
+#define MRRR_K_GHEP 8
+#define MRRR_K_COUNT 9
 
 typedef struct {
   int64_t launches;
@@ -359,6 +362,40 @@ int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const
  * MRRR_ERR_CAPACITY when the workspace cannot be allocated; MRRR_ERR_HIP on a
  * failed launch.  Non-finite entries propagate (no status). */
 int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e, double* tau, void* stream);
+
+/* Stages 1, 2 and 6 of the generalized eigenproblem A x = lambda B x with B
+ * symmetric positive definite (Sec. 1.2, stage list): the Cholesky
+ * factorization B = L L^T, the reduction to the standard problem
+ * M y = lambda y with M = L^{-1} A L^{-T}, and the second back-transformation
+ * x = L^{-T} y.  With mrrr_tridiagonalize, mrrr_step and mrrr_backtransform
+ * in between they form the dense generalized eigensolver.  All matrices are
+ * device, column-major, blocked in 64 x 64 tiles (triangular solves with one
+ * diagonal block per lane vector, rank-64 updates on FP64 matrix cores);
+ * calls synchronize the stream before returning and are serialized by a
+ * lock per function family.  n <= 2^18.
+ *
+ * mrrr_cholesky: B (n x n, leading dimension ldb): the lower triangle holds B
+ * on entry and L on return; the strict upper triangle is not referenced.
+ * *info (host) = 0, or the 1-based column whose pivot was not positive (B
+ * not positive definite; the factorization stops there, the lower triangle
+ * holds partial results).  Returns 0; -1 (n), -2 (B null with n > 0),
+ * -3 (ldb < max(1, n)), -4 (info null); MRRR_ERR_HIP on a failed launch. */
+int mrrr_cholesky(int64_t n, double* B, int64_t ldb, int64_t* info, void* stream);
+
+/* mrrr_sygst: M = L^{-1} A L^{-T}.  A (n x n, lda): its lower triangle holds
+ * the symmetric A on entry; on return all of A holds M (symmetric up to
+ * rounding; the reduction to tridiagonal form reads its lower triangle).
+ * L (n x n, ldl): the lower triangle of the Cholesky factor, read-only.  The
+ * library keeps a grow-only workspace of n x n doubles.  Returns 0; -1 (n),
+ * -2 (A null), -3 (lda), -4 (L null), -5 (ldl); MRRR_ERR_CAPACITY when the
+ * workspace cannot be allocated; MRRR_ERR_HIP on a failed launch. */
+int mrrr_sygst(int64_t n, double* A, int64_t lda, const double* L, int64_t ldl, void* stream);
+
+/* mrrr_trsm_lt: Y <- L^{-T} Y for Y (n x m, ldy), L (n x n lower, ldl,
+ * read-only).  Returns 0; -1 (n), -2 (m < 0 or m > 2^31), -3 (L null), -4
+ * (ldl), -5 (Y null with n, m > 0), -6 (ldy); MRRR_ERR_HIP on a failed
+ * launch. */
+int mrrr_trsm_lt(int64_t n, int64_t m, const double* L, int64_t ldl, double* Y, int64_t ldy, void* stream);
 
 /* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
  * caller-given operands (no solve; for tests of their rounding).  a, b: device

@@ -21,7 +21,7 @@ from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
            "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division",
-           "backtransform", "tridiagonalize"]
+           "backtransform", "tridiagonalize", "cholesky", "sygst", "trsm_lt", "eigh_generalized"]
 
 
 def _torch():
@@ -400,6 +400,87 @@ def tridiagonalize(A, stream=None):
         _lib.check(_lib.load().mrrr_tridiagonalize(n, _ptr(Ad), lda, _ptr(d), _ptr(e), _ptr(tau),
                                                     _stream_ptr(stream)))
     return d, e, tau, Ad
+
+
+def _colmajor(X, dev, square=False):
+    """X itself when it is a column-major float64 tensor on dev, else a
+    column-major copy there"""
+    torch = _torch()
+    Xt = X if torch.is_tensor(X) else torch.as_tensor(np.asarray(X), dtype=torch.float64)
+    if Xt.dim() != 2 or (square and Xt.shape[0] != Xt.shape[1]):
+        raise ValueError("a square matrix is required" if square else "a matrix is required")
+    n = Xt.shape[0]
+    if not (Xt.is_cuda and Xt.device == dev and Xt.dtype == torch.float64 and
+            (Xt.numel() == 0 or (Xt.stride(0) == 1 and Xt.stride(1) >= max(1, n)))):
+        Xt = Xt.to(device=dev, dtype=torch.float64).t().contiguous().t()
+    return Xt
+
+
+def _ld(X):
+    return max(1, X.shape[0], X.stride(1) if X.numel() > 0 else 1)
+
+
+def _dev_of(X):
+    torch = _torch()
+    return X.device if torch.is_tensor(X) and X.is_cuda else torch.device("cuda")
+
+
+def cholesky(B, stream=None):
+    """B = L L^T on the GPU (lower triangle of B read; L written over it when
+    B is a column-major float64 device tensor, else into a copy).  Returns L
+    (its strict upper triangle is whatever B held there); raises when B is
+    not positive definite."""
+    dev = _dev_of(B)
+    Bd = _colmajor(B, dev, square=True)
+    info = ctypes.c_int64(0)
+    with _torch().cuda.device(dev):
+        _lib.check(_lib.load().mrrr_cholesky(Bd.shape[0], _ptr(Bd), _ld(Bd), ctypes.byref(info),
+                                              _stream_ptr(stream)))
+    if info.value:
+        raise ValueError(f"matrix not positive definite (pivot of column {info.value})")
+    return Bd
+
+
+def sygst(A, L, stream=None):
+    """M = L^{-1} A L^{-T} on the GPU (lower triangle of A read; M written over
+    A when it is a column-major float64 device tensor, else into a copy)."""
+    dev = _dev_of(A)
+    Ad = _colmajor(A, dev, square=True)
+    Ld = _colmajor(L, dev, square=True)
+    if Ld.shape != Ad.shape:
+        raise ValueError("A and L must have one order")
+    with _torch().cuda.device(dev):
+        _lib.check(_lib.load().mrrr_sygst(Ad.shape[0], _ptr(Ad), _ld(Ad), _ptr(Ld), _ld(Ld), _stream_ptr(stream)))
+    return Ad
+
+
+def trsm_lt(L, Y, stream=None):
+    """Y <- L^{-T} Y on the GPU (in place on a column-major float64 device
+    tensor, else on a copy); returns the result."""
+    dev = _dev_of(Y)
+    Yd = _colmajor(Y, dev)
+    Ld = _colmajor(L, dev, square=True)
+    if Ld.shape[0] != Yd.shape[0]:
+        raise ValueError("L and Y must have the same number of rows")
+    with _torch().cuda.device(dev):
+        _lib.check(_lib.load().mrrr_trsm_lt(Yd.shape[0], Yd.shape[1], _ptr(Ld), _ld(Ld), _ptr(Yd), _ld(Yd),
+                                             _stream_ptr(stream)))
+    return Yd
+
+
+def eigh_generalized(A, B, stream=None):
+    """All eigenpairs of A x = lambda B x (A symmetric, B symmetric positive
+    definite, lower triangles read), every stage on the GPU: Cholesky
+    factorization, reduction to standard form, reduction to tridiagonal form,
+    the MRRR tridiagonal eigensolver, and both back-transformations.  A and B
+    are overwritten when they are column-major float64 device tensors.
+    Returns (w ascending, X column-major with X^T B X = I)."""
+    L = cholesky(B, stream)
+    M = sygst(A, L, stream)
+    d, e, tau, V = tridiagonalize(M, stream)
+    w, Z = eigh_tridiagonal(d, e, stream=stream)
+    Y = backtransform(V, tau, Z, stream)
+    return w, trsm_lt(L, Y, stream)
 
 
 def probe_division(a, b, stream=None):

@@ -16,8 +16,9 @@ EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_ba
            "mrrr_get_tuning", "mrrr_set_tuning", "mrrr_autotune_batched", "mrrr_profile_enable", "mrrr_profile_reset",
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
            "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc",
-           "mrrr_probe_division", "mrrr_backtransform", "mrrr_tridiagonalize")
-KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform", "tridiag")
+           "mrrr_probe_division", "mrrr_backtransform", "mrrr_tridiagonalize",
+           "mrrr_cholesky", "mrrr_sygst", "mrrr_trsm_lt")
+KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform", "tridiag", "ghep")
 
 
 class MrrrRange(ctypes.Structure):
@@ -84,6 +85,12 @@ def load():
     lib.mrrr_backtransform.argtypes = [I64, I64, P, I64, P, P, I64, P]
     lib.mrrr_tridiagonalize.restype = ctypes.c_int
     lib.mrrr_tridiagonalize.argtypes = [I64, P, I64, P, P, P, P]
+    lib.mrrr_cholesky.restype = ctypes.c_int
+    lib.mrrr_cholesky.argtypes = [I64, P, I64, PI64, P]
+    lib.mrrr_sygst.restype = ctypes.c_int
+    lib.mrrr_sygst.argtypes = [I64, P, I64, P, I64, P]
+    lib.mrrr_trsm_lt.restype = ctypes.c_int
+    lib.mrrr_trsm_lt.argtypes = [I64, I64, P, I64, P, I64, P]
     lib.mrrr_probe_division.restype = ctypes.c_int
     lib.mrrr_probe_division.argtypes = [I64, P, P, P, P]
     lib.mrrr_get_limits.restype = ctypes.c_int

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrrr.so")
-SOURCES = ["mrrr_kernels.hip", "mrrr_host.hip", "mrrr_backward.hip", "mrrr_backtransform.hip", "mrrr_reduce.hip"]
+SOURCES = ["mrrr_kernels.hip", "mrrr_host.hip", "mrrr_backward.hip", "mrrr_backtransform.hip", "mrrr_reduce.hip", "mrrr_ghep.hip"]
 HEADERS = ["mrrr_dev.h", "mrrr_launch.h", "mrrr_prof.h"]
 ARCH = os.environ.get("MRRR_OFFLOAD_ARCH", "gfx950")
 

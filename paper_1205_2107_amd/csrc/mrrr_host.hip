@@ -687,7 +687,7 @@ static int solve(Workspace& W, std::vector<Problem>& probs, const double* d, con
     const double bytes[MRRR_K_COUNT] = {0.0, 0.0, 32.0 * (double)hc.child_steps, 8.0 * ze, 0.0,
                                         8.0 * (double)hc.ckpt_z_entries};
     for (int k = 0; k < MRRR_K_COUNT; ++k) {
-      if (k == MRRR_K_BACKWARD || k == MRRR_K_BACKTRANSFORM || k == MRRR_K_TRIDIAG) continue;
+      if (k == MRRR_K_BACKWARD || k == MRRR_K_BACKTRANSFORM || k == MRRR_K_TRIDIAG || k == MRRR_K_GHEP) continue;
       double ms;
       int64_t l;
       prof.total(k, &ms, &l);

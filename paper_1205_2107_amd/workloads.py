@@ -26,7 +26,7 @@ the "1-2-1" and "Wilkinson" matrices) plus random and prescribed-spectrum types.
                        ``dense_symmetric_device`` draws the same kind of matrix
                        on a torch device with torch's seeded generator
 * ``dense_spd``        symmetric positive definite B = G G^T / n + I with G
-                       having U(-1, 1) entries (condition number about 5);
+                       having U(-1, 1) entries (spectrum within [1, 7/3]);
                        ``dense_spd_device`` the same on a torch device
 """
 import ctypes

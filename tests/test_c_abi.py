@@ -197,3 +197,30 @@ def test_tridiagonalize_argument_checks():
     assert lib.mrrr_tridiagonalize(4, fake, 4, fake, None, fake, None) == -5
     assert lib.mrrr_tridiagonalize(4, fake, 4, fake, fake, None, None) == -6
     assert lib.mrrr_tridiagonalize(0, None, 1, None, None, None, None) == 0
+
+
+def test_generalized_stage_argument_checks():
+    """Cholesky, reduction to standard form and the L^T solve reject bad
+    sizes, pointers and leading dimensions on the host"""
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    info = ctypes.c_int64(7)
+    assert lib.mrrr_cholesky(-1, fake, 1, ctypes.byref(info), None) == -1
+    assert lib.mrrr_cholesky(4, None, 4, ctypes.byref(info), None) == -2
+    assert lib.mrrr_cholesky(4, fake, 3, ctypes.byref(info), None) == -3
+    assert lib.mrrr_cholesky(4, fake, 4, None, None) == -4
+    assert lib.mrrr_cholesky(0, None, 1, ctypes.byref(info), None) == 0 and info.value == 0
+    assert lib.mrrr_sygst(-1, fake, 1, fake, 1, None) == -1
+    assert lib.mrrr_sygst(4, None, 4, fake, 4, None) == -2
+    assert lib.mrrr_sygst(4, fake, 3, fake, 4, None) == -3
+    assert lib.mrrr_sygst(4, fake, 4, None, 4, None) == -4
+    assert lib.mrrr_sygst(4, fake, 4, fake, 3, None) == -5
+    assert lib.mrrr_sygst(0, None, 1, None, 1, None) == 0
+    assert lib.mrrr_trsm_lt(-1, 1, fake, 1, fake, 1, None) == -1
+    assert lib.mrrr_trsm_lt(4, -1, fake, 4, fake, 4, None) == -2
+    assert lib.mrrr_trsm_lt(4, 2, None, 4, fake, 4, None) == -3
+    assert lib.mrrr_trsm_lt(4, 2, fake, 3, fake, 4, None) == -4
+    assert lib.mrrr_trsm_lt(4, 2, fake, 4, None, 4, None) == -5
+    assert lib.mrrr_trsm_lt(4, 2, fake, 4, fake, 3, None) == -6
+    assert lib.mrrr_trsm_lt(4, 0, fake, 4, None, 4, None) == 0
