@@ -30,6 +30,9 @@ Also reported on the same JSON line:
   reduce        the Stage 3 reduction of a dense symmetric order-20000 matrix
                 to tridiagonal form (panels of 64 reflectors), against HBM
                 bandwidth for the matrix-vector products that bound it
+  ghep          the generalized eigenproblem A x = lambda B x of order 20000
+                (the paper's dense workload), every stage on the GPU, each
+                stage timed
 """
 import argparse
 import json
@@ -333,8 +336,8 @@ def reduce_leg(torch, M, n, reps=2):
     (lower triangle U(-1, 1), seeded, drawn on the device).  Each call
     overwrites its input, so every repetition reduces a fresh device copy made
     outside the timed region.  Work 4 n^3 / 3 flops; HBM bytes of the
-    matrix-vector products (one read of the trailing columns per reflector,
-    sum over i of 8 (n - i - 1)^2) bound it."""
+    matrix-vector products (one read of the trailing lower triangle per
+    reflector, sum over m = 1 .. n-1 of 8 m (m + 1) / 2) bound it."""
     from paper_1205_2107_amd import workloads as W
     lower, full = W.dense_symmetric_device(n, W.SEEDS["c2_random"], "cuda")
     del full
@@ -357,11 +360,50 @@ def reduce_leg(torch, M, n, reps=2):
     t = median(ts)
     nn = float(n)
     flops = 4.0 / 3.0 * nn ** 3
-    symv_bytes = 8.0 * (nn - 1.0) * nn * (2.0 * nn - 1.0) / 6.0
+    symv_bytes = 8.0 * (nn - 1.0) * nn * (nn + 1.0) / 6.0
     return {"n": n, "seconds": t, "gflops": flops / t / 1e9,
             "symv_bytes": symv_bytes, "symv_gbs_over_call": symv_bytes / t / 1e9,
             "frac_of_hbm_peak_over_call": symv_bytes / t / 1e9 / PEAK_HBM_GBS,
             "launches": prof[-1]["launches"] if prof else None, "reps": reps}
+
+
+def ghep_leg(torch, M, n):
+    """A x = lambda B x of order n, all eigenpairs: A symmetric (lower
+    triangle U(-1, 1)), B = G G^T / n + I, both seeded and drawn on the device.
+    Each of the six stages is timed on its own (stream synchronized around
+    it); the total is their sum.  Work of the dense stages: Cholesky n^3/3,
+    reduction to standard form 2 n^3 (two triangular solves with n right-hand
+    sides), tridiagonal reduction 4 n^3/3, first back-transformation 2 n^3,
+    second back-transformation n^3 flops."""
+    from paper_1205_2107_amd import workloads as W
+    lower, full = W.dense_symmetric_device(n, W.SEEDS["c2_random"], "cuda")
+    del full
+    B = W.dense_spd_device(n, W.SEEDS["c2_random"] + 1, "cuda")
+    torch.cuda.empty_cache()
+    t = {}
+
+    def timed(name, f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        t[name] = time.perf_counter() - t0
+        return r
+
+    L = timed("cholesky", lambda: M.cholesky(B))
+    Ms = timed("standard_form", lambda: M.sygst(lower, L))
+    d, e, tau, V = timed("tridiagonal_reduction", lambda: M.tridiagonalize(Ms))
+    w, Z = timed("tridiagonal_eigensolver", lambda: M.eigh_tridiagonal(d, e))
+    Y = timed("back_transformation_q", lambda: M.backtransform(V, tau, Z))
+    X = timed("back_transformation_l", lambda: M.trsm_lt(L, Y))
+    ok = bool(torch.isfinite(w).all()) and bool(torch.isfinite(X[:, :4]).all())
+    nn = float(n)
+    flops = {"cholesky": nn ** 3 / 3.0, "standard_form": 2.0 * nn ** 3, "tridiagonal_reduction": 4.0 * nn ** 3 / 3.0,
+             "back_transformation_q": 2.0 * nn ** 3, "back_transformation_l": nn ** 3}
+    del lower, B, L, Ms, V, Z, Y, X
+    total = sum(t.values())
+    return {"n": n, "seconds_total": total, "seconds": t, "eigenpairs_per_s": n / total,
+            "tflops": {k: flops[k] / t[k] / 1e12 for k in flops}, "finite": ok}
 
 
 def main():
@@ -375,6 +417,9 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-backtransform", action="store_true")
     ap.add_argument("--no-reduce", action="store_true")
+    ap.add_argument("--no-ghep", action="store_true")
+    ap.add_argument("--only-ghep", action="store_true",
+                    help="only the generalized-problem leg (for a profiler run); prints its JSON")
     ap.add_argument("--only-reduce", action="store_true",
                     help="only the reduction leg (for a profiler run); prints its JSON")
     ap.add_argument("--only-backtransform", action="store_true",
@@ -396,6 +441,10 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.n
+    if args.only_ghep:
+        log("[bench] generalized-problem leg only")
+        print(json.dumps({"ghep": ghep_leg(torch, M, n)}), flush=True)
+        return
     if args.only_reduce:
         log("[bench] reduction leg only")
         print(json.dumps({"reduce": reduce_leg(torch, M, n)}), flush=True)
@@ -514,6 +563,10 @@ def main():
     if not args.no_reduce:
         log("[bench] reduction leg")
         out["reduce"] = reduce_leg(torch, M, n)
+        torch.cuda.empty_cache()
+    if not args.no_ghep:
+        log("[bench] generalized-problem leg")
+        out["ghep"] = ghep_leg(torch, M, n)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -287,8 +287,8 @@ int mrrr_autotune_batched(int64_t batch, const int64_t* n_host, const int64_t* o
  *                   its K rows (about 2 n^2 m in all)
  *   MRRR_K_TRIDIAG  mrrr_tridiagonalize (all its launches as one):
  *                   work = 4 n^3 / 3 flops; bytes = 8 per entry of the
- *                   trailing columns the matrix-vector products read
- *                   (sum over i of (n - i - 1)^2)
+ *                   trailing lower triangles the matrix-vector products
+ *                   read (sum over m = 1 .. n-1 of m (m + 1) / 2)
  *   MRRR_K_GHEP     mrrr_cholesky (n^3 / 3 flops), mrrr_sygst (2 n^3) and
  *                   mrrr_trsm_lt (n^2 m), all their launches
  * mrrr_profile_read fills launches, total milliseconds, work and bytes. */
@@ -341,11 +341,10 @@ int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const
  * M, by Householder reflectors in the storage a lower reduction (LAPACK's
  * dsytrd with uplo 'L') leaves, so that mrrr_backtransform applies Q.
  *   A    device, n x n column-major (leading dimension lda).  On entry the
- *        lower triangle holds M (the strict upper triangle is not read).  On
- *        return the diagonal holds d, the first subdiagonal e, and
- *        A[(i+2..n-1) + i lda] the reflector v_i below its unit entry
- *        (v_i[0..i] = 0, v_i[i+1] = 1); the strict upper triangle is
- *        overwritten (workspace);
+ *        lower triangle holds M.  On return the diagonal holds d, the first
+ *        subdiagonal e, and A[(i+2..n-1) + i lda] the reflector v_i below its
+ *        unit entry (v_i[0..i] = 0, v_i[i+1] = 1).  The strict upper triangle
+ *        is neither read nor written;
  *   d    device, n doubles: the diagonal of T;
  *   e    device, n - 1 doubles: the off-diagonal of T (e_i = beta_i, either
  *        sign);
@@ -355,9 +354,10 @@ int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const
  * beta) below the unit entry; H = I (tau = 0, beta = alpha) when x_2.. are
  * zero.  Blocked in panels of 64 columns (trailing update on FP64 matrix
  * cores); reductions in a fixed order, so results repeat exactly.  The library
- * keeps a grow-only workspace (2 x 64 n doubles plus O(n)); calls are
+ * keeps a grow-only workspace (2 x 64 n doubles for the panel, 64 ceil(n/64)^2
+ * for the partial sums of the matrix-vector products, plus O(n)); calls are
  * serialized by a lock and synchronize the stream before returning.  Returns
- * 0; -1 (n < 0 or n > 2^20), -2 (A null with n > 0), -3 (lda < max(1, n)),
+ * 0; -1 (n < 0 or n > 2^18), -2 (A null with n > 0), -3 (lda < max(1, n)),
  * -4 (d null with n > 0), -5 (e null with n > 1), -6 (tau null with n > 1);
  * MRRR_ERR_CAPACITY when the workspace cannot be allocated; MRRR_ERR_HIP on a
  * failed launch.  Non-finite entries propagate (no status). */

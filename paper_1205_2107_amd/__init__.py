@@ -382,7 +382,7 @@ def tridiagonalize(A, stream=None):
     reduced.  Returns (d, e, tau, V): T's diagonal and off-diagonal, the
     reflector scalars, and the reduced matrix V holding v_i[i+2:] in
     V[i+2:, i] (the input of backtransform; its strict upper triangle is
-    workspace)."""
+    neither read nor written)."""
     torch = _torch()
     Ad = A if torch.is_tensor(A) else torch.as_tensor(np.asarray(A), dtype=torch.float64)
     if Ad.dim() != 2 or Ad.shape[0] != Ad.shape[1]:

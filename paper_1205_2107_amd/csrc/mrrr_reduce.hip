@@ -16,15 +16,19 @@
 //   reflector       from a[i+1:]
 //   product         y = tau (A v - V_j (W_j^T v) - W_j (V_j^T v))
 //   correction      w = y - (tau/2)(v^T y) v.
-// The product's A v reads the panel-start trailing matrix; A is kept with
-// both triangles (mirrored from the lower one at the start, the panel
-// updates write both), so (A v)[c] = A[:, c] . v reads one contiguous column
-// per output entry (k_tr_symv).  The column work is spread so that only the
-// reflector itself runs in one workgroup:
+// The product's A v reads the panel-start trailing matrix, its lower
+// triangle only, in 64 x 64 tiles: a workgroup takes up to kStrip tiles of
+// one column strip J, accumulates A_IJ^T v_I for the strip's columns over its
+// tiles and forms A_IJ v_J for each tile's rows; these partial sums go to one
+// slot per (row block, contributor), and k_tr_ysum adds each row's slots in a
+// fixed order (k_tr_symv, k_tr_ysum).  The strict upper triangle is neither
+// read nor written.  The column work is spread so that only the reflector
+// itself runs in one workgroup:
 //   k_tr_col   (one workgroup)  finishes the previous column's w (its
 //              (tau/2)(v^T y) term needs the global sum of k_tr_w's
 //              partials), the rest of the column update, the reflector;
-//   k_tr_symv  (one wavefront per two columns) A v, W_j^T v, V_j^T v;
+//   k_tr_symv  the partial sums of A v; W_j^T v and V_j^T v;
+//   k_tr_ysum  A v from the partial sums;
 //   k_tr_w     (one row per thread) w before its correction, the partial
 //              sums of v^T w, and the next column's update by every pair
 //              but the correction term.
@@ -45,8 +49,7 @@ constexpr int NBR = 64;         // panel width (reflectors per trailing update)
 constexpr int TK = 16;          // reduction step of the panel update staged in LDS
 constexpr int NT = 256;         // threads per workgroup (panel update, w, mirror)
 constexpr int NTC = 1024;       // threads of the reflector workgroup
-constexpr int kSymvWaves = 4;   // wavefronts per workgroup of the product
-constexpr int kUnroll = 4;      // row loads in flight per lane in the product
+constexpr int kStrip = 8;       // tiles of one column strip per workgroup of the product
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -151,62 +154,169 @@ __global__ void __launch_bounds__(NTC) k_tr_col(int64_t n, double* __restrict__ 
   }
 }
 
-// y[c] = A[i+1:, c] . v for c = i+1 .. n-1 (one wavefront per two columns),
-// then pq[j'] = W[:, j'] . v and pq[NBR + j'] = V[:, j'] . v for j' < j
-// (one wavefront per j'), all over rows i+1 .. n-1.
-__global__ void __launch_bounds__(64 * kSymvWaves) k_tr_symv(int64_t n, const double* __restrict__ A, int64_t lda,
-                                                             int64_t i, int j, const double* __restrict__ Vp,
-                                                             const double* __restrict__ Wp, double* __restrict__ y,
-                                                             double* __restrict__ pq) {
-  const int lane = threadIdx.x & 63;
-  const int64_t task = (int64_t)blockIdx.x * kSymvWaves + (threadIdx.x >> 6);
-  const int64_t m = n - i - 1;
-  const int64_t ncol = (m + 1) / 2;
-  if (task >= ncol + j) return;
+// group g of column strip J of the product -> linear index: the groups are
+// numbered by g, then J; group g of every strip J < Tn - g kStrip exists
+__device__ __forceinline__ int64_t strip_offset(int64_t g, int64_t Tn) { return g * Tn - kStrip * g * (g - 1) / 2; }
+__device__ __forceinline__ void strip_group(int64_t l, int64_t Tn, int64_t* g, int64_t* J) {
+  const double b = (double)Tn + 0.5 * kStrip;
+  int64_t x = (int64_t)((b - sqrt(fmax(0.0, b * b - 2.0 * kStrip * (double)l))) / kStrip);
+  x = x < 0 ? 0 : x;
+  while (x > 0 && strip_offset(x, Tn) > l) --x;
+  while (strip_offset(x + 1, Tn) <= l && (x + 1) * kStrip < Tn) ++x;
+  *g = x;
+  *J = l - strip_offset(x, Tn);
+}
+
+// Partial sums of y = A v over the trailing matrix (rows and columns
+// o = i+1 .. n-1, lower triangle), v = V[:, j].  Blocks of 64 rows are counted
+// from T0 = o / 64 (absolute alignment; rows and columns below o masked), Tn
+// of them; P holds Tn slots of 64 doubles per block:
+//   slot J < K of block K:            A_KJ v_J              (tile (K, J))
+//   slot K + g kStrip of block K:     sum over the tiles I of group g of
+//                                     strip K of A_IK^T v_I, plus for g = 0
+//                                     the strict lower part of A_KK v_K.
+// Workgroup (g, J) takes tiles I = J + g kStrip .. of strip J: thread (a, w)
+// holds row a of the tile in its 16 columns b = w + 4k, forms its share of
+// A_IJ v_J (the four wavefronts' shares added in LDS) and accumulates
+// A_IJ^T v_I over its tiles; at the end each wavefront reduces its 16 column
+// sums across its lanes (halving exchanges).  The next tile is fetched while
+// the current one is used.  Workgroups past ntask form pq[j'] = W[:, j'] . v
+// and pq[NBR + j'] = V[:, j'] . v, j' < j.
+__global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restrict__ A, int64_t lda, int64_t i,
+                                                int j, const double* __restrict__ Vp, const double* __restrict__ Wp,
+                                                double* __restrict__ P, double* __restrict__ pq, int64_t ntask) {
+  __shared__ double vJs[NBR];
+  __shared__ double rs[NT / 64][NBR];
+  __shared__ double us[NBR];
+  __shared__ double sh[NT / 64];
+  const int t = threadIdx.x, lane = t & 63, part = t >> 6;
+  const int64_t o = i + 1;
+  const int64_t T0 = o >> 6, Tn = ((n + 63) >> 6) - T0;
   const double* v = Vp + (int64_t)j * n;
-  const double *c0, *c1;
-  bool two = true;
-  if (task < ncol) {
-    const int64_t c = i + 1 + 2 * task;
-    c0 = A + c * lda;
-    two = c + 1 < n;
-    c1 = two ? c0 + lda : c0;
-  } else {
-    const int jj = (int)(task - ncol);
-    c0 = Wp + (int64_t)jj * n;
-    c1 = Vp + (int64_t)jj * n;
+  if ((int64_t)blockIdx.x >= ntask) {
+    const int jj = (int)(blockIdx.x - ntask);
+    const double* w = Wp + (int64_t)jj * n;
+    const double* u = Vp + (int64_t)jj * n;
+    double sp = 0.0, sq = 0.0;
+    for (int64_t r = o + t; r < n; r += NT) {
+      const double vr = v[r];
+      sp = fma(w[r], vr, sp);
+      sq = fma(u[r], vr, sq);
+    }
+    sp = block_reduce<false>(sp, sh);
+    sq = block_reduce<false>(sq, sh);
+    if (t == 0) {
+      pq[jj] = sp;
+      pq[NBR + jj] = sq;
+    }
+    return;
   }
-  // rows from i+1, loads aligned to 64-row groups
-  const int64_t r0 = (i + 1) & ~(int64_t)63;
+  int64_t g, Jr;
+  strip_group(blockIdx.x, Tn, &g, &Jr);
+  const int64_t Ib = Jr + g * kStrip, Ie = std::min<int64_t>(Tn, Ib + kStrip);
+  const int64_t cJ = (T0 + Jr) * NBR;
+  if (t < NBR) {
+    const int64_t c = cJ + t;
+    vJs[t] = (c >= o && c < n) ? v[c] : 0.0;
+  }
+  __syncthreads();
+  double vj[16], u[16], cur[16], nxt[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    vj[k] = vJs[part + 4 * k];
+    u[k] = 0.0;
+  }
+  auto fetch = [&](int64_t I, double* dst) {
+    const int64_t r = (T0 + I) * NBR + lane;
+    const bool rin = r >= o && r < n;
+    const bool diag = I == Jr;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int b = part + 4 * k;
+      const int64_t c = cJ + b;
+      const bool in = rin && c >= o && c < n && (!diag || lane >= b);
+      dst[k] = in ? A[c * lda + r] : 0.0;
+    }
+  };
+  fetch(Ib, nxt);
+  double xdiag = 0.0;
+  for (int64_t I = Ib; I < Ie; ++I) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+    if (I + 1 < Ie) fetch(I + 1, nxt);
+    const int64_t r = (T0 + I) * NBR + lane;
+    const double vi = (r >= o && r < n) ? v[r] : 0.0;
+    const bool diag = I == Jr;
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int b = part + 4 * k;
+      const double a = (diag && b == lane) ? 0.0 : cur[k];  // the row sums take the strict lower part
+      x = fma(a, vj[k], x);
+      u[k] = fma(cur[k], vi, u[k]);
+    }
+    rs[part][lane] = x;
+    __syncthreads();
+    if (t < NBR) {
+      const double xs = (rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t]);
+      if (diag)
+        xdiag = xs;
+      else
+        P[(I * Tn + Jr) * NBR + t] = xs;
+    }
+    __syncthreads();
+  }
+  // column sums: halving exchanges leave lane l with column k(l) = 8 b5 + 4 b4
+  // + 2 b3 + b2 (bits of l) summed over the lanes that share those bits, then
+  // two exchanges complete it
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int off = 32 >> step, half = 8 >> step;
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < half) {
+        const double lo = u[k], hi = u[k + half];
+        const double send = up ? lo : hi;
+        const double keep = up ? hi : lo;
+        u[k] = keep + __shfl_xor(send, off, 64);
+      }
+    }
+  }
+  double cs = u[0];
+  cs += __shfl_xor(cs, 2, 64);
+  cs += __shfl_xor(cs, 1, 64);
+  if ((lane & 3) == 0) {
+    const int k = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+    us[part + 4 * k] = cs;
+  }
+  __syncthreads();
+  if (t < NBR) P[(Jr * Tn + Ib) * NBR + t] = (g == 0) ? us[t] + xdiag : us[t];
+}
+
+// y[r] = (A v)[r] for rows o .. n-1: block K's slots added in a fixed order
+// (each of the four wavefronts a quarter of them, then the four in order)
+__global__ void __launch_bounds__(NT) k_tr_ysum(int64_t n, int64_t i, const double* __restrict__ P,
+                                                double* __restrict__ y) {
+  __shared__ double rs[NT / 64][NBR];
+  const int t = threadIdx.x, a = t & 63, part = t >> 6;
+  const int64_t o = i + 1;
+  const int64_t T0 = o >> 6, Tn = ((n + 63) >> 6) - T0;
+  const int64_t K = blockIdx.x;
+  const double* p = P + (K * Tn) * NBR + a;
   double s0 = 0.0, s1 = 0.0;
-  for (int64_t rb = r0; rb < n; rb += 64 * kUnroll) {
-    double a0[kUnroll], a1[kUnroll], vv[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t rr = rb + 64 * u + lane;
-      const bool in = rr > i && rr < n;
-      vv[u] = in ? v[rr] : 0.0;
-      a0[u] = in ? c0[rr] : 0.0;
-      a1[u] = in ? c1[rr] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      s0 = fma(a0[u], vv[u], s0);
-      s1 = fma(a1[u], vv[u], s1);
-    }
+  int64_t s = part;
+  for (; s + 4 < K; s += 8) {
+    s0 += p[s * NBR];
+    s1 += p[(s + 4) * NBR];
   }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  if (lane == 0) {
-    if (task < ncol) {
-      const int64_t c = i + 1 + 2 * task;
-      y[c] = s0;
-      if (two) y[c + 1] = s1;
-    } else {
-      const int jj = (int)(task - ncol);
-      pq[jj] = s0;
-      pq[NBR + jj] = s1;
-    }
+  for (; s < K; s += 4) s0 += p[s * NBR];
+  for (int64_t gg = part; K + gg * kStrip < Tn; gg += 4) s1 += p[(K + gg * kStrip) * NBR];
+  rs[part][a] = s0 + s1;
+  __syncthreads();
+  if (t < NBR) {
+    const int64_t r = (T0 + K) * NBR + t;
+    if (r >= o && r < n) y[r] = (rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t]);
   }
 }
 
@@ -290,27 +400,19 @@ __device__ __forceinline__ void lower_tile(int64_t tl, int64_t* I, int64_t* J) {
   *J = tl - a * (a + 1) / 2;
 }
 
-// writes the tile L (L[b][a] = entry (a, b) of block (I, J), padded) to block
-// (I, J) and its transpose to block (J, I); a diagonal block takes its lower
-// triangle mirrored.  Rows and columns at or beyond mt (the trailing order)
-// are skipped.
-__device__ void store_sym_tile(double* __restrict__ A, int64_t lda, int64_t o, int64_t mt, int64_t I, int64_t J,
-                               const double (*L)[NBR + 1]) {
+// writes the lower part of tile L (L[b][a] = entry (a, b) of block (I, J),
+// padded) to block (I, J): all of it below the diagonal blocks, the lower
+// triangle of a diagonal block.  Rows and columns at or beyond mt (the
+// trailing order) are skipped.
+__device__ void store_lower_tile(double* __restrict__ A, int64_t lda, int64_t o, int64_t mt, int64_t I, int64_t J,
+                                 const double (*L)[NBR + 1]) {
   const int t = threadIdx.x;
   const int64_t oi = o + I * NBR, oj = o + J * NBR;
   const int64_t ri = std::min<int64_t>(NBR, mt - I * NBR), rj = std::min<int64_t>(NBR, mt - J * NBR);
   for (int e = t; e < NBR * NBR; e += NT) {
     const int a = e & (NBR - 1), b = e >> 6;
-    if (a < ri && b < rj) {
-      const double x = (I != J || a >= b) ? L[b][a] : L[a][b];
-      A[(oj + b) * lda + oi + a] = x;
-    }
+    if (a < ri && b < rj && (I != J || a >= b)) A[(oj + b) * lda + oi + a] = L[b][a];
   }
-  if (I != J)
-    for (int e = t; e < NBR * NBR; e += NT) {
-      const int b = e & (NBR - 1), a = e >> 6;  // entry (b, a) of block (J, I)
-      if (a < ri && b < rj) A[(oi + a) * lda + oj + b] = L[b][a];
-    }
 }
 
 __device__ void load_tile(const double* __restrict__ A, int64_t lda, int64_t o, int64_t mt, int64_t I, int64_t J,
@@ -322,16 +424,6 @@ __device__ void load_tile(const double* __restrict__ A, int64_t lda, int64_t o, 
     const int a = e & (NBR - 1), b = e >> 6;
     L[b][a] = (a < ri && b < rj) ? A[(oj + b) * lda + oi + a] : 0.0;
   }
-}
-
-// upper triangle <- lower triangle, one lower tile per workgroup
-__global__ void __launch_bounds__(NT) k_tr_mirror(int64_t n, double* __restrict__ A, int64_t lda) {
-  __shared__ double L[NBR][NBR + 1];
-  int64_t I, J;
-  lower_tile(blockIdx.x, &I, &J);
-  load_tile(A, lda, 0, n, I, J, L);
-  __syncthreads();
-  store_sym_tile(A, lda, 0, n, I, J, L);
 }
 
 // One 64 x 64 x 16 step: P[a][k], Q[b][k] in LDS; each wave accumulates a
@@ -414,7 +506,7 @@ __global__ void __launch_bounds__(NT) k_tr_syr2k(int64_t n, double* __restrict__
 #pragma unroll
       for (int v = 0; v < 4; ++v) L[acc_col(wc, q, lane)][acc_row(wr, m, lane, v)] -= acc[m][q][v];
   __syncthreads();
-  store_sym_tile(A, lda, o, mt, I, J, L);
+  store_lower_tile(A, lda, o, mt, I, J, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,7 +552,7 @@ using namespace mrrr_tr;
 extern "C" {
 
 int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e, double* tau, void* stream) {
-  if (n < 0 || n > (int64_t)1 << 20) return -1;
+  if (n < 0 || n > (int64_t)1 << 18) return -1;
   if (n > 0 && !A) return -2;
   if (lda < std::max<int64_t>(1, n)) return -3;
   if (n > 0 && !d) return -4;
@@ -470,26 +562,25 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
   const int64_t nS_max = (n + NT - 1) / NT;
+  const int64_t nb_max = (n + NBR - 1) / NBR;  // row blocks of the product's partial sums
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t pbytes = al(sizeof(double) * (size_t)(n * NBR));
   const size_t ybytes = al(sizeof(double) * (size_t)n);
+  const size_t Pbytes = al(sizeof(double) * (size_t)(nb_max * nb_max * NBR));
   const size_t qbytes = al(sizeof(double) * 2 * NBR);
   const size_t sbytes = al(sizeof(double) * (size_t)nS_max);
-  int rc = grow(2 * pbytes + ybytes + qbytes + sbytes);
+  int rc = grow(2 * pbytes + ybytes + Pbytes + qbytes + sbytes);
   if (rc) return rc;
   char* base = (char*)g_ws;
   double* Vp = (double*)base;
   double* Wp = (double*)(base + pbytes);
   double* y = (double*)(base + 2 * pbytes);
-  double* pq = (double*)(base + 2 * pbytes + ybytes);
-  double* S = (double*)(base + 2 * pbytes + ybytes + qbytes);
+  double* Py = (double*)(base + 2 * pbytes + ybytes);
+  double* pq = (double*)(base + 2 * pbytes + ybytes + Pbytes);
+  double* S = (double*)(base + 2 * pbytes + ybytes + Pbytes + qbytes);
   mrrr::ProfEvents prof(st);
   prof.begin(MRRR_K_TRIDIAG);
   int64_t launches = 0;
-  if (n > 1) {
-    hipLaunchKernelGGL(k_tr_mirror, dim3(lower_tiles(n)), dim3(NT), 0, st, n, A, lda);
-    ++launches;
-  }
   int nS = 0;
   for (int64_t k = 0; k < n - 1; k += NBR) {
     const int pw = (int)std::min<int64_t>(NBR, n - 1 - k);
@@ -498,14 +589,17 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
       hipLaunchKernelGGL(k_tr_col, dim3(1), dim3(NTC), 0, st, n, A, lda, i, j, Vp, Wp, (const double*)S, nS, d, e,
                          tau, 0);
       const int64_t m = n - i - 1;
-      const int64_t tasks = (m + 1) / 2 + j;
-      hipLaunchKernelGGL(k_tr_symv, dim3((unsigned)((tasks + kSymvWaves - 1) / kSymvWaves)), dim3(64 * kSymvWaves),
-                         0, st, n, (const double*)A, lda, i, j, (const double*)Vp, (const double*)Wp, y, pq);
+      const int64_t T0 = (i + 1) / NBR, Tn = (n + NBR - 1) / NBR - T0;
+      const int64_t G = (Tn + kStrip - 1) / kStrip;
+      const int64_t ntask = G * Tn - (int64_t)kStrip * G * (G - 1) / 2;
+      hipLaunchKernelGGL(k_tr_symv, dim3((unsigned)(ntask + j)), dim3(NT), 0, st, n, (const double*)A, lda, i, j,
+                         (const double*)Vp, (const double*)Wp, Py, pq, ntask);
+      hipLaunchKernelGGL(k_tr_ysum, dim3((unsigned)Tn), dim3(NT), 0, st, n, i, (const double*)Py, y);
       nS = (int)((m + NT - 1) / NT);
       const int next = (j + 1 < pw) || (i + 1 == n - 1);
       hipLaunchKernelGGL(k_tr_w, dim3((unsigned)nS), dim3(NT), 0, st, n, A, lda, i, j, Vp, Wp, (const double*)y,
                          (const double*)pq, (const double*)tau, S, next);
-      launches += 3;
+      launches += 4;
     }
     if (k + pw == n - 1) {
       // the last column: its update by the final panel, then d
@@ -538,11 +632,11 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
     double ms;
     int64_t l;
     prof.total(MRRR_K_TRIDIAG, &ms, &l);
-    // 4/3 n^3 flops; bytes: the product's reads of the trailing columns,
-    // sum over i of (n - i - 1)^2 entries
+    // 4/3 n^3 flops; bytes: the product's reads of the trailing lower
+    // triangles, sum over m = 1 .. n-1 of m (m + 1) / 2 entries
     const double nn = (double)n;
     const double work = 4.0 / 3.0 * nn * nn * nn;
-    const double bytes = 8.0 * (nn - 1.0) * nn * (2.0 * nn - 1.0) / 6.0;
+    const double bytes = 8.0 * (nn - 1.0) * nn * (nn + 1.0) / 6.0;
     mrrr::prof_add(MRRR_K_TRIDIAG, launches, ms, work, bytes);
   }
   return 0;

@@ -190,7 +190,7 @@ def test_tridiagonalize_argument_checks():
     lib = _lib.load()
     fake = ctypes.c_void_p(16)
     assert lib.mrrr_tridiagonalize(-1, fake, 1, fake, fake, fake, None) == -1
-    assert lib.mrrr_tridiagonalize((1 << 20) + 1, fake, (1 << 20) + 1, fake, fake, fake, None) == -1
+    assert lib.mrrr_tridiagonalize((1 << 18) + 1, fake, (1 << 18) + 1, fake, fake, fake, None) == -1
     assert lib.mrrr_tridiagonalize(4, None, 4, fake, fake, fake, None) == -2
     assert lib.mrrr_tridiagonalize(4, fake, 3, fake, fake, fake, None) == -3
     assert lib.mrrr_tridiagonalize(4, fake, 4, None, fake, fake, None) == -4

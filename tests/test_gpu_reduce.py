@@ -65,6 +65,7 @@ def test_reduction_vs_oracle(M, n):
     low = np.tril(np.ones((n, n), dtype=bool), -2)
     if low.any():
         assert np.abs(V[low] - V0[low]).max() <= bar
+    assert np.isnan(V[np.triu_indices(n, 1)]).all()  # strict upper triangle untouched
     # backward error and spectrum
     Q = apply_q(V, tau, np.eye(n))
     assert np.abs(Q @ tri(d, e) @ Q.T - A).max() <= 20 * max(n, 1) * EPS * norm
