@@ -50,6 +50,8 @@ constexpr int TK = 16;          // reduction step of the panel update staged in 
 constexpr int NT = 256;         // threads per workgroup (panel update, w, mirror)
 constexpr int NTC = 1024;       // threads of the reflector workgroup
 constexpr int kStrip = 8;       // tiles of one column strip per workgroup of the product
+constexpr int kSW = 8;          // wavefronts per workgroup of the product
+constexpr int kCPT = NBR / kSW; // tile columns per thread in the product
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -182,13 +184,13 @@ __device__ __forceinline__ void strip_group(int64_t l, int64_t Tn, int64_t* g, i
 // sums across its lanes (halving exchanges).  The next tile is fetched while
 // the current one is used.  Workgroups past ntask form pq[j'] = W[:, j'] . v
 // and pq[NBR + j'] = V[:, j'] . v, j' < j.
-__global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restrict__ A, int64_t lda, int64_t i,
+__global__ void __launch_bounds__(64 * kSW) k_tr_symv(int64_t n, const double* __restrict__ A, int64_t lda, int64_t i,
                                                 int j, const double* __restrict__ Vp, const double* __restrict__ Wp,
                                                 double* __restrict__ P, double* __restrict__ pq, int64_t ntask) {
   __shared__ double vJs[NBR];
-  __shared__ double rs[NT / 64][NBR];
+  __shared__ double rs[kSW][NBR];
   __shared__ double us[NBR];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[kSW];
   const int t = threadIdx.x, lane = t & 63, part = t >> 6;
   const int64_t o = i + 1;
   const int64_t T0 = o >> 6, Tn = ((n + 63) >> 6) - T0;
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     const double* w = Wp + (int64_t)jj * n;
     const double* u = Vp + (int64_t)jj * n;
     double sp = 0.0, sq = 0.0;
-    for (int64_t r = o + t; r < n; r += NT) {
+    for (int64_t r = o + t; r < n; r += 64 * kSW) {
       const double vr = v[r];
       sp = fma(w[r], vr, sp);
       sq = fma(u[r], vr, sq);
@@ -220,10 +222,10 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     vJs[t] = (c >= o && c < n) ? v[c] : 0.0;
   }
   __syncthreads();
-  double vj[16], u[16], cur[16], nxt[16];
+  double vj[kCPT], u[kCPT], cur[kCPT], nxt[kCPT];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    vj[k] = vJs[part + 4 * k];
+  for (int k = 0; k < kCPT; ++k) {
+    vj[k] = vJs[part + kSW * k];
     u[k] = 0.0;
   }
   auto fetch = [&](int64_t I, double* dst) {
@@ -231,8 +233,8 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     const bool rin = r >= o && r < n;
     const bool diag = I == Jr;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int b = part + 4 * k;
+    for (int k = 0; k < kCPT; ++k) {
+      const int b = part + kSW * k;
       const int64_t c = cJ + b;
       const bool in = rin && c >= o && c < n && (!diag || lane >= b);
       dst[k] = in ? A[c * lda + r] : 0.0;
@@ -242,15 +244,15 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
   double xdiag = 0.0;
   for (int64_t I = Ib; I < Ie; ++I) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+    for (int k = 0; k < kCPT; ++k) cur[k] = nxt[k];
     if (I + 1 < Ie) fetch(I + 1, nxt);
     const int64_t r = (T0 + I) * NBR + lane;
     const double vi = (r >= o && r < n) ? v[r] : 0.0;
     const bool diag = I == Jr;
     double x = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int b = part + 4 * k;
+    for (int k = 0; k < kCPT; ++k) {
+      const int b = part + kSW * k;
       const double a = (diag && b == lane) ? 0.0 : cur[k];  // the row sums take the strict lower part
       x = fma(a, vj[k], x);
       u[k] = fma(cur[k], vi, u[k]);
@@ -258,7 +260,9 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     rs[part][lane] = x;
     __syncthreads();
     if (t < NBR) {
-      const double xs = (rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t]);
+      double xs = rs[0][t];
+#pragma unroll
+      for (int w = 1; w < kSW; ++w) xs += rs[w][t];
       if (diag)
         xdiag = xs;
       else
@@ -266,15 +270,17 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     }
     __syncthreads();
   }
-  // column sums: halving exchanges leave lane l with column k(l) = 8 b5 + 4 b4
-  // + 2 b3 + b2 (bits of l) summed over the lanes that share those bits, then
-  // two exchanges complete it
+  // column sums: log2(kCPT) halving exchanges leave lane l with column index
+  // k(l) (the top bits of l) summed over the lanes that differ in those
+  // bits; exchanges over the remaining bits complete it
+  constexpr int kSteps = kCPT == 16 ? 4 : (kCPT == 8 ? 3 : (kCPT == 4 ? 2 : (kCPT == 2 ? 1 : 0)));
+  static_assert((1 << kSteps) == kCPT, "columns per thread must be a power of two up to 16");
 #pragma unroll
-  for (int step = 0; step < 4; ++step) {
-    const int off = 32 >> step, half = 8 >> step;
+  for (int step = 0; step < kSteps; ++step) {
+    const int off = 32 >> step, half = (kCPT / 2) >> step;
     const bool up = (lane & off) != 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < kCPT / 2; ++k) {
       if (k < half) {
         const double lo = u[k], hi = u[k + half];
         const double send = up ? lo : hi;
@@ -284,11 +290,13 @@ __global__ void __launch_bounds__(NT) k_tr_symv(int64_t n, const double* __restr
     }
   }
   double cs = u[0];
-  cs += __shfl_xor(cs, 2, 64);
-  cs += __shfl_xor(cs, 1, 64);
-  if ((lane & 3) == 0) {
-    const int k = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
-    us[part + 4 * k] = cs;
+#pragma unroll
+  for (int off = 32 >> kSteps; off >= 1; off >>= 1) cs += __shfl_xor(cs, off, 64);
+  if ((lane & ((32 >> kSteps) * 2 - 1)) == 0) {
+    int k = 0;
+#pragma unroll
+    for (int step = 0; step < kSteps; ++step) k = 2 * k + ((lane >> (5 - step)) & 1);
+    us[part + kSW * k] = cs;
   }
   __syncthreads();
   if (t < NBR) P[(Jr * Tn + Ib) * NBR + t] = (g == 0) ? us[t] + xdiag : us[t];
@@ -592,7 +600,7 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
       const int64_t T0 = (i + 1) / NBR, Tn = (n + NBR - 1) / NBR - T0;
       const int64_t G = (Tn + kStrip - 1) / kStrip;
       const int64_t ntask = G * Tn - (int64_t)kStrip * G * (G - 1) / 2;
-      hipLaunchKernelGGL(k_tr_symv, dim3((unsigned)(ntask + j)), dim3(NT), 0, st, n, (const double*)A, lda, i, j,
+      hipLaunchKernelGGL(k_tr_symv, dim3((unsigned)(ntask + j)), dim3(64 * kSW), 0, st, n, (const double*)A, lda, i, j,
                          (const double*)Vp, (const double*)Wp, Py, pq, ntask);
       hipLaunchKernelGGL(k_tr_ysum, dim3((unsigned)Tn), dim3(NT), 0, st, n, i, (const double*)Py, y);
       nS = (int)((m + NT - 1) / NT);
