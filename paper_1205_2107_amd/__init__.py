@@ -402,7 +402,7 @@ def tridiagonalize(A, stream=None):
     return d, e, tau, Ad
 
 
-def _colmajor(X, dev, square=False):
+def _dense_colmajor(X, dev, square=False):
     """X itself when it is a column-major float64 tensor on dev, else a
     column-major copy there"""
     torch = _torch()
@@ -431,7 +431,7 @@ def cholesky(B, stream=None):
     (its strict upper triangle is whatever B held there); raises when B is
     not positive definite."""
     dev = _dev_of(B)
-    Bd = _colmajor(B, dev, square=True)
+    Bd = _dense_colmajor(B, dev, square=True)
     info = ctypes.c_int64(0)
     with _torch().cuda.device(dev):
         _lib.check(_lib.load().mrrr_cholesky(Bd.shape[0], _ptr(Bd), _ld(Bd), ctypes.byref(info),
@@ -445,8 +445,8 @@ def sygst(A, L, stream=None):
     """M = L^{-1} A L^{-T} on the GPU (lower triangle of A read; M written over
     A when it is a column-major float64 device tensor, else into a copy)."""
     dev = _dev_of(A)
-    Ad = _colmajor(A, dev, square=True)
-    Ld = _colmajor(L, dev, square=True)
+    Ad = _dense_colmajor(A, dev, square=True)
+    Ld = _dense_colmajor(L, dev, square=True)
     if Ld.shape != Ad.shape:
         raise ValueError("A and L must have one order")
     with _torch().cuda.device(dev):
@@ -458,8 +458,8 @@ def trsm_lt(L, Y, stream=None):
     """Y <- L^{-T} Y on the GPU (in place on a column-major float64 device
     tensor, else on a copy); returns the result."""
     dev = _dev_of(Y)
-    Yd = _colmajor(Y, dev)
-    Ld = _colmajor(L, dev, square=True)
+    Yd = _dense_colmajor(Y, dev)
+    Ld = _dense_colmajor(L, dev, square=True)
     if Ld.shape[0] != Yd.shape[0]:
         raise ValueError("L and Y must have the same number of rows")
     with _torch().cuda.device(dev):

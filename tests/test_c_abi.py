@@ -224,3 +224,13 @@ def test_generalized_stage_argument_checks():
     assert lib.mrrr_trsm_lt(4, 2, fake, 4, None, 4, None) == -5
     assert lib.mrrr_trsm_lt(4, 2, fake, 4, fake, 3, None) == -6
     assert lib.mrrr_trsm_lt(4, 0, fake, 4, None, 4, None) == 0
+
+
+def test_binding_helpers_are_not_shadowed():
+    """every module-level name of the binding is defined once (a later
+    definition would silently replace an earlier helper)"""
+    import ast
+    src = open(os.path.join(ROOT, "paper_1205_2107_amd", "__init__.py")).read()
+    names = [n.name for n in ast.parse(src).body if isinstance(n, (ast.FunctionDef, ast.ClassDef))]
+    dup = sorted({x for x in names if names.count(x) > 1})
+    assert not dup, dup
