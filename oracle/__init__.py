@@ -17,6 +17,9 @@ never touches it, and it shares no code with the GPU library.
                         reflector at a time (see ``tridiagonalize.py``).
 * ``ghep``           -- the generalized problem A x = lambda B x through all
                         six stages (see ``ghep.py``).
+* ``mrrr_fp32``      -- FP32 data solved in FP64 (the mixed-precision use of
+                        Sec. 2.3): the inputs widened exactly, ``mrrr``, the
+                        results rounded to FP32.
 """
 import ctypes
 import os
@@ -110,6 +113,15 @@ def mrrr(d, e, kind=RANGE_ALL, il=0, iu=0, vl=0.0, vu=0.0, vectors=True, return_
     if return_stats:
         out = out + (dict(zip(STAT_NAMES, list(stats))),)
     return out
+
+
+def mrrr_fp32(d, e, **kw):
+    """(w, Z, status) of the FP32 tridiagonal (d, e): widened exactly to FP64,
+    solved by ``mrrr``, w and Z rounded to FP32."""
+    d64 = np.asarray(d, dtype=np.float32).astype(np.float64)
+    e64 = np.asarray(e, dtype=np.float32).astype(np.float64)
+    w, Z, st = mrrr(d64, e64, **kw)[:3]
+    return w.astype(np.float32), (None if Z is None else Z.astype(np.float32)), st
 
 
 def bisect_T(d, e, j):
