@@ -30,6 +30,9 @@ Also reported on the same JSON line:
   reduce        the Stage 3 reduction of a dense symmetric order-20000 matrix
                 to tridiagonal form (panels of 64 reflectors), against HBM
                 bandwidth for the matrix-vector products that bound it
+  fp32          the three order-20000 matrices rounded to FP32 through the FP32
+                interface (FP64 inside, relaxed classification threshold),
+                against the FP64 calls on the same data
   ghep          the generalized eigenproblem A x = lambda B x of order 20000
                 (the paper's dense workload), every stage on the GPU, each
                 stage timed
@@ -367,6 +370,38 @@ def reduce_leg(torch, M, n, reps=2):
             "launches": prof[-1]["launches"] if prof else None, "reps": reps}
 
 
+def fp32_leg(torch, M, n, reps=3):
+    """The bench matrices rounded to FP32 (so both interfaces solve the same
+    tridiagonal): median call time of mrrr_step_f32 and of mrrr_step on the
+    widened data, and the representation-tree sizes of both."""
+    import numpy as np
+    from paper_1205_2107_amd import workloads as W
+    out = {}
+    for kind, (d, e) in (("random", W.random_uniform(n, W.SEEDS["c2_random"])), ("toeplitz_121", W.toeplitz(n)),
+                         ("geometric_1e-8", W.geometric(n, W.SEEDS["c2_geometric"]))):
+        d32 = torch.tensor(np.asarray(d, dtype=np.float32), device="cuda")
+        e32 = torch.tensor(np.asarray(e, dtype=np.float32), device="cuda")
+        d64, e64 = d32.double(), e32.double()
+        row = {}
+        for name, call in (("fp32", lambda: M.eigh_tridiagonal_f32(d32, e32, return_info=True)),
+                           ("fp64", lambda: M.eigh_tridiagonal(d64, e64, return_info=True))):
+            w, Z, info = call()
+            del w, Z
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                w, Z, info = call()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                del w, Z
+            row[name + "_ms"] = median(ts) * 1e3
+            row[name + "_nodes"] = info["nodes"]
+        out[kind] = row
+        torch.cuda.empty_cache()
+    return out
+
+
 def ghep_leg(torch, M, n):
     """A x = lambda B x of order n, all eigenpairs: A symmetric (lower
     triangle U(-1, 1)), B = G G^T / n + I, both seeded and drawn on the device.
@@ -418,6 +453,8 @@ def main():
     ap.add_argument("--no-backtransform", action="store_true")
     ap.add_argument("--no-reduce", action="store_true")
     ap.add_argument("--no-ghep", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--only-fp32", action="store_true", help="only the FP32-interface leg; prints its JSON")
     ap.add_argument("--only-ghep", action="store_true",
                     help="only the generalized-problem leg (for a profiler run); prints its JSON")
     ap.add_argument("--only-reduce", action="store_true",
@@ -441,6 +478,10 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.n
+    if args.only_fp32:
+        log("[bench] FP32-interface leg only")
+        print(json.dumps({"fp32": fp32_leg(torch, M, n)}), flush=True)
+        return
     if args.only_ghep:
         log("[bench] generalized-problem leg only")
         print(json.dumps({"ghep": ghep_leg(torch, M, n)}), flush=True)
@@ -563,6 +604,10 @@ def main():
     if not args.no_reduce:
         log("[bench] reduction leg")
         out["reduce"] = reduce_leg(torch, M, n)
+        torch.cuda.empty_cache()
+    if not args.no_fp32:
+        log("[bench] FP32-interface leg")
+        out["fp32"] = fp32_leg(torch, M, n)
         torch.cuda.empty_cache()
     if not args.no_ghep:
         log("[bench] generalized-problem leg")

@@ -314,6 +314,22 @@ int mrrr_profile_enable(int on);
 int mrrr_profile_reset(void);
 int mrrr_profile_read(int kernel, mrrr_kernel_time* out); /* -1 on a bad kernel id */
 
+/* mrrr_step_f32 -- the FP32 interface with FP64 arithmetic inside (the
+ * mixed-precision use the paper names for orthogonality-sensitive work,
+ * Sec. 2.3): d, e, w, Z are FP32 device arrays, laid out as for mrrr_step;
+ * the library widens d and e, runs the FP64 solver with the relative-gap
+ * threshold of the classification lowered from 1e-3 to min(1e-3, n 2^-27)
+ * (FP64 arithmetic leaves room for that: eigenvectors of singletons that
+ * close still lean towards their neighbours by less than eps32 / 4, and the
+ * representation tree has fewer clusters), and rounds w and Z to FP32.
+ * Orthogonality and residuals are then set by that rounding, O(eps32)
+ * rather than O(n eps32).  The library keeps a grow-only FP64 staging
+ * buffer (3 n + n m doubles, m the wanted pairs; n columns for VALUE ranges);
+ * calls are serialized and synchronize the stream.  Arguments, range, info
+ * and returns as for mrrr_step. */
+int mrrr_step_f32(int64_t n, const float* d, const float* e, mrrr_range range, float* w, float* Z, int64_t ldz,
+                  mrrr_info* info, void* stream);
+
 /* Stage 5 back-transformation (Sec. 1.2, stage 5: the eigenvectors of the
  * dense symmetric M are Y = Q Z after a lower tridiagonal reduction
  * T = Q^T M Q), on FP64 matrix cores.  Q = H_0 H_1 ... H_{n-2},

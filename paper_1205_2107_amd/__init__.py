@@ -21,7 +21,8 @@ from ._lib import MrrrError, MrrrInfo, MrrrRange, MrrrTuning  # noqa: F401
 __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "eigh_tridiagonal_backward",
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
            "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division",
-           "backtransform", "tridiagonalize", "cholesky", "sygst", "trsm_lt", "eigh_generalized"]
+           "backtransform", "tridiagonalize", "cholesky", "sygst", "trsm_lt", "eigh_generalized",
+           "eigh_tridiagonal_f32"]
 
 
 def _torch():
@@ -103,6 +104,39 @@ def eigh_tridiagonal(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigva
         _lib.check(rc)
         host = info_dev.cpu().numpy()  # kept alive across the copy
         ctypes.memmove(ctypes.addressof(info), host.ctypes.data, ctypes.sizeof(MrrrInfo))
+    mm = int(info.m) if n > 0 else 0
+    w = w[:mm]
+    Z = None if Zbuf is None else Zbuf[:mm, :n].t()
+    out = (w, Z)
+    if return_info:
+        out = out + (info.as_dict(),)
+    return out
+
+
+def eigh_tridiagonal_f32(d, e, select="a", il=None, iu=None, vl=None, vu=None, eigvals_only=False,
+                         stream=None, return_info=False):
+    """eigh_tridiagonal for FP32 data with FP64 arithmetic inside
+    (mrrr_step_f32): d and e are taken as float32, w and Z are float32 with
+    orthogonality and residuals at the FP32 rounding level."""
+    torch = _torch()
+    lib = _lib.load()
+
+    def f32(x, device=None):
+        if not torch.is_tensor(x):
+            x = torch.as_tensor(np.asarray(x, dtype=np.float32))
+        if device is None:
+            device = x.device if x.is_cuda else torch.device("cuda")
+        return x.to(device=device, dtype=torch.float32).contiguous()
+
+    d = f32(d)
+    n = d.numel()
+    e = f32(e, d.device) if n > 1 else torch.zeros(1, dtype=torch.float32, device=d.device)
+    rng, m = _range(select, il, iu, vl, vu, n)
+    w = torch.empty(max(m, 1), dtype=torch.float32, device=d.device)
+    Zbuf = None if eigvals_only else torch.empty((max(m, 1), max(n, 1)), dtype=torch.float32, device=d.device)
+    info = MrrrInfo()
+    _lib.check(lib.mrrr_step_f32(n, _ptr(d), _ptr(e), rng, _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(info),
+                                 _stream_ptr(stream)))
     mm = int(info.m) if n > 0 else 0
     w = w[:mm]
     Z = None if Zbuf is None else Zbuf[:mm, :n].t()

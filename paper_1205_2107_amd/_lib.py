@@ -17,7 +17,7 @@ EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_ba
            "mrrr_profile_read", "mrrr_release", "mrrr_last_error", "mrrr_status_string", "mrrr_workspace_size",
            "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc",
            "mrrr_probe_division", "mrrr_backtransform", "mrrr_tridiagonalize",
-           "mrrr_cholesky", "mrrr_sygst", "mrrr_trsm_lt")
+           "mrrr_cholesky", "mrrr_sygst", "mrrr_trsm_lt", "mrrr_step_f32")
 KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform", "tridiag", "ghep")
 
 
@@ -75,6 +75,8 @@ def load():
     PI64 = ctypes.POINTER(ctypes.c_int64)
     lib.mrrr_step.restype = ctypes.c_int
     lib.mrrr_step.argtypes = [I64, P, P, MrrrRange, P, P, I64, ctypes.POINTER(MrrrInfo), P]
+    lib.mrrr_step_f32.restype = ctypes.c_int
+    lib.mrrr_step_f32.argtypes = [I64, P, P, MrrrRange, P, P, I64, ctypes.POINTER(MrrrInfo), P]
     lib.mrrr_workspace_size.restype = ctypes.c_size_t
     lib.mrrr_workspace_size.argtypes = [I64, MrrrRange]
     lib.mrrr_step_ws.restype = ctypes.c_int

@@ -60,6 +60,7 @@ struct Problem {
   int32_t status;
   int32_t first_blk;    // first block id of the problem
   int64_t below;        // VALUE: eigenvalues at or below vl over all blocks
+  double gaptol;        // relative-gap threshold of the classification (0: kRelgapTol)
 };
 
 struct Block {
@@ -73,6 +74,7 @@ struct Block {
   int32_t gP;      // grid intervals
   int64_t goff;    // first grid point
   double glo, ghi; // grid end points (root frame)
+  double gaptol;   // relative-gap threshold of the classification
 };
 
 struct Node {

@@ -741,7 +741,8 @@ static int check_step_args(int64_t n, const double* d, const double* e, mrrr_ran
 // one problem; arena (may be NULL): carve every buffer from [work, work +
 // work_bytes) instead of the library's workspace
 static int step_impl(int64_t n, const double* d, const double* e, mrrr_range range, double* w, double* Z,
-                     int64_t ldz, void* work, size_t work_bytes, bool no_fork, mrrr_info* info, hipStream_t stream) {
+                     int64_t ldz, void* work, size_t work_bytes, bool no_fork, mrrr_info* info, hipStream_t stream,
+                     double gaptol = 0.0) {
   if (info) memset(info, 0, sizeof(*info));
   if (n == 0) return 0;
   int dev = 0;
@@ -760,6 +761,7 @@ static int step_impl(int64_t n, const double* d, const double* e, mrrr_range ran
   p.iu = range.iu;
   p.vl = range.vl;
   p.vu = range.vu;
+  p.gaptol = gaptol;
   Report r;
   int rc;
   if (work) {
@@ -842,6 +844,37 @@ static size_t workspace_bytes(int64_t n, int64_t m, bool vectors, const mrrr_tun
   return b;
 }
 
+// ---------------------------------------------------------------------------
+// the FP32 interface (mrrr_step_f32): FP32 data in and out, the solver in
+// FP64 with the classification threshold relaxed to what FP32 results need
+
+__global__ void k_f32_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+
+// y[:, c] = x[:, c] rounded, columns of n rows (leading dimensions ldx, ldy)
+__global__ void k_f64_to_f32(int64_t n, int64_t m, const double* __restrict__ x, int64_t ldx, float* __restrict__ y,
+                             int64_t ldy) {
+  for (int64_t c = blockIdx.y; c < m; c += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+      y[c * ldy + i] = (float)x[c * ldx + i];
+}
+
+// Relative-gap threshold for FP32 results computed in FP64: a singleton's
+// vector leans towards its neighbours by about eps64 / relgap, the pairs
+// of a node by about n eps64 / gaptol; with gaptol = 4 n eps64 / eps32 =
+// n 2^-27 that stays below eps32 / 4, so singletons may be much closer than
+// the FP64 threshold of 1e-3 allows (fewer clusters, a shallower tree).
+static double mixed_gaptol(int64_t n) {
+  return std::min(kRelgapTol, std::max(1.0, (double)n) * std::ldexp(1.0, -27));
+}
+
+static std::mutex g_mixed_mu;
+static void* g_mixed = nullptr;
+static size_t g_mixed_bytes = 0;
+static int g_mixed_dev = -1;
+
 }  // namespace mrrr
 
 using namespace mrrr;
@@ -854,6 +887,57 @@ int mrrr_step(int64_t n, const double* d, const double* e, mrrr_range range, dou
   int rc = check_step_args(n, d, e, range, w, Z, ldz);
   if (rc != 0) return rc;
   return step_impl(n, d, e, range, w, Z, ldz, nullptr, 0, false, info, (hipStream_t)stream);
+}
+
+int mrrr_step_f32(int64_t n, const float* d, const float* e, mrrr_range range, float* w, float* Z, int64_t ldz,
+                  mrrr_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  int rc = check_step_args(n, (const double*)d, (const double*)e, range, (const double*)w, (const double*)Z, ldz);
+  if (rc != 0) return rc;
+  if (n == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t mmax = range.kind == MRRR_INDEX ? range.iu - range.il + 1 : n;
+  std::lock_guard<std::mutex> lk(g_mixed_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MRRR_ERR_NO_DEVICE, "no HIP device");
+  const size_t zb = Z ? sizeof(double) * (size_t)n * (size_t)mmax : 0;
+  const size_t need = align_up(sizeof(double) * (size_t)n) * 3 + align_up(std::max<size_t>(zb, 1));
+  if (!g_mixed || g_mixed_bytes < need || g_mixed_dev != dev) {
+    if (g_mixed) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_mixed);
+    }
+    g_mixed = nullptr;
+    g_mixed_bytes = 0;
+    if (hipMalloc(&g_mixed, need) != hipSuccess) return fail(MRRR_ERR_CAPACITY, "hipMalloc failed for the FP32 interface");
+    g_mixed_bytes = need;
+    g_mixed_dev = dev;
+  }
+  char* base = (char*)g_mixed;
+  double* d64 = (double*)base;
+  double* e64 = (double*)(base + align_up(sizeof(double) * (size_t)n));
+  double* w64 = (double*)(base + 2 * align_up(sizeof(double) * (size_t)n));
+  double* Z64 = Z ? (double*)(base + 3 * align_up(sizeof(double) * (size_t)n)) : nullptr;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(g), dim3(256), 0, st, n, d, d64);
+  if (n > 1) hipLaunchKernelGGL(k_f32_to_f64, dim3(g), dim3(256), 0, st, n - 1, e, e64);
+  mrrr_info inf;
+  rc = step_impl(n, d64, e64, range, w64, Z64, n, nullptr, 0, false, &inf, st, mixed_gaptol(n));
+  if (info) *info = inf;
+  if (rc < 0) return rc;
+  const int64_t m = inf.m;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 65535), 1), dim3(256), 0, st,
+                       m, (int64_t)1, (const double*)w64, m, w, m);
+    if (Z)
+      hipLaunchKernelGGL(k_f64_to_f32,
+                         dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64), (unsigned)std::min<int64_t>(m, 65535)),
+                         dim3(256), 0, st, n, m, (const double*)Z64, n, Z, ldz);
+  }
+  hipError_t er = hipStreamSynchronize(st);
+  if (er == hipSuccess) er = hipGetLastError();
+  if (er != hipSuccess) return fail(MRRR_ERR_HIP, "FP32 conversion failed: %s", hipGetErrorString(er));
+  return rc;
 }
 
 size_t mrrr_workspace_size(int64_t n, mrrr_range range) {

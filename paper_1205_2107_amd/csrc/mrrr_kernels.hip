@@ -197,6 +197,7 @@ __global__ void k_blocks2(Problem* __restrict__ P, const int64_t* __restrict__ p
   blk.gP = 0;
   blk.goff = 0;
   blk.glo = blk.ghi = 0.0;
+  blk.gaptol = P[p].gaptol > 0.0 ? P[p].gaptol : kRelgapTol;
   B[b] = blk;
   atomicAdd(&P[p].nblk, 1);
   if (blk.lrow0 == 0) P[p].first_blk = b;
@@ -974,10 +975,10 @@ __global__ void k_block_wanted(Block* __restrict__ B, int nblk, const Problem* _
 // ---------------------------------------------------------------------------
 // 6. classification of the active nodes' indices into runs
 
-__device__ inline bool rel_break(double lo_j, double hi_j, double lo_k, double hi_k) {
+__device__ inline bool rel_break(double lo_j, double hi_j, double lo_k, double hi_k, double gaptol) {
   const double mj = 0.5 * (lo_j + hi_j);
   const double mk = 0.5 * (lo_k + hi_k);
-  return (lo_k - hi_j) >= kRelgapTol * fmax(fabs(mj), fabs(mk));
+  return (lo_k - hi_j) >= gaptol * fmax(fabs(mj), fabs(mk));
 }
 
 // absolute gap of slot s to its neighbours within node nd (the node's outer gaps
@@ -1006,12 +1007,12 @@ __global__ void k_cls_flags(const Block* __restrict__ B, const Node* __restrict_
       start = 1;
     } else {
       const double l0 = lo[s - 1], h0 = hi[s - 1], l1 = lo[s], h1 = hi[s];
-      start = rel_break(l0, h0, l1, h1);
+      start = rel_break(l0, h0, l1, h1, blk.gaptol);
       // the decision is ambiguous when the bracket widths could flip it
       const uint32_t fp = sflag[s - 1];
       if (!((fp & F_ACCURATE) && (fl & F_ACCURATE))) {
         const double m0 = 0.5 * (l0 + h0), m1 = 0.5 * (l1 + h1);
-        const double margin = (l1 - h0) - kRelgapTol * fmax(fabs(m0), fabs(m1));
+        const double margin = (l1 - h0) - blk.gaptol * fmax(fabs(m0), fabs(m1));
         const double unc = 2.0 * ((h0 - l0) + (h1 - l1));
         if (fabs(margin) <= unc) {
           if (!(fp & F_ACCURATE)) atomicOr(&sflag[s - 1], F_NEEDS_REFINE);
