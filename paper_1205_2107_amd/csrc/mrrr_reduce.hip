@@ -79,6 +79,25 @@ __device__ double block_reduce(double x, double* sh) {
   return r;
 }
 
+// two maxima over the workgroup with one pair of barriers; every thread gets both
+__device__ void block_max2(double& x, double& y, double* sh, double* sh2) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  x = wave_max(x);
+  y = wave_max(y);
+  __syncthreads();
+  if (lane == 0) {
+    sh[wave] = x;
+    sh2[wave] = y;
+  }
+  __syncthreads();
+  x = sh[0];
+  y = sh2[0];
+  for (int k = 1; k < nw; ++k) {
+    x = fmax(x, sh[k]);
+    y = fmax(y, sh2[k]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the column update and reflector of column i (j = i - k within the panel).
 // A[r, i] for r >= i holds the column updated by every pair of the panel but
@@ -90,10 +109,13 @@ __global__ void __launch_bounds__(NTC) k_tr_col(int64_t n, double* __restrict__ 
                                                 double* __restrict__ Vp, double* __restrict__ Wp,
                                                 const double* __restrict__ S, int nS, double* __restrict__ d,
                                                 double* __restrict__ e, double* __restrict__ tau, int last) {
-  __shared__ double sh[NTC / 64];
+  __shared__ double sh[NTC / 64], sh2[NTC / 64];
   __shared__ double s_alpha;
   const int t = threadIdx.x;
   double* col = A + i * lda;
+  // the column update (j > 0) and the largest magnitudes of the entries below
+  // the diagonal (mx) and below the subdiagonal (mt) in one pass
+  double mx = 0.0, mt = 0.0;
   if (j > 0) {
     if (t == 0) {
       double s = 0.0;
@@ -107,23 +129,25 @@ __global__ void __launch_bounds__(NTC) k_tr_col(int64_t n, double* __restrict__ 
     for (int64_t r = i + t; r < n; r += NTC) {
       const double v = vp[r];
       wp[r] = fma(al, v, wp[r]);
-      col[r] = fma(-2.0 * al, v, col[r]);
+      const double c = fma(-2.0 * al, v, col[r]);
+      col[r] = c;
+      if (r >= i + 1) mx = fmax(mx, fabs(c));
+      if (r >= i + 2) mt = fmax(mt, fabs(c));
     }
-    __syncthreads();
+  } else {
+    for (int64_t r = i + 1 + t; r < n; r += NTC) {
+      const double a = fabs(col[r]);
+      mx = fmax(mx, a);
+      if (r >= i + 2) mt = fmax(mt, a);
+    }
   }
   if (last) {
+    __syncthreads();
     if (t == 0) d[i] = col[i];
     return;
   }
   // reflector of x = col[i+1 ..]: scale by a power of two near max |x|
-  double mx = 0.0, mt = 0.0;
-  for (int64_t r = i + 1 + t; r < n; r += NTC) {
-    const double a = fabs(col[r]);
-    mx = fmax(mx, a);
-    if (r >= i + 2) mt = fmax(mt, a);
-  }
-  mx = block_reduce<true>(mx, sh);
-  mt = block_reduce<true>(mt, sh);
+  block_max2(mx, mt, sh, sh2);
   const double alpha = col[i + 1];
   double beta = alpha, tu = 0.0, scale = 0.0;
   if (mt > 0.0) {
@@ -188,7 +212,7 @@ __global__ void __launch_bounds__(64 * kSW) k_tr_symv(int64_t n, const double* _
                                                 int j, const double* __restrict__ Vp, const double* __restrict__ Wp,
                                                 double* __restrict__ P, double* __restrict__ pq, int64_t ntask) {
   __shared__ double vJs[NBR];
-  __shared__ double rs[kSW][NBR];
+  __shared__ double rs[2][kSW][NBR];
   __shared__ double us[NBR];
   __shared__ double sh[kSW];
   const int t = threadIdx.x, lane = t & 63, part = t >> 6;
@@ -257,18 +281,20 @@ __global__ void __launch_bounds__(64 * kSW) k_tr_symv(int64_t n, const double* _
       x = fma(a, vj[k], x);
       u[k] = fma(cur[k], vi, u[k]);
     }
-    rs[part][lane] = x;
+    // two buffers: the barrier of the next tile orders this tile's readers
+    // before the writers of the tile after it
+    const int buf = (int)((I - Ib) & 1);
+    rs[buf][part][lane] = x;
     __syncthreads();
     if (t < NBR) {
-      double xs = rs[0][t];
+      double xs = rs[buf][0][t];
 #pragma unroll
-      for (int w = 1; w < kSW; ++w) xs += rs[w][t];
+      for (int w = 1; w < kSW; ++w) xs += rs[buf][w][t];
       if (diag)
         xdiag = xs;
       else
         P[(I * Tn + Jr) * NBR + t] = xs;
     }
-    __syncthreads();
   }
   // column sums: log2(kCPT) halving exchanges leave lane l with column index
   // k(l) (the top bits of l) summed over the lanes that differ in those
