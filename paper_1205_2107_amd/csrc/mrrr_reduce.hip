@@ -52,6 +52,7 @@ constexpr int NTC = 1024;       // threads of the reflector workgroup
 constexpr int kStrip = 8;       // tiles of one column strip per workgroup of the product
 constexpr int kSW = 8;          // wavefronts per workgroup of the product
 constexpr int kCPT = NBR / kSW; // tile columns per thread in the product
+constexpr int kYW = 8;          // wavefronts per workgroup adding the product's slots
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -330,9 +331,9 @@ __global__ void __launch_bounds__(64 * kSW) k_tr_symv(int64_t n, const double* _
 
 // y[r] = (A v)[r] for rows o .. n-1: block K's slots added in a fixed order
 // (each of the four wavefronts a quarter of them, then the four in order)
-__global__ void __launch_bounds__(NT) k_tr_ysum(int64_t n, int64_t i, const double* __restrict__ P,
-                                                double* __restrict__ y) {
-  __shared__ double rs[NT / 64][NBR];
+__global__ void __launch_bounds__(64 * kYW) k_tr_ysum(int64_t n, int64_t i, const double* __restrict__ P,
+                                                      double* __restrict__ y) {
+  __shared__ double rs[kYW][NBR];
   const int t = threadIdx.x, a = t & 63, part = t >> 6;
   const int64_t o = i + 1;
   const int64_t T0 = o >> 6, Tn = ((n + 63) >> 6) - T0;
@@ -340,17 +341,20 @@ __global__ void __launch_bounds__(NT) k_tr_ysum(int64_t n, int64_t i, const doub
   const double* p = P + (K * Tn) * NBR + a;
   double s0 = 0.0, s1 = 0.0;
   int64_t s = part;
-  for (; s + 4 < K; s += 8) {
+  for (; s + kYW < K; s += 2 * kYW) {
     s0 += p[s * NBR];
-    s1 += p[(s + 4) * NBR];
+    s1 += p[(s + kYW) * NBR];
   }
-  for (; s < K; s += 4) s0 += p[s * NBR];
-  for (int64_t gg = part; K + gg * kStrip < Tn; gg += 4) s1 += p[(K + gg * kStrip) * NBR];
+  for (; s < K; s += kYW) s0 += p[s * NBR];
+  for (int64_t gg = part; K + gg * kStrip < Tn; gg += kYW) s1 += p[(K + gg * kStrip) * NBR];
   rs[part][a] = s0 + s1;
   __syncthreads();
   if (t < NBR) {
     const int64_t r = (T0 + K) * NBR + t;
-    if (r >= o && r < n) y[r] = (rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t]);
+    double acc = rs[0][t];
+#pragma unroll
+    for (int w = 1; w < kYW; ++w) acc += rs[w][t];
+    if (r >= o && r < n) y[r] = acc;
   }
 }
 
@@ -628,7 +632,7 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
       const int64_t ntask = G * Tn - (int64_t)kStrip * G * (G - 1) / 2;
       hipLaunchKernelGGL(k_tr_symv, dim3((unsigned)(ntask + j)), dim3(64 * kSW), 0, st, n, (const double*)A, lda, i, j,
                          (const double*)Vp, (const double*)Wp, Py, pq, ntask);
-      hipLaunchKernelGGL(k_tr_ysum, dim3((unsigned)Tn), dim3(NT), 0, st, n, i, (const double*)Py, y);
+      hipLaunchKernelGGL(k_tr_ysum, dim3((unsigned)Tn), dim3(64 * kYW), 0, st, n, i, (const double*)Py, y);
       nS = (int)((m + NT - 1) / NT);
       const int next = (j + 1 < pw) || (i + 1 == n - 1);
       hipLaunchKernelGGL(k_tr_w, dim3((unsigned)nS), dim3(NT), 0, st, n, A, lda, i, j, Vp, Wp, (const double*)y,
