@@ -413,6 +413,28 @@ int mrrr_sygst(int64_t n, double* A, int64_t lda, const double* L, int64_t ldl, 
  * launch. */
 int mrrr_trsm_lt(int64_t n, int64_t m, const double* L, int64_t ldl, double* Y, int64_t ldy, void* stream);
 
+/* Dense drivers: every stage on the GPU, on the caller's stream.
+ *
+ * mrrr_syev: all eigenpairs of the dense symmetric A (n x n, lda, lower
+ * triangle read): mrrr_tridiagonalize, mrrr_step, mrrr_backtransform.  A is
+ * overwritten (its lower triangle holds the reduction); w (device, n) the
+ * eigenvalues ascending; Z (device, n x n, ldz) the eigenvectors; info as for
+ * mrrr_step (the tridiagonal solve's report).  Returns 0; -1 (n < 0 or
+ * n > 2^18), -2 (A null), -3 (lda), -4 (w null), -5 (Z null), -6 (ldz); else
+ * the first non-zero return of a stage.
+ *
+ * mrrr_sygv: all eigenpairs of A x = lambda B x, B positive definite (lower
+ * triangles of A and B read): mrrr_cholesky, mrrr_sygst, mrrr_syev,
+ * mrrr_trsm_lt.  A and B are overwritten (B with L); Z holds X with
+ * X^T B X = I.  *not_pd (host) = 0, or the 1-based column whose pivot was not
+ * positive (then nothing else is computed and the return is 0).  Returns 0;
+ * -1 (n), -2 (A null), -3 (lda), -4 (B null), -5 (ldb), -6 (w null), -7 (Z
+ * null), -8 (ldz), -9 (not_pd null); else the first non-zero return of a
+ * stage.  The library keeps 3 n doubles for d, e and tau. */
+int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t ldz, mrrr_info* info, void* stream);
+int mrrr_sygv(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, double* w, double* Z, int64_t ldz,
+              int64_t* not_pd, mrrr_info* info, void* stream);
+
 /* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
  * caller-given operands (no solve; for tests of their rounding).  a, b: device
  * arrays of n doubles; out: device array of 4 n doubles, written as

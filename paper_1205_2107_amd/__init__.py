@@ -22,7 +22,7 @@ __all__ = ["eigh_tridiagonal", "eigh_tridiagonal_batched", "autotune_batched", "
            "eigh_tridiagonal_backward_batched", "MRRRFunction", "get_tuning", "set_tuning", "profile",
            "profile_read", "release", "workspace_size", "get_limits", "set_limits", "probe_division",
            "backtransform", "tridiagonalize", "cholesky", "sygst", "trsm_lt", "eigh_generalized",
-           "eigh_tridiagonal_f32"]
+           "eigh_tridiagonal_f32", "eigh_dense"]
 
 
 def _torch():
@@ -502,19 +502,50 @@ def trsm_lt(L, Y, stream=None):
     return Yd
 
 
+def eigh_dense(A, stream=None):
+    """All eigenpairs of the dense symmetric A (lower triangle read) through
+    the library's driver mrrr_syev: reduction to tridiagonal form, the MRRR
+    tridiagonal eigensolver, back-transformation, all on the GPU.  A is
+    overwritten when it is a column-major float64 device tensor.  Returns
+    (w ascending, Z column-major)."""
+    torch = _torch()
+    dev = _dev_of(A)
+    Ad = _dense_colmajor(A, dev, square=True)
+    n = Ad.shape[0]
+    w = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    Z = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+    info = MrrrInfo()
+    with torch.cuda.device(dev):
+        _lib.check(_lib.load().mrrr_syev(n, _ptr(Ad), _ld(Ad), _ptr(w), _ptr(Z), max(n, 1), ctypes.byref(info),
+                                          _stream_ptr(stream)))
+    return w[:n], Z[:n, :n].t()
+
+
 def eigh_generalized(A, B, stream=None):
     """All eigenpairs of A x = lambda B x (A symmetric, B symmetric positive
-    definite, lower triangles read), every stage on the GPU: Cholesky
-    factorization, reduction to standard form, reduction to tridiagonal form,
-    the MRRR tridiagonal eigensolver, and both back-transformations.  A and B
-    are overwritten when they are column-major float64 device tensors.
-    Returns (w ascending, X column-major with X^T B X = I)."""
-    L = cholesky(B, stream)
-    M = sygst(A, L, stream)
-    d, e, tau, V = tridiagonalize(M, stream)
-    w, Z = eigh_tridiagonal(d, e, stream=stream)
-    Y = backtransform(V, tau, Z, stream)
-    return w, trsm_lt(L, Y, stream)
+    definite, lower triangles read) through the library's driver mrrr_sygv,
+    every stage on the GPU: Cholesky factorization, reduction to standard
+    form, reduction to tridiagonal form, the MRRR tridiagonal eigensolver,
+    and both back-transformations.  A and B are overwritten when they are
+    column-major float64 device tensors.  Returns (w ascending, X
+    column-major with X^T B X = I); raises when B is not positive definite."""
+    torch = _torch()
+    dev = _dev_of(A)
+    Ad = _dense_colmajor(A, dev, square=True)
+    Bd = _dense_colmajor(B, dev, square=True)
+    if Bd.shape != Ad.shape:
+        raise ValueError("A and B must have one order")
+    n = Ad.shape[0]
+    w = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    X = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+    bad = ctypes.c_int64(0)
+    info = MrrrInfo()
+    with torch.cuda.device(dev):
+        _lib.check(_lib.load().mrrr_sygv(n, _ptr(Ad), _ld(Ad), _ptr(Bd), _ld(Bd), _ptr(w), _ptr(X), max(n, 1),
+                                          ctypes.byref(bad), ctypes.byref(info), _stream_ptr(stream)))
+    if bad.value:
+        raise ValueError(f"B not positive definite (pivot of column {bad.value})")
+    return w[:n], X[:n, :n].t()
 
 
 def probe_division(a, b, stream=None):

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <string>
 
@@ -504,6 +505,86 @@ int mrrr_trsm_lt(int64_t n, int64_t m, const double* L, int64_t ldl, double* Y, 
     mrrr::prof_add(MRRR_K_GHEP, l, ms, nn * nn * (double)m, 0.0);
   }
   return 0;
+}
+
+// the dense drivers: every stage in turn on the caller's stream, through
+// the entry points above (their workspaces, locks and synchronisation)
+static std::mutex g_drv_mu;
+static void* g_drv = nullptr;
+static size_t g_drv_bytes = 0;
+static int g_drv_dev = -1;
+
+static int drv_buffers(int64_t n, double** d, double** e, double** tau) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    mrrr::set_last_error("hipGetDevice failed");
+    return MRRR_ERR_HIP;
+  }
+  const size_t one = ((sizeof(double) * (size_t)std::max<int64_t>(n, 1)) + 255) & ~(size_t)255;
+  if (!g_drv || g_drv_bytes < 3 * one || g_drv_dev != dev) {
+    if (g_drv) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_drv);
+    }
+    g_drv = nullptr;
+    g_drv_bytes = 0;
+    if (hipMalloc(&g_drv, 3 * one) != hipSuccess) {
+      mrrr::set_last_error("hipMalloc failed for the dense driver");
+      return MRRR_ERR_CAPACITY;
+    }
+    g_drv_bytes = 3 * one;
+    g_drv_dev = dev;
+  }
+  *d = (double*)g_drv;
+  *e = (double*)((char*)g_drv + one);
+  *tau = (double*)((char*)g_drv + 2 * one);
+  return 0;
+}
+
+int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t ldz, mrrr_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (n < 0 || n > (int64_t)1 << 18) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (n > 0 && !w) return -4;
+  if (n > 0 && !Z) return -5;
+  if (ldz < std::max<int64_t>(1, n)) return -6;
+  if (n == 0) return 0;
+  std::lock_guard<std::mutex> lk(g_drv_mu);
+  double *d, *e, *tau;
+  int rc = drv_buffers(n, &d, &e, &tau);
+  if (rc) return rc;
+  rc = mrrr_tridiagonalize(n, A, lda, d, e, tau, stream);
+  if (rc) return rc;
+  mrrr_range all;
+  memset(&all, 0, sizeof(all));
+  all.kind = MRRR_ALL;
+  rc = mrrr_step(n, d, e, all, w, Z, ldz, info, stream);
+  if (rc) return rc;
+  return mrrr_backtransform(n, n, A, lda, tau, Z, ldz, stream);
+}
+
+int mrrr_sygv(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, double* w, double* Z, int64_t ldz,
+              int64_t* not_pd, mrrr_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (n < 0 || n > (int64_t)1 << 18) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (n > 0 && !B) return -4;
+  if (ldb < std::max<int64_t>(1, n)) return -5;
+  if (n > 0 && !w) return -6;
+  if (n > 0 && !Z) return -7;
+  if (ldz < std::max<int64_t>(1, n)) return -8;
+  if (!not_pd) return -9;
+  *not_pd = 0;
+  if (n == 0) return 0;
+  int rc = mrrr_cholesky(n, B, ldb, not_pd, stream);
+  if (rc || *not_pd) return rc;
+  rc = mrrr_sygst(n, A, lda, B, ldb, stream);
+  if (rc) return rc;
+  rc = mrrr_syev(n, A, lda, w, Z, ldz, info, stream);
+  if (rc) return rc;
+  return mrrr_trsm_lt(n, n, B, ldb, Z, ldz, stream);
 }
 
 }  // extern "C"

@@ -234,3 +234,21 @@ def test_binding_helpers_are_not_shadowed():
     names = [n.name for n in ast.parse(src).body if isinstance(n, (ast.FunctionDef, ast.ClassDef))]
     dup = sorted({x for x in names if names.count(x) > 1})
     assert not dup, dup
+
+
+def test_dense_driver_argument_checks():
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    bad = ctypes.c_int64(3)
+    assert lib.mrrr_syev(-1, fake, 1, fake, fake, 1, None, None) == -1
+    assert lib.mrrr_syev(4, None, 4, fake, fake, 4, None, None) == -2
+    assert lib.mrrr_syev(4, fake, 3, fake, fake, 4, None, None) == -3
+    assert lib.mrrr_syev(4, fake, 4, None, fake, 4, None, None) == -4
+    assert lib.mrrr_syev(4, fake, 4, fake, None, 4, None, None) == -5
+    assert lib.mrrr_syev(4, fake, 4, fake, fake, 3, None, None) == -6
+    assert lib.mrrr_syev(0, None, 1, None, None, 1, None, None) == 0
+    assert lib.mrrr_sygv(4, fake, 4, None, 4, fake, fake, 4, ctypes.byref(bad), None, None) == -4
+    assert lib.mrrr_sygv(4, fake, 4, fake, 3, fake, fake, 4, ctypes.byref(bad), None, None) == -5
+    assert lib.mrrr_sygv(4, fake, 4, fake, 4, fake, fake, 4, None, None, None) == -9
+    assert lib.mrrr_sygv(0, None, 1, None, 1, None, None, 1, ctypes.byref(bad), None, None) == 0 and bad.value == 0

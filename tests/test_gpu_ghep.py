@@ -144,3 +144,32 @@ def test_generalized_full_size_sampled(M):
     assert res <= 20.0 and borth <= 20.0 * 3.0  # the spectrum of G G^T / n + I lies in [1, 7/3]
     del lower, full, Bf, Bw, X
     torch.cuda.empty_cache()
+
+
+def test_drivers_equal_the_stages(M):
+    # mrrr_syev and mrrr_sygv run the same kernels in the same order as the
+    # stage-by-stage calls: identical bits
+    n = 170
+    A = W.dense_symmetric(n, 2100)
+    B = W.dense_spd(n, 2101)
+    w1, Z1 = M.eigh_dense(dev_lower(A))
+    d, e, tau, V = M.tridiagonalize(dev_lower(A))
+    w2, Z2 = M.eigh_tridiagonal(d, e)
+    Y2 = M.backtransform(V, tau, Z2)
+    assert torch.equal(w1, w2) and torch.equal(Z1, Y2)
+    wg1, X1 = M.eigh_generalized(dev_lower(A), dev_lower(B))
+    L = M.cholesky(dev_lower(B))
+    Ms = M.sygst(dev_lower(A), L)
+    d, e, tau, V = M.tridiagonalize(Ms)
+    wg2, Zg = M.eigh_tridiagonal(d, e)
+    X2 = M.trsm_lt(L, M.backtransform(V, tau, Zg))
+    assert torch.equal(wg1, wg2) and torch.equal(X1, X2)
+    bad = B.copy()
+    bad[100, 100] = -5.0
+    with pytest.raises(ValueError, match="not positive definite"):
+        M.eigh_generalized(dev_lower(A), dev_lower(bad))
+    # trivial orders
+    w0, Z0 = M.eigh_dense(torch.zeros((0, 0), dtype=torch.float64, device="cuda"))
+    assert w0.numel() == 0
+    w1, X1 = M.eigh_generalized(np.array([[3.0]]), np.array([[4.0]]))
+    assert abs(float(w1[0]) - 0.75) <= 4 * EPS and abs(float(X1[0, 0]) - 0.5) <= 4 * EPS
