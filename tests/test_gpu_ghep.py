@@ -173,3 +173,31 @@ def test_drivers_equal_the_stages(M):
     assert w0.numel() == 0
     w1, X1 = M.eigh_generalized(np.array([[3.0]]), np.array([[4.0]]))
     assert abs(float(w1[0]) - 0.75) <= 4 * EPS and abs(float(X1[0, 0]) - 0.5) <= 4 * EPS
+
+
+def test_leading_dimensions_and_nonfinite_input(M):
+    # leading dimensions above n (views into taller buffers) give the same
+    # bits; a NaN in A reaches the tridiagonal solver, which reports it
+    n = 90
+    A = W.dense_symmetric(n, 2200)
+    B = W.dense_spd(n, 2201)
+
+    def tall(X, extra):
+        big = torch.full((n + extra, n), float("nan"), dtype=torch.float64, device="cuda").t().contiguous().t()
+        big[:n, :] = torch.tensor(X, device="cuda")
+        return big[:n, :]
+
+    w1, X1 = M.eigh_generalized(dev_lower(A), dev_lower(B))
+    Av, Bv = tall(A, 7), tall(B, 13)
+    assert Av.stride(1) == n + 7 and Bv.stride(1) == n + 13
+    w2, X2 = M.eigh_generalized(Av, Bv)
+    assert torch.equal(w1, w2) and torch.equal(X1, X2)
+    bad = A.copy()
+    bad[50, 20] = np.nan
+    with pytest.raises(Exception):
+        M.eigh_generalized(dev_lower(bad), dev_lower(B))
+    with pytest.raises(Exception):
+        M.eigh_dense(dev_lower(bad))
+    # the library stays usable
+    w3, X3 = M.eigh_generalized(dev_lower(A), dev_lower(B))
+    assert torch.equal(w1, w3)

@@ -100,3 +100,13 @@ def test_fp32_subsets(M):
     assert res <= 4.0 and orth <= 4.0
     w, _ = M.eigh_tridiagonal_f32(d, e, eigvals_only=True)
     check(d, e, w.cpu().numpy(), None, wo)
+
+
+def test_fp32_nonfinite_input_reports(M):
+    d, e = f32(*W.random_uniform(64, 8400))
+    d[10] = np.nan
+    with pytest.raises(Exception, match="non-finite|inf|NaN|4"):
+        M.eigh_tridiagonal_f32(d, e)
+    d, e = f32(*W.random_uniform(64, 8400))
+    w, Z = M.eigh_tridiagonal_f32(d, e)
+    assert torch.isfinite(w).all() and torch.isfinite(Z).all()
