@@ -175,7 +175,7 @@ __device__ __forceinline__ void lower_tile(int64_t tl, int64_t* I, int64_t* J) {
   *J = tl - a * (a + 1) / 2;
 }
 
-// C (M x N, leading dimension ldc) -= op(A) op(B) with K = kk <= 64:
+// C (M x N, leading dimension ldc) -= op(A) op(B) with K = kk (in steps of 16):
 //   op(A)[i][k] = kTA ? A[k + i lda] : A[i + k lda]
 //   op(B)[k][j] = kTB ? B[j + k ldb] : B[k + j ldb]
 // one 64 x 64 tile of C per workgroup (grid x = tiles over N, y = tiles over
@@ -369,14 +369,24 @@ static unsigned tiles(int64_t m) { return (unsigned)((m + NB - 1) / NB); }
 // rank-64 update of the rows below
 static void trsm_lower_left(hipStream_t st, int64_t n, int64_t nv, const double* L, int64_t ldl, double* R,
                             int64_t ldr) {
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    const int kb = (int)std::min<int64_t>(NB, n - k0);
-    hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb,
+  // two diagonal blocks per step: the second is brought up to date by the
+  // first (a 64-row update), and the rows below take one rank-128 update, so
+  // the large updates pass over R half as often
+  for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
+    const int kb1 = (int)std::min<int64_t>(NB, n - k0);
+    hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb1,
                        R + k0, ldr, nv, (const int*)nullptr);
-    const int64_t below = n - k0 - kb;
+    const int64_t k1 = k0 + kb1;
+    if (k1 >= n) break;
+    const int kb2 = (int)std::min<int64_t>(NB, n - k1);
+    hipLaunchKernelGGL((k_gemm_sub<false, false, false>), dim3(tiles(nv), 1), dim3(NT), 0, st, (int64_t)kb2, nv, kb1,
+                       L + k1 + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + k1, ldr, (const int*)nullptr);
+    hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + k1 + k1 * ldl, ldl, kb2,
+                       R + k1, ldr, nv, (const int*)nullptr);
+    const int64_t below = n - k1 - kb2;
     if (below > 0)
       hipLaunchKernelGGL((k_gemm_sub<false, false, false>), dim3(tiles(nv), tiles(below)), dim3(NT), 0, st, below, nv,
-                         kb, L + (k0 + kb) + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + k0 + kb, ldr,
+                         kb1 + kb2, L + (k1 + kb2) + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + k1 + kb2, ldr,
                          (const int*)nullptr);
   }
 }
@@ -483,16 +493,25 @@ int mrrr_trsm_lt(int64_t n, int64_t m, const double* L, int64_t ldl, double* Y, 
   std::lock_guard<std::mutex> lk(g_mu);
   mrrr::ProfEvents prof(st);
   prof.begin(MRRR_K_GHEP);
+  // two diagonal blocks per step, last first (as in the forward solve): the
+  // rows above take one rank-(kb + 64) update
   const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t b = nblk - 1; b >= 0; --b) {
+  for (int64_t b = nblk - 1; b >= 0; b -= 2) {
     const int64_t k0 = b * NB;
     const int kb = (int)std::min<int64_t>(NB, n - k0);
     hipLaunchKernelGGL((k_trsm_tile<false, true>), dim3(tiles(m)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb,
                        Y + k0, ldy, m, (const int*)nullptr);
-    if (k0 > 0)
-      // rows above: Y[0:k0, :] -= L[k0:k0+kb, 0:k0]^T Y[k0:k0+kb, :]
-      hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), tiles(k0)), dim3(NT), 0, st, k0, m, kb,
-                         L + k0, ldl, (const double*)(Y + k0), ldy, Y, ldy, (const int*)nullptr);
+    if (k0 == 0) break;
+    // block b - 1: Y[k1:k0, :] -= L[k0:k0+kb, k1:k0]^T Y[k0:k0+kb, :], then its solve
+    const int64_t k1 = k0 - NB;
+    hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), 1), dim3(NT), 0, st, (int64_t)NB, m, kb,
+                       L + k0 + k1 * ldl, ldl, (const double*)(Y + k0), ldy, Y + k1, ldy, (const int*)nullptr);
+    hipLaunchKernelGGL((k_trsm_tile<false, true>), dim3(tiles(m)), dim3(64), 0, st, L + k1 + k1 * ldl, ldl, NB,
+                       Y + k1, ldy, m, (const int*)nullptr);
+    if (k1 > 0)
+      // rows above: Y[0:k1, :] -= L[k1:k0+kb, 0:k1]^T Y[k1:k0+kb, :]
+      hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), tiles(k1)), dim3(NT), 0, st, k1, m,
+                         NB + kb, L + k1, ldl, (const double*)(Y + k1), ldy, Y, ldy, (const int*)nullptr);
   }
   prof.end();
   int rc = finish(st, "triangular solve");
