@@ -28,6 +28,7 @@ namespace mrrr_gh {
 constexpr int NB = 64;  // tile order
 constexpr int TK = 16;  // reduction step of the updates staged in LDS
 constexpr int NT = 256; // threads per workgroup of the updates
+constexpr int kPanel = 4; // diagonal blocks per step of the triangular solves
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -369,24 +370,26 @@ static unsigned tiles(int64_t m) { return (unsigned)((m + NB - 1) / NB); }
 // rank-64 update of the rows below
 static void trsm_lower_left(hipStream_t st, int64_t n, int64_t nv, const double* L, int64_t ldl, double* R,
                             int64_t ldr) {
-  // two diagonal blocks per step: the second is brought up to date by the
-  // first (a 64-row update), and the rows below take one rank-128 update, so
-  // the large updates pass over R half as often
-  for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
-    const int kb1 = (int)std::min<int64_t>(NB, n - k0);
-    hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb1,
-                       R + k0, ldr, nv, (const int*)nullptr);
-    const int64_t k1 = k0 + kb1;
-    if (k1 >= n) break;
-    const int kb2 = (int)std::min<int64_t>(NB, n - k1);
-    hipLaunchKernelGGL((k_gemm_sub<false, false, false>), dim3(tiles(nv), 1), dim3(NT), 0, st, (int64_t)kb2, nv, kb1,
-                       L + k1 + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + k1, ldr, (const int*)nullptr);
-    hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + k1 + k1 * ldl, ldl, kb2,
-                       R + k1, ldr, nv, (const int*)nullptr);
-    const int64_t below = n - k1 - kb2;
+  // kPanel diagonal blocks per step: each block's solve is followed by the
+  // update of the panel's remaining rows, and the rows below the panel take
+  // one update of rank 64 kPanel, so the large updates pass over R
+  // 1 / kPanel as often
+  for (int64_t k0 = 0; k0 < n; k0 += kPanel * NB) {
+    const int64_t kend = std::min<int64_t>(n, k0 + kPanel * NB);
+    for (int64_t kb0 = k0; kb0 < kend; kb0 += NB) {
+      const int kb = (int)std::min<int64_t>(NB, kend - kb0);
+      hipLaunchKernelGGL((k_trsm_tile<false, false>), dim3(tiles(nv)), dim3(64), 0, st, L + kb0 + kb0 * ldl, ldl, kb,
+                         R + kb0, ldr, nv, (const int*)nullptr);
+      const int64_t rest = kend - kb0 - kb;
+      if (rest > 0)
+        hipLaunchKernelGGL((k_gemm_sub<false, false, false>), dim3(tiles(nv), tiles(rest)), dim3(NT), 0, st, rest, nv,
+                           kb, L + (kb0 + kb) + kb0 * ldl, ldl, (const double*)(R + kb0), ldr, R + kb0 + kb, ldr,
+                           (const int*)nullptr);
+    }
+    const int64_t below = n - kend;
     if (below > 0)
       hipLaunchKernelGGL((k_gemm_sub<false, false, false>), dim3(tiles(nv), tiles(below)), dim3(NT), 0, st, below, nv,
-                         kb1 + kb2, L + (k1 + kb2) + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + k1 + kb2, ldr,
+                         (int)(kend - k0), L + kend + k0 * ldl, ldl, (const double*)(R + k0), ldr, R + kend, ldr,
                          (const int*)nullptr);
   }
 }
@@ -493,25 +496,28 @@ int mrrr_trsm_lt(int64_t n, int64_t m, const double* L, int64_t ldl, double* Y, 
   std::lock_guard<std::mutex> lk(g_mu);
   mrrr::ProfEvents prof(st);
   prof.begin(MRRR_K_GHEP);
-  // two diagonal blocks per step, last first (as in the forward solve): the
-  // rows above take one rank-(kb + 64) update
+  // kPanel diagonal blocks per step, last first (as in the forward solve):
+  // after each block's solve the panel's blocks above it are updated, and
+  // the rows above the panel take one update of rank up to 64 kPanel
   const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t b = nblk - 1; b >= 0; b -= 2) {
-    const int64_t k0 = b * NB;
-    const int kb = (int)std::min<int64_t>(NB, n - k0);
-    hipLaunchKernelGGL((k_trsm_tile<false, true>), dim3(tiles(m)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb,
-                       Y + k0, ldy, m, (const int*)nullptr);
-    if (k0 == 0) break;
-    // block b - 1: Y[k1:k0, :] -= L[k0:k0+kb, k1:k0]^T Y[k0:k0+kb, :], then its solve
-    const int64_t k1 = k0 - NB;
-    hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), 1), dim3(NT), 0, st, (int64_t)NB, m, kb,
-                       L + k0 + k1 * ldl, ldl, (const double*)(Y + k0), ldy, Y + k1, ldy, (const int*)nullptr);
-    hipLaunchKernelGGL((k_trsm_tile<false, true>), dim3(tiles(m)), dim3(64), 0, st, L + k1 + k1 * ldl, ldl, NB,
-                       Y + k1, ldy, m, (const int*)nullptr);
-    if (k1 > 0)
-      // rows above: Y[0:k1, :] -= L[k1:k0+kb, 0:k1]^T Y[k1:k0+kb, :]
-      hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), tiles(k1)), dim3(NT), 0, st, k1, m,
-                         NB + kb, L + k1, ldl, (const double*)(Y + k1), ldy, Y, ldy, (const int*)nullptr);
+  for (int64_t bt = nblk - 1; bt >= 0; bt -= kPanel) {
+    const int64_t bb = std::max<int64_t>(0, bt - kPanel + 1);  // the panel's first block
+    const int64_t p0 = bb * NB, pend = std::min<int64_t>(n, (bt + 1) * NB);
+    for (int64_t b = bt; b >= bb; --b) {
+      const int64_t k0 = b * NB;
+      const int kb = (int)std::min<int64_t>(NB, n - k0);
+      hipLaunchKernelGGL((k_trsm_tile<false, true>), dim3(tiles(m)), dim3(64), 0, st, L + k0 + k0 * ldl, ldl, kb,
+                         Y + k0, ldy, m, (const int*)nullptr);
+      const int64_t up = k0 - p0;  // panel rows above this block
+      if (up > 0)
+        // Y[p0:k0, :] -= L[k0:k0+kb, p0:k0]^T Y[k0:k0+kb, :]
+        hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), tiles(up)), dim3(NT), 0, st, up, m, kb,
+                           L + k0 + p0 * ldl, ldl, (const double*)(Y + k0), ldy, Y + p0, ldy, (const int*)nullptr);
+    }
+    if (p0 > 0)
+      // rows above: Y[0:p0, :] -= L[p0:pend, 0:p0]^T Y[p0:pend, :]
+      hipLaunchKernelGGL((k_gemm_sub<true, false, false>), dim3(tiles(m), tiles(p0)), dim3(NT), 0, st, p0, m,
+                         (int)(pend - p0), L + p0, ldl, (const double*)(Y + p0), ldy, Y, ldy, (const int*)nullptr);
   }
   prof.end();
   int rc = finish(st, "triangular solve");
