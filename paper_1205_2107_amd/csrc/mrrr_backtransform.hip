@@ -123,41 +123,48 @@ __global__ void __launch_bounds__(NT) k_bt_tfactor(int64_t n, const double* __re
   for (int e = t; e < NB * NB; e += NT) Tb[e] = Ts[e / NB][e % NB];
 }
 
-// Partial products P_s = Z[rows_s, c0 : c0 + 64]^T V_b[rows_s, :] over the
-// s-th chunk of kc rows of block b (rows j0 + 1 + s kc ..), grid (column
-// tiles, chunks).  The accumulator holds D[j][c] (Z column j, reflector c),
-// so the 16 lanes of an MFMA row group write 16 consecutive reflectors.
-// The next chunk's operands are fetched into registers while the matrix
-// cores work on the current one.  P_s is stored as 64 x m (ld 64) at
-// P + s 64 m.
+// Partial products P_s = Z[rows_s, c0 : c0 + 64]^T [V_b .. V_{b+kH-1}][rows_s, :]
+// over the s-th chunk of kc rows from the first block's first row (rows
+// j0 + 1 + s kc ..), grid (column tiles, chunks): kH = 1 one block of 64
+// reflectors, kH = 2 two adjacent blocks read with one pass over Z.  The
+// accumulator holds D[j][c] (Z column j, reflector c), so the 16 lanes of an
+// MFMA row group write 16 consecutive reflectors.  The next chunk's operands
+// are fetched into registers while the matrix cores work on the current one.
+// P_s is stored as 64 kH x m (ld 64 kH) at P + s 64 kH m.
+template <int kH>
 __global__ void __launch_bounds__(NT) k_bt_wpart(int64_t n, int64_t m, const double* __restrict__ V, int64_t ldv,
                                                  const double* __restrict__ Z, int64_t ldz, int b, int64_t kc,
                                                  double* __restrict__ P) {
-  __shared__ double As[NB][TK + 1];  // Z^T: As[j][k] = Z[r0 + k, c0 + j]
-  __shared__ double Bs[NB][TK + 1];  // V_b: Bs[c][k] = v_{j0 + c}[r0 + k]
+  __shared__ double As[NB][TK + 1];       // Z^T: As[j][k] = Z[r0 + k, c0 + j]
+  __shared__ double Bs[kH][NB][TK + 1];   // V: Bs[h][c][k] = v_{j0 + 64 h + c}[r0 + k]
   const int64_t j0 = (int64_t)b * NB;
-  const int nbk = (int)std::min<int64_t>(NB, n - 1 - j0);
   const int64_t c0 = (int64_t)blockIdx.x * NB;
   const int64_t rb = j0 + 1 + (int64_t)blockIdx.y * kc;
   const int64_t re = std::min<int64_t>(n, rb + kc);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  v4d acc[2][2];
+  v4d acc[kH][2][2];
 #pragma unroll
-  for (int mm = 0; mm < 2; ++mm)
+  for (int h = 0; h < kH; ++h)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) acc[mm][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[h][mm][q] = v4d{0.0, 0.0, 0.0, 0.0};
   // thread t loads column / reflector t / 4, rows 4 (t % 4) .. +3 of the chunk
   const int lc = t >> 2, lr = (t & 3) * 4;
   const int64_t cz = c0 + lc;
-  const bool zcol = cz < m, vcol = lc < nbk;
-  double ra[4], rv[4];
+  const bool zcol = cz < m;
+  bool vcol[kH];
+#pragma unroll
+  for (int h = 0; h < kH; ++h) vcol[h] = j0 + NB * h + lc < n - 1;
+  double ra[4], rv[kH][4];
   auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t r = r0 + lr + u;
       ra[u] = (r < re && zcol) ? Z[cz * ldz + r] : 0.0;
-      rv[u] = (r < re && vcol) ? vref(V, ldv, r, j0 + lc) : 0.0;
+#pragma unroll
+      for (int h = 0; h < kH; ++h) rv[h][u] = (r < re && vcol[h]) ? vref(V, ldv, r, j0 + NB * h + lc) : 0.0;
     }
   };
   fetch(rb);
@@ -165,24 +172,28 @@ __global__ void __launch_bounds__(NT) k_bt_wpart(int64_t n, int64_t m, const dou
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       As[lc][lr + u] = ra[u];
-      Bs[lc][lr + u] = rv[u];
+#pragma unroll
+      for (int h = 0; h < kH; ++h) Bs[h][lc][lr + u] = rv[h][u];
     }
     __syncthreads();
     if (r0 + TK < re) fetch(r0 + TK);
-    mma_step(As, Bs, acc, wr, wc, lane);
+#pragma unroll
+    for (int h = 0; h < kH; ++h) mma_step(As, Bs[h], acc[h], wr, wc, lane);
     __syncthreads();
   }
-  double* Ps = P + (int64_t)blockIdx.y * NB * m;
+  double* Ps = P + (int64_t)blockIdx.y * kH * NB * m;
 #pragma unroll
-  for (int mm = 0; mm < 2; ++mm)
+  for (int h = 0; h < kH; ++h)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int mm = 0; mm < 2; ++mm)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t j = c0 + acc_row(wr, mm, lane, v);
-        const int c = acc_col(wc, q, lane);
-        if (j < m) Ps[j * NB + c] = acc[mm][q][v];
-      }
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = c0 + acc_row(wr, mm, lane, v);
+          const int c = acc_col(wc, q, lane);
+          if (j < m) Ps[j * (kH * NB) + NB * h + c] = acc[h][mm][q][v];
+        }
 }
 
 // W[:, c0 : c0 + 64] = T_b (sum_s P_s) for block b (chunks summed in order);
@@ -190,7 +201,7 @@ __global__ void __launch_bounds__(NT) k_bt_wpart(int64_t n, int64_t m, const dou
 // 16 (t % 4) .. +15 (T upper triangular, read from global memory where it is
 // cached for every workgroup of the block).
 __global__ void __launch_bounds__(NT) k_bt_wsum(int64_t m, const double* __restrict__ Tws, int b, int nchunk,
-                                                const double* __restrict__ P, double* __restrict__ W) {
+                                                const double* __restrict__ P, double* __restrict__ W, int64_t ldw) {
   __shared__ double Xs[NB][NB + 1];  // Xs[k][j] = sum_s P_s[k, c0 + j]
   const int64_t c0 = (int64_t)blockIdx.x * NB;
   const int t = threadIdx.x;
@@ -209,8 +220,102 @@ __global__ void __launch_bounds__(NT) k_bt_wsum(int64_t m, const double* __restr
   for (int i = or0; i < or0 + 16; ++i) {
     double x = 0.0;
     for (int k = i; k < NB; ++k) x += Tb[i * NB + k] * Xs[k][oc];
-    if (cz < m) W[cz * NB + i] = x;
+    if (cz < m) W[cz * ldw + i] = x;
   }
+}
+
+// Two adjacent blocks b, b + 1 applied as one block of 128 reflectors:
+// I - [V0 V1] T [V0 V1]^T with T = [[T0, -T0 C T1], [0, T1]], C = V0^T V1, so
+// W = T X for X = [V0 V1]^T Z is W1 = T1 X1 and W0 = T0 (X0 - C W1).
+// X = the sum of the chunks of the two-block partial products (P_s 128 x m,
+// ld 128); W is 128 x m (ld 128).  32 columns per workgroup, eight threads a
+// column, each 16 rows of a half.
+__global__ void __launch_bounds__(NT) k_bt_wsum2(int64_t m, const double* __restrict__ Tws, int b, int nchunk,
+                                                 const double* __restrict__ P, const double* __restrict__ Cws,
+                                                 double* __restrict__ W) {
+  __shared__ double Xs[2 * NB][33];  // Xs[k][j] = sum_s P_s[k, c0 + j]; rows 0..63 later hold X0 - C W1
+  __shared__ double W1s[NB][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32;
+  const int t = threadIdx.x;
+  for (int e = t; e < 2 * NB * 32; e += NT) {
+    const int k = e % (2 * NB), j = e / (2 * NB);
+    const int64_t cz = c0 + j;
+    double x = 0.0;
+    if (cz < m)
+      for (int s = 0; s < nchunk; ++s) x += P[(int64_t)s * 2 * NB * m + cz * 2 * NB + k];
+    Xs[k][j] = x;
+  }
+  __syncthreads();
+  const double* T0 = Tws + (int64_t)b * NB * NB;
+  const double* T1 = Tws + (int64_t)(b + 1) * NB * NB;
+  const double* C = Cws + (int64_t)b * NB * NB;
+  const int oc = t >> 3, part = t & 7;
+  const int64_t cz = c0 + oc;
+  if (part >= 4) {  // W1 = T1 X1
+    const int r0 = (part - 4) * 16;
+    for (int i = r0; i < r0 + 16; ++i) {
+      double x = 0.0;
+      for (int k = i; k < NB; ++k) x += T1[i * NB + k] * Xs[NB + k][oc];
+      W1s[i][oc] = x;
+      if (cz < m) W[cz * 2 * NB + NB + i] = x;
+    }
+  }
+  __syncthreads();
+  if (part < 4) {  // X0 - C W1
+    const int r0 = part * 16;
+    for (int i = r0; i < r0 + 16; ++i) {
+      double x = Xs[i][oc];
+      for (int k = 0; k < NB; ++k) x -= C[i * NB + k] * W1s[k][oc];
+      Xs[i][oc] = x;
+    }
+  }
+  __syncthreads();
+  if (part < 4) {  // W0 = T0 (X0 - C W1)
+    const int r0 = part * 16;
+    for (int i = r0; i < r0 + 16; ++i) {
+      double x = 0.0;
+      for (int k = i; k < NB; ++k) x += T0[i * NB + k] * Xs[k][oc];
+      if (cz < m) W[cz * 2 * NB + i] = x;
+    }
+  }
+}
+
+// C_b = V_b^T V_{b+1} (64 x 64 row-major, rows of V_{b+1}'s nonzero part) for
+// every adjacent pair of blocks, one workgroup per pair
+__global__ void __launch_bounds__(NT) k_bt_cross(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                 double* __restrict__ Cws) {
+  __shared__ double As[NB][TK + 1];
+  __shared__ double Bs[NB][TK + 1];
+  const int b = blockIdx.x;
+  const int64_t nref = n - 1;
+  const int64_t j0 = (int64_t)b * NB, j1 = j0 + NB;
+  const int nb0 = (int)std::min<int64_t>(NB, nref - j0), nb1 = (int)std::min<int64_t>(NB, nref - j1);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v4d acc[2][2];
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[mm][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int lc = t >> 2, lr = (t & 3) * 4;
+  for (int64_t r0 = j1 + 1; r0 < n; r0 += TK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = r0 + lr + u;
+      As[lc][lr + u] = (r < n && lc < nb0) ? vref(V, ldv, r, j0 + lc) : 0.0;
+      Bs[lc][lr + u] = (r < n && lc < nb1) ? vref(V, ldv, r, j1 + lc) : 0.0;
+    }
+    __syncthreads();
+    mma_step(As, Bs, acc, wr, wc, lane);
+    __syncthreads();
+  }
+  double* Cb = Cws + (int64_t)b * NB * NB;
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cb[acc_row(wr, mm, lane, v) * NB + acc_col(wc, q, lane)] = acc[mm][q][v];
 }
 
 // One 64 x 64 x 64 product from operands held whole in LDS in k-major
@@ -241,10 +346,12 @@ __device__ inline void mma_tile64(const double (*At)[NB], const double (*Bt)[NB]
 // row i), so the 16 lanes of an MFMA row group update 16 consecutive rows of
 // one column.  Workgroup L runs on XCD L mod 8 (round-robin dispatch); each
 // XCD takes its own contiguous share of the column groups, so the slice of W
-// its tiles read stays in that XCD's L2.  ncx column groups per XCD.
+// its tiles read stays in that XCD's L2.  ncx column groups per XCD; rows at
+// or beyond rend are left alone; W has leading dimension ldw.
 __global__ void __launch_bounds__(NT) k_bt_update(int64_t n, int64_t m, const double* __restrict__ V, int64_t ldv,
                                                   double* __restrict__ Z, int64_t ldz, int b,
-                                                  const double* __restrict__ W, int ncx, int ngroups) {
+                                                  const double* __restrict__ W, int64_t ldw, int64_t rend, int ncx,
+                                                  int ngroups) {
   __shared__ double Vt[NB][NB];  // Vt[k][i] = v_{j0 + k}[i0 + i]
   __shared__ double Wt[NB][NB];  // Wt[k][j] = W[k, c0 + j]
   const int xcd = (int)(blockIdx.x % kXcds), local = (int)(blockIdx.x / kXcds);
@@ -261,7 +368,7 @@ __global__ void __launch_bounds__(NT) k_bt_update(int64_t n, int64_t m, const do
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int64_t r = i0 + ib + u;
-      Vt[k][ib + u] = (r < n && k < nbk) ? vref(V, ldv, r, j0 + k) : 0.0;
+      Vt[k][ib + u] = (r < rend && k < nbk) ? vref(V, ldv, r, j0 + k) : 0.0;
     }
   }
   // W block: thread t reads column t / 4, reflectors 16 (t % 4) .. +15
@@ -271,7 +378,7 @@ __global__ void __launch_bounds__(NT) k_bt_update(int64_t n, int64_t m, const do
   auto fetch = [&](int64_t c0) {
     const int64_t cz = c0 + wj;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) wr_[u] = (cz < m && wk + u < nbk) ? W[cz * NB + wk + u] : 0.0;
+    for (int u = 0; u < 16; ++u) wr_[u] = (cz < m && wk + u < nbk) ? W[cz * ldw + wk + u] : 0.0;
 #pragma unroll
     for (int mm = 0; mm < 2; ++mm)
 #pragma unroll
@@ -280,7 +387,7 @@ __global__ void __launch_bounds__(NT) k_bt_update(int64_t n, int64_t m, const do
         for (int v = 0; v < 4; ++v) {
           const int64_t j = c0 + acc_row(wr, mm, lane, v);
           const int64_t r = i0 + acc_col(wc, q, lane);
-          zr[mm][q][v] = (r < n && j < m) ? Z[j * ldz + r] : 0.0;
+          zr[mm][q][v] = (r < rend && j < m) ? Z[j * ldz + r] : 0.0;
         }
   };
   fetch(cbeg);
@@ -312,7 +419,7 @@ __global__ void __launch_bounds__(NT) k_bt_update(int64_t n, int64_t m, const do
         for (int v = 0; v < 4; ++v) {
           const int64_t j = c0 + acc_row(wr, mm, lane, v);
           const int64_t r = i0 + acc_col(wc, q, lane);
-          if (r < n && j < m) Z[j * ldz + r] = zc[mm][q][v] - acc[mm][q][v];
+          if (r < rend && j < m) Z[j * ldz + r] = zc[mm][q][v] - acc[mm][q][v];
         }
     __syncthreads();
   }
@@ -353,6 +460,73 @@ static int grow(size_t bytes) {
 
 using namespace mrrr_bt;
 
+// Z[r, :] -= V[r, j0 : j0 + 128] W (W 128 x m, ld 128) for the rows r >= rb
+// where both blocks' reflectors are stored entries of V (no unit or zero
+// entries formed), one 64 x 64 tile of Z per workgroup (grid x column tiles,
+// y row tiles); K = 128 in steps of TK with the next step's operands fetched
+// into registers while the matrix cores work, the lane's Z entries fetched
+// before the products; 16 lanes of an MFMA row group update 16 consecutive
+// rows of one column.
+__global__ void __launch_bounds__(NT) k_bt_rank128(int64_t n, int64_t m, const double* __restrict__ V, int64_t ldv,
+                                                   int64_t j0, int64_t rb, const double* __restrict__ W,
+                                                   double* __restrict__ Z, int64_t ldz) {
+  __shared__ double Ps[NB][TK + 1];  // Ps[i][k] = V[rb + I 64 + i, j0 + k0 + k]
+  __shared__ double Qs[NB][TK + 1];  // Qs[j][k] = W[k0 + k, c0 + j]
+  const int64_t i0 = rb + (int64_t)blockIdx.y * NB, c0 = (int64_t)blockIdx.x * NB;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v4d acc[2][2];
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[mm][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  double zc[2][2][4];
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = c0 + acc_row(wr, mm, lane, v);
+        const int64_t r = i0 + acc_col(wc, q, lane);
+        zc[mm][q][v] = (r < n && j < m) ? Z[j * ldz + r] : 0.0;
+      }
+  // loaders: V rows contiguous over threads; W reflectors contiguous over threads
+  double rp[4], rq[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ia = t & 63, ka = (t >> 6) * 4 + u;
+      const int kb = t & 15, jb = (t >> 4) + 16 * u;
+      const int64_t r = i0 + ia, c = c0 + jb;
+      rp[u] = r < n ? V[(j0 + k0 + ka) * ldv + r] : 0.0;
+      rq[u] = c < m ? W[c * 2 * NB + k0 + kb] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < 2 * NB; k0 += TK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      Ps[t & 63][(t >> 6) * 4 + u] = rp[u];
+      Qs[(t >> 4) + 16 * u][t & 15] = rq[u];
+    }
+    __syncthreads();
+    if (k0 + TK < 2 * NB) fetch(k0 + TK);
+    mma_step(Qs, Ps, acc, wr, wc, lane);  // D[j][i]: Z column j, row i
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = c0 + acc_row(wr, mm, lane, v);
+        const int64_t r = i0 + acc_col(wc, q, lane);
+        if (r < n && j < m) Z[j * ldz + r] = zc[mm][q][v] - acc[mm][q][v];
+      }
+}
+
 extern "C" {
 
 int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const double* tau, double* Z,
@@ -375,30 +549,64 @@ int mrrr_backtransform(int64_t n, int64_t m, const double* V, int64_t ldv, const
   const int64_t maxch = (nref + kc - 1) / kc;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t tbytes = al(sizeof(double) * (size_t)(nblk * NB * NB));
-  const size_t wbytes = al(sizeof(double) * (size_t)(NB * m));
-  const size_t pbytes = sizeof(double) * (size_t)(maxch * NB * m);
-  int rc = grow(tbytes + wbytes + pbytes);
+  const size_t cbytes = al(sizeof(double) * (size_t)(std::max<int64_t>(nblk - 1, 1) * NB * NB));
+  const size_t wbytes = al(sizeof(double) * (size_t)(2 * NB * m));
+  const size_t pbytes = sizeof(double) * (size_t)(maxch * 2 * NB * m);
+  int rc = grow(tbytes + cbytes + wbytes + pbytes);
   if (rc) return rc;
   double* Tws = (double*)g_ws;
-  double* W = (double*)((char*)g_ws + tbytes);
-  double* P = (double*)((char*)g_ws + tbytes + wbytes);
+  double* Cws = (double*)((char*)g_ws + tbytes);
+  double* W = (double*)((char*)g_ws + tbytes + cbytes);
+  double* P = (double*)((char*)g_ws + tbytes + cbytes + wbytes);
   mrrr::ProfEvents prof(st);
   prof.begin(MRRR_K_BACKTRANSFORM);
   hipLaunchKernelGGL(k_bt_tfactor, dim3((unsigned)nblk), dim3(NT), 0, st, n, V, ldv, tau, Tws);
+  if (nblk > 1) hipLaunchKernelGGL(k_bt_cross, dim3((unsigned)(nblk - 1)), dim3(NT), 0, st, n, V, ldv, Cws);
   const unsigned ct = (unsigned)((m + NB - 1) / NB);
-  for (int64_t b = nblk - 1; b >= 0; --b) {
+  const int ngroups = (int)((ct + kUpdCols - 1) / kUpdCols);
+  const int ncx = (ngroups + kXcds - 1) / kXcds;
+  // the update of block b over rows j0 + 1 .. rend - 1 (W with leading dimension ldw)
+  auto update = [&](int64_t b, const double* Wb, int64_t ldw, int64_t rend) {
+    const int64_t rows = rend - (b * NB + 1);
+    if (rows <= 0) return;
+    const int64_t rt = (rows + NB - 1) / NB;
+    hipLaunchKernelGGL(k_bt_update, dim3((unsigned)(kXcds * ncx * rt)), dim3(NT), 0, st, n, m, V, ldv, Z, ldz, (int)b,
+                       Wb, ldw, rend, ncx, ngroups);
+  };
+  // one block of 64 reflectors: three passes over its rows of Z
+  auto single = [&](int64_t b) {
     const int64_t rows = n - 1 - b * NB;
     const int64_t nch = (rows + kc - 1) / kc;
-    hipLaunchKernelGGL(k_bt_wpart, dim3(ct, (unsigned)nch), dim3(NT), 0, st, n, m, V, ldv, (const double*)Z, ldz,
+    hipLaunchKernelGGL(k_bt_wpart<1>, dim3(ct, (unsigned)nch), dim3(NT), 0, st, n, m, V, ldv, (const double*)Z, ldz,
                        (int)b, kc, P);
     hipLaunchKernelGGL(k_bt_wsum, dim3(ct), dim3(NT), 0, st, m, (const double*)Tws, (int)b, (int)nch,
-                       (const double*)P, W);
-    const int64_t rt = (rows + NB - 1) / NB;
-    const int ngroups = (int)((ct + kUpdCols - 1) / kUpdCols);
-    const int ncx = (ngroups + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(k_bt_update, dim3((unsigned)(kXcds * ncx * rt)), dim3(NT), 0, st, n, m, V, ldv, Z, ldz, (int)b,
-                       (const double*)W, ncx, ngroups);
-  }
+                       (const double*)P, W, (int64_t)NB);
+    update(b, W, NB, n);
+  };
+  // blocks b, b + 1 (both full) as one block of 128: the same three passes
+  // for both; the first 128 rows (unit and zero entries of the reflectors)
+  // by the one-block update, the rows below by one rank-128 update
+  auto pair = [&](int64_t b) {
+    const int64_t j0 = b * NB;
+    const int64_t rows = n - 1 - j0;
+    const int64_t nch = (rows + kc - 1) / kc;
+    hipLaunchKernelGGL(k_bt_wpart<2>, dim3(ct, (unsigned)nch), dim3(NT), 0, st, n, m, V, ldv, (const double*)Z, ldz,
+                       (int)b, kc, P);
+    hipLaunchKernelGGL(k_bt_wsum2, dim3((unsigned)((m + 31) / 32)), dim3(NT), 0, st, m, (const double*)Tws, (int)b,
+                       (int)nch, (const double*)P, (const double*)Cws, W);
+    const int64_t rtop = std::min<int64_t>(n, j0 + 1 + 2 * NB);
+    update(b, W, 2 * NB, rtop);
+    update(b + 1, W + NB, 2 * NB, rtop);
+    if (rtop < n)
+      hipLaunchKernelGGL(k_bt_rank128, dim3(ct, (unsigned)((n - rtop + NB - 1) / NB)), dim3(NT), 0, st, n, m, V, ldv,
+                         j0, rtop, (const double*)W, Z, ldz);
+  };
+  // last block first; pairs of full blocks, a ragged last block and an odd
+  // first block alone
+  int64_t b = nblk - 1;
+  if (nref - b * NB < NB) single(b--);
+  for (; b >= 1; b -= 2) pair(b - 1);
+  if (b == 0) single(0);
   prof.end();
   hipError_t e = hipStreamSynchronize(st);
   if (e == hipSuccess) e = hipGetLastError();
