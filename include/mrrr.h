@@ -386,9 +386,9 @@ int mrrr_tridiagonalize(int64_t n, double* A, int64_t lda, double* d, double* e,
  * x = L^{-T} y.  With mrrr_tridiagonalize, mrrr_step and mrrr_backtransform
  * in between they form the dense generalized eigensolver.  All matrices are
  * device, column-major, blocked in 64 x 64 tiles (triangular solves with one
- * diagonal block per lane vector, rank-64 updates on FP64 matrix cores);
- * calls synchronize the stream before returning and are serialized by a
- * lock per function family.  n <= 2^18.
+ * diagonal block per lane vector, updates of rank 64 to 256 on FP64 matrix
+ * cores); calls synchronize the stream before returning and are serialized
+ * by a lock per function family.  n <= 2^18.
  *
  * mrrr_cholesky: B (n x n, leading dimension ldb): the lower triangle holds B
  * on entry and L on return; the strict upper triangle is not referenced.

@@ -9,9 +9,11 @@
 //
 // All three are blocked in 64 x 64 tiles: a triangular solve with one
 // diagonal block of L, one RHS vector per lane, the block staged in LDS
-// (k_trsm_tile), and a rank-64 update of everything below (or above) it on
-// FP64 matrix cores (k_gemm_sub).  The Cholesky factorization adds the
-// factorization of its diagonal blocks (k_chol_diag, one wavefront).
+// (k_trsm_tile), and updates of everything below (or above) it on FP64
+// matrix cores (k_gemm_sub; the triangular solves take four diagonal blocks
+// per step, so the large updates are of rank 256).  The Cholesky
+// factorization adds the factorization of its diagonal blocks (k_chol_diag,
+// one wavefront) and rank-64 trailing updates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -366,8 +368,7 @@ static int finish(hipStream_t st, const char* what) {
 
 static unsigned tiles(int64_t m) { return (unsigned)((m + NB - 1) / NB); }
 
-// R (n x nv) <- L^{-1} R, L lower n x n: per diagonal block a solve, then the
-// rank-64 update of the rows below
+// R (n x nv) <- L^{-1} R, L lower n x n
 static void trsm_lower_left(hipStream_t st, int64_t n, int64_t nv, const double* L, int64_t ldl, double* R,
                             int64_t ldr) {
   // kPanel diagonal blocks per step: each block's solve is followed by the
