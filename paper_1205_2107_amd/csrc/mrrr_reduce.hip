@@ -80,6 +80,16 @@ __device__ double block_reduce(double x, double* sh) {
   return r;
 }
 
+// the sum of the partials S[0 .. nS) by the first wavefront (every lane
+// gets it): lane l adds S[l], S[l + 64], ... in order, then the lanes in a
+// fixed tree
+__device__ __forceinline__ double sum_partials(const double* __restrict__ S, int nS) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nS; b += 64) s += S[b];
+  return wave_sum(s);
+}
+
 // two maxima over the workgroup with one pair of barriers; every thread gets both
 __device__ void block_max2(double& x, double& y, double* sh, double* sh2) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -118,10 +128,9 @@ __global__ void __launch_bounds__(NTC) k_tr_col(int64_t n, double* __restrict__ 
   // the diagonal (mx) and below the subdiagonal (mt) in one pass
   double mx = 0.0, mt = 0.0;
   if (j > 0) {
-    if (t == 0) {
-      double s = 0.0;
-      for (int b = 0; b < nS; ++b) s += S[b];
-      s_alpha = -0.5 * tau[i - 1] * s;
+    if (t < 64) {
+      const double s = sum_partials(S, nS);
+      if (t == 0) s_alpha = -0.5 * tau[i - 1] * s;
     }
     __syncthreads();
     const double al = s_alpha;
@@ -419,10 +428,9 @@ __global__ void __launch_bounds__(NT) k_tr_wfin(int64_t n, int64_t i, int j, con
                                                 double* __restrict__ Wp, const double* __restrict__ S, int nS,
                                                 const double* __restrict__ tau) {
   __shared__ double s_alpha;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nS; ++b) s += S[b];
-    s_alpha = -0.5 * tau[i] * s;
+  if (threadIdx.x < 64) {
+    const double s = sum_partials(S, nS);
+    if (threadIdx.x == 0) s_alpha = -0.5 * tau[i] * s;
   }
   __syncthreads();
   const int64_t r = i + 1 + (int64_t)blockIdx.x * NT + threadIdx.x;
