@@ -435,6 +435,18 @@ int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t l
 int mrrr_sygv(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, double* w, double* Z, int64_t ldz,
               int64_t* not_pd, mrrr_info* info, void* stream);
 
+/* The same drivers for a subset of the eigenpairs (range as for mrrr_step:
+ * all, an index range il..iu, or the values in (vl, vu]; for mrrr_sygvr the
+ * generalized eigenvalues, which are those of the standard problem).  Only
+ * the info->m computed eigenvectors are back-transformed, in the first
+ * info->m columns of Z (room for n columns with a value range).  Returns as
+ * mrrr_syev and mrrr_sygv with the range as argument 4 (mrrr_syevr: -4 on a
+ * bad kind, later arguments numbered one higher) and 6 (mrrr_sygvr). */
+int mrrr_syevr(int64_t n, double* A, int64_t lda, mrrr_range range, double* w, double* Z, int64_t ldz,
+               mrrr_info* info, void* stream);
+int mrrr_sygvr(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, mrrr_range range, double* w, double* Z,
+               int64_t ldz, int64_t* not_pd, mrrr_info* info, void* stream);
+
 /* Arithmetic probe: the reciprocal and quotient forms the kernels use, on
  * caller-given operands (no solve; for tests of their rounding).  a, b: device
  * arrays of n doubles; out: device array of 4 n doubles, written as

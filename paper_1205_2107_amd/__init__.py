@@ -502,32 +502,36 @@ def trsm_lt(L, Y, stream=None):
     return Yd
 
 
-def eigh_dense(A, stream=None):
-    """All eigenpairs of the dense symmetric A (lower triangle read) through
-    the library's driver mrrr_syev: reduction to tridiagonal form, the MRRR
-    tridiagonal eigensolver, back-transformation, all on the GPU.  A is
-    overwritten when it is a column-major float64 device tensor.  Returns
-    (w ascending, Z column-major)."""
+def eigh_dense(A, select="a", il=None, iu=None, vl=None, vu=None, stream=None):
+    """Eigenpairs of the dense symmetric A (lower triangle read) through the
+    library's driver mrrr_syevr: reduction to tridiagonal form, the MRRR
+    tridiagonal eigensolver for the selected eigenpairs (select as for
+    eigh_tridiagonal), back-transformation of those vectors only, all on the
+    GPU.  A is overwritten when it is a column-major float64 device tensor.
+    Returns (w ascending, Z column-major, one column per eigenvalue)."""
     torch = _torch()
     dev = _dev_of(A)
     Ad = _dense_colmajor(A, dev, square=True)
     n = Ad.shape[0]
+    rng, m = _range(select, il, iu, vl, vu, n)
     w = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
-    Z = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+    Z = torch.empty((max(m, 1), max(n, 1)), dtype=torch.float64, device=dev)
     info = MrrrInfo()
     with torch.cuda.device(dev):
-        _lib.check(_lib.load().mrrr_syev(n, _ptr(Ad), _ld(Ad), _ptr(w), _ptr(Z), max(n, 1), ctypes.byref(info),
-                                          _stream_ptr(stream)))
-    return w[:n], Z[:n, :n].t()
+        _lib.check(_lib.load().mrrr_syevr(n, _ptr(Ad), _ld(Ad), rng, _ptr(w), _ptr(Z), max(n, 1), ctypes.byref(info),
+                                           _stream_ptr(stream)))
+    mm = int(info.m) if n > 0 else 0
+    return w[:mm], Z[:mm, :n].t()
 
 
-def eigh_generalized(A, B, stream=None):
-    """All eigenpairs of A x = lambda B x (A symmetric, B symmetric positive
-    definite, lower triangles read) through the library's driver mrrr_sygv,
+def eigh_generalized(A, B, select="a", il=None, iu=None, vl=None, vu=None, stream=None):
+    """Eigenpairs of A x = lambda B x (A symmetric, B symmetric positive
+    definite, lower triangles read) through the library's driver mrrr_sygvr,
     every stage on the GPU: Cholesky factorization, reduction to standard
-    form, reduction to tridiagonal form, the MRRR tridiagonal eigensolver,
-    and both back-transformations.  A and B are overwritten when they are
-    column-major float64 device tensors.  Returns (w ascending, X
+    form, reduction to tridiagonal form, the MRRR tridiagonal eigensolver for
+    the selected eigenpairs (select as for eigh_tridiagonal), and both
+    back-transformations of those vectors.  A and B are overwritten when they
+    are column-major float64 device tensors.  Returns (w ascending, X
     column-major with X^T B X = I); raises when B is not positive definite."""
     torch = _torch()
     dev = _dev_of(A)
@@ -536,16 +540,18 @@ def eigh_generalized(A, B, stream=None):
     if Bd.shape != Ad.shape:
         raise ValueError("A and B must have one order")
     n = Ad.shape[0]
+    rng, m = _range(select, il, iu, vl, vu, n)
     w = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
-    X = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+    X = torch.empty((max(m, 1), max(n, 1)), dtype=torch.float64, device=dev)
     bad = ctypes.c_int64(0)
     info = MrrrInfo()
     with torch.cuda.device(dev):
-        _lib.check(_lib.load().mrrr_sygv(n, _ptr(Ad), _ld(Ad), _ptr(Bd), _ld(Bd), _ptr(w), _ptr(X), max(n, 1),
-                                          ctypes.byref(bad), ctypes.byref(info), _stream_ptr(stream)))
+        _lib.check(_lib.load().mrrr_sygvr(n, _ptr(Ad), _ld(Ad), _ptr(Bd), _ld(Bd), rng, _ptr(w), _ptr(X), max(n, 1),
+                                           ctypes.byref(bad), ctypes.byref(info), _stream_ptr(stream)))
     if bad.value:
         raise ValueError(f"B not positive definite (pivot of column {bad.value})")
-    return w[:n], X[:n, :n].t()
+    mm = int(info.m) if n > 0 else 0
+    return w[:mm], X[:mm, :n].t()
 
 
 def probe_division(a, b, stream=None):

@@ -18,7 +18,7 @@ EXPORTS = ("mrrr_step", "mrrr_step_batched", "mrrr_step_backward", "mrrr_step_ba
            "mrrr_step_ws", "mrrr_get_limits", "mrrr_set_limits", "mrrr_step_noalloc",
            "mrrr_probe_division", "mrrr_backtransform", "mrrr_tridiagonalize",
            "mrrr_cholesky", "mrrr_sygst", "mrrr_trsm_lt", "mrrr_step_f32",
-           "mrrr_syev", "mrrr_sygv")
+           "mrrr_syev", "mrrr_sygv", "mrrr_syevr", "mrrr_sygvr")
 KERNELS = ("grid", "refine", "child", "vectors", "backward", "vectors_ckpt", "backtransform", "tridiag", "ghep")
 
 
@@ -98,6 +98,10 @@ def load():
     lib.mrrr_syev.argtypes = [I64, P, I64, P, P, I64, ctypes.POINTER(MrrrInfo), P]
     lib.mrrr_sygv.restype = ctypes.c_int
     lib.mrrr_sygv.argtypes = [I64, P, I64, P, I64, P, P, I64, PI64, ctypes.POINTER(MrrrInfo), P]
+    lib.mrrr_syevr.restype = ctypes.c_int
+    lib.mrrr_syevr.argtypes = [I64, P, I64, MrrrRange, P, P, I64, ctypes.POINTER(MrrrInfo), P]
+    lib.mrrr_sygvr.restype = ctypes.c_int
+    lib.mrrr_sygvr.argtypes = [I64, P, I64, P, I64, MrrrRange, P, P, I64, PI64, ctypes.POINTER(MrrrInfo), P]
     lib.mrrr_probe_division.restype = ctypes.c_int
     lib.mrrr_probe_division.argtypes = [I64, P, P, P, P]
     lib.mrrr_get_limits.restype = ctypes.c_int

@@ -567,14 +567,16 @@ static int drv_buffers(int64_t n, double** d, double** e, double** tau) {
   return 0;
 }
 
-int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t ldz, mrrr_info* info, void* stream) {
+int mrrr_syevr(int64_t n, double* A, int64_t lda, mrrr_range range, double* w, double* Z, int64_t ldz,
+                mrrr_info* info, void* stream) {
   if (info) memset(info, 0, sizeof(*info));
   if (n < 0 || n > (int64_t)1 << 18) return -1;
   if (n > 0 && !A) return -2;
   if (lda < std::max<int64_t>(1, n)) return -3;
-  if (n > 0 && !w) return -4;
-  if (n > 0 && !Z) return -5;
-  if (ldz < std::max<int64_t>(1, n)) return -6;
+  if (range.kind < MRRR_ALL || range.kind > MRRR_VALUE) return -4;
+  if (n > 0 && !w) return -5;
+  if (n > 0 && !Z) return -6;
+  if (ldz < std::max<int64_t>(1, n)) return -7;
   if (n == 0) return 0;
   std::lock_guard<std::mutex> lk(g_drv_mu);
   double *d, *e, *tau;
@@ -582,35 +584,55 @@ int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t l
   if (rc) return rc;
   rc = mrrr_tridiagonalize(n, A, lda, d, e, tau, stream);
   if (rc) return rc;
+  mrrr_info inf;
+  rc = mrrr_step(n, d, e, range, w, Z, ldz, &inf, stream);
+  if (info) *info = inf;
+  if (rc) return rc;
+  // only the m computed eigenvectors are transformed
+  return mrrr_backtransform(n, inf.m, A, lda, tau, Z, ldz, stream);
+}
+
+int mrrr_syev(int64_t n, double* A, int64_t lda, double* w, double* Z, int64_t ldz, mrrr_info* info, void* stream) {
   mrrr_range all;
   memset(&all, 0, sizeof(all));
   all.kind = MRRR_ALL;
-  rc = mrrr_step(n, d, e, all, w, Z, ldz, info, stream);
-  if (rc) return rc;
-  return mrrr_backtransform(n, n, A, lda, tau, Z, ldz, stream);
+  const int rc = mrrr_syevr(n, A, lda, all, w, Z, ldz, info, stream);
+  return rc <= -5 ? rc + 1 : rc;  // argument numbers without the range
 }
 
-int mrrr_sygv(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, double* w, double* Z, int64_t ldz,
-              int64_t* not_pd, mrrr_info* info, void* stream) {
+int mrrr_sygvr(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, mrrr_range range, double* w, double* Z,
+               int64_t ldz, int64_t* not_pd, mrrr_info* info, void* stream) {
   if (info) memset(info, 0, sizeof(*info));
   if (n < 0 || n > (int64_t)1 << 18) return -1;
   if (n > 0 && !A) return -2;
   if (lda < std::max<int64_t>(1, n)) return -3;
   if (n > 0 && !B) return -4;
   if (ldb < std::max<int64_t>(1, n)) return -5;
-  if (n > 0 && !w) return -6;
-  if (n > 0 && !Z) return -7;
-  if (ldz < std::max<int64_t>(1, n)) return -8;
-  if (!not_pd) return -9;
+  if (range.kind < MRRR_ALL || range.kind > MRRR_VALUE) return -6;
+  if (n > 0 && !w) return -7;
+  if (n > 0 && !Z) return -8;
+  if (ldz < std::max<int64_t>(1, n)) return -9;
+  if (!not_pd) return -10;
   *not_pd = 0;
   if (n == 0) return 0;
   int rc = mrrr_cholesky(n, B, ldb, not_pd, stream);
   if (rc || *not_pd) return rc;
   rc = mrrr_sygst(n, A, lda, B, ldb, stream);
   if (rc) return rc;
-  rc = mrrr_syev(n, A, lda, w, Z, ldz, info, stream);
+  mrrr_info inf;
+  rc = mrrr_syevr(n, A, lda, range, w, Z, ldz, &inf, stream);
+  if (info) *info = inf;
   if (rc) return rc;
-  return mrrr_trsm_lt(n, n, B, ldb, Z, ldz, stream);
+  return mrrr_trsm_lt(n, inf.m, B, ldb, Z, ldz, stream);
+}
+
+int mrrr_sygv(int64_t n, double* A, int64_t lda, double* B, int64_t ldb, double* w, double* Z, int64_t ldz,
+              int64_t* not_pd, mrrr_info* info, void* stream) {
+  mrrr_range all;
+  memset(&all, 0, sizeof(all));
+  all.kind = MRRR_ALL;
+  const int rc = mrrr_sygvr(n, A, lda, B, ldb, all, w, Z, ldz, not_pd, info, stream);
+  return rc <= -7 ? rc + 1 : rc;  // argument numbers without the range
 }
 
 }  // extern "C"

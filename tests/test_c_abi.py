@@ -252,3 +252,20 @@ def test_dense_driver_argument_checks():
     assert lib.mrrr_sygv(4, fake, 4, fake, 3, fake, fake, 4, ctypes.byref(bad), None, None) == -5
     assert lib.mrrr_sygv(4, fake, 4, fake, 4, fake, fake, 4, None, None, None) == -9
     assert lib.mrrr_sygv(0, None, 1, None, 1, None, None, 1, ctypes.byref(bad), None, None) == 0 and bad.value == 0
+
+
+def test_subset_driver_argument_checks():
+    from paper_1205_2107_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(16)
+    bad = ctypes.c_int64(0)
+    rng = _lib.MrrrRange()
+    rng.kind = 7
+    assert lib.mrrr_syevr(4, fake, 4, rng, fake, fake, 4, None, None) == -4
+    rng.kind = _lib.MRRR_ALL
+    assert lib.mrrr_syevr(4, fake, 4, rng, None, fake, 4, None, None) == -5
+    assert lib.mrrr_syevr(4, fake, 4, rng, fake, fake, 3, None, None) == -7
+    rng.kind = 9
+    assert lib.mrrr_sygvr(4, fake, 4, fake, 4, rng, fake, fake, 4, ctypes.byref(bad), None, None) == -6
+    rng.kind = _lib.MRRR_ALL
+    assert lib.mrrr_sygvr(4, fake, 4, fake, 4, rng, fake, fake, 4, None, None, None) == -10

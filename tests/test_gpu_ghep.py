@@ -201,3 +201,33 @@ def test_leading_dimensions_and_nonfinite_input(M):
     # the library stays usable
     w3, X3 = M.eigh_generalized(dev_lower(A), dev_lower(B))
     assert torch.equal(w1, w3)
+
+
+def test_dense_drivers_on_subsets(M):
+    # index and value ranges: only the selected eigenvectors are computed and
+    # back-transformed; they are eigenpairs of the dense (generalized) problem
+    n = 300
+    A = W.dense_symmetric(n, 2300)
+    B = W.dense_spd(n, 2301)
+    wl = np.linalg.eigvalsh(A)
+    norm1 = np.abs(A).sum(axis=0).max()
+    w, Z = M.eigh_dense(dev_lower(A), select="i", il=50, iu=120)
+    w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    assert w.shape == (71,) and Z.shape == (n, 71)
+    assert np.abs(w - wl[49:120]).max() <= 2 * n * EPS * norm1
+    assert np.linalg.norm(A @ Z - Z * w[None, :], axis=0).max() <= 10 * n * EPS * norm1
+    assert np.abs(Z.T @ Z - np.eye(71)).max() <= 30 * n * EPS
+    vl, vu = float(wl[199]) + 1e-9, float(wl[260]) + 1e-9
+    w, Z = M.eigh_dense(dev_lower(A), select="v", vl=vl, vu=vu)
+    assert w.shape == (61,) and Z.shape == (n, 61)
+    assert np.abs(w.cpu().numpy() - wl[200:261]).max() <= 2 * n * EPS * norm1
+    scipy_linalg = pytest.importorskip("scipy.linalg")
+    wg = scipy_linalg.eigh(A, B, eigvals_only=True)
+    w, X = M.eigh_generalized(dev_lower(A), dev_lower(B), select="i", il=1, iu=40)
+    w, X = w.cpu().numpy(), X.cpu().numpy()
+    kappa = np.linalg.cond(B)
+    normA = np.abs(wl).max()
+    assert np.abs(w - wg[:40]).max() <= 20 * n * EPS * normA * kappa
+    R = A @ X - (B @ X) * w[None, :]
+    assert np.abs(R).max() <= 20 * n * EPS * normA * kappa * np.abs(X).max()
+    assert np.abs(X.T @ B @ X - np.eye(40)).max() <= 20 * n * EPS * kappa
