@@ -39,9 +39,11 @@ def colerr(Y, R, Z):
 
 
 # orders spanning one block, a block plus one reflector, several blocks with a
-# ragged last block; column counts below, at and above the 64-column tile
-@pytest.mark.parametrize("n,m", [(2, 3), (3, 1), (64, 64), (65, 65), (66, 10), (130, 200), (300, 300),
-                                 (1000, 257)])
+# ragged last block, two full blocks as one pair with no rows below it (129),
+# a pair and a lone first block (193), two pairs (257); column counts below,
+# at and above the 64-column tile
+@pytest.mark.parametrize("n,m", [(2, 3), (3, 1), (64, 64), (65, 65), (66, 10), (129, 70), (130, 200), (193, 64),
+                                 (257, 129), (300, 300), (1000, 257)])
 def test_backtransform_vs_oracle(M, n, m):
     V, tau = W.reflectors(n, 9000 + n, fill=np.nan)  # unreferenced entries are NaN
     rng = np.random.default_rng(n * 7 + m)
