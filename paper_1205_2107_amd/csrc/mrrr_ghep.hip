@@ -10,10 +10,10 @@
 // All three are blocked in 64 x 64 tiles: a triangular solve with one
 // diagonal block of L, one RHS vector per lane, the block staged in LDS
 // (k_trsm_tile), and updates of everything below (or above) it on FP64
-// matrix cores (k_gemm_sub; the triangular solves take four diagonal blocks
-// per step, so the large updates are of rank 256).  The Cholesky
-// factorization adds the factorization of its diagonal blocks (k_chol_diag,
-// one wavefront) and rank-64 trailing updates.
+// matrix cores (k_gemm_sub; the triangular solves and the Cholesky
+// factorization work in panels of four tiles, so the large updates are of
+// rank 256).  The Cholesky factorization adds the factorization of its
+// diagonal blocks (k_chol_diag, one wavefront).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -419,19 +419,39 @@ int mrrr_cholesky(int64_t n, double* B, int64_t ldb, int64_t* info, void* stream
   }
   mrrr::ProfEvents prof(st);
   prof.begin(MRRR_K_GHEP);
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    const int kb = (int)std::min<int64_t>(NB, n - k0);
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, B + k0 + k0 * ldb, ldb, kb, k0, fail);
-    const int64_t below = n - k0 - kb;
-    if (below <= 0) break;
-    double* X = B + (k0 + kb) + k0 * ldb;  // the panel below the diagonal block
-    // X L_kk^T = A21, row by row: L_kk x^T = a^T (forward)
-    hipLaunchKernelGGL((k_trsm_tile<true, false>), dim3(tiles(below)), dim3(64), 0, st,
-                       (const double*)(B + k0 + k0 * ldb), ldb, kb, X, ldb, below, (const int*)fail);
-    const int64_t T = tiles(below);
-    hipLaunchKernelGGL((k_gemm_sub<false, true, true>), dim3((unsigned)(T * (T + 1) / 2)), dim3(NT), 0, st, below,
-                       below, kb, (const double*)X, ldb, (const double*)X, ldb, B + (k0 + kb) + (k0 + kb) * ldb, ldb,
-                       (const int*)fail);
+  // panels of kPanel tile columns: each tile column is first brought up to
+  // date by the panel's earlier columns (its diagonal tile's lower triangle
+  // and the rows below), then factored and solved; the trailing matrix takes
+  // one update of rank 64 kPanel per panel
+  for (int64_t k0 = 0; k0 < n; k0 += kPanel * NB) {
+    const int64_t kend = std::min<int64_t>(n, k0 + kPanel * NB);
+    for (int64_t t0 = k0; t0 < kend; t0 += NB) {
+      const int kb = (int)std::min<int64_t>(NB, n - t0);
+      const int64_t below = n - t0 - kb;
+      if (t0 > k0) {
+        const int kk = (int)(t0 - k0);
+        const double* Pt = B + t0 + k0 * ldb;  // rows t0 .. t0 + kb of the panel's earlier columns
+        hipLaunchKernelGGL((k_gemm_sub<false, true, true>), dim3(1), dim3(NT), 0, st, (int64_t)kb, (int64_t)kb, kk,
+                           Pt, ldb, Pt, ldb, B + t0 + t0 * ldb, ldb, (const int*)fail);
+        if (below > 0)
+          hipLaunchKernelGGL((k_gemm_sub<false, true, false>), dim3(1, tiles(below)), dim3(NT), 0, st, below,
+                             (int64_t)kb, kk, (const double*)(B + (t0 + kb) + k0 * ldb), ldb, Pt, ldb,
+                             B + (t0 + kb) + t0 * ldb, ldb, (const int*)fail);
+      }
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, B + t0 + t0 * ldb, ldb, kb, t0, fail);
+      if (below > 0)
+        // X L_tt^T = A21, row by row: L_tt x^T = a^T (forward)
+        hipLaunchKernelGGL((k_trsm_tile<true, false>), dim3(tiles(below)), dim3(64), 0, st,
+                           (const double*)(B + t0 + t0 * ldb), ldb, kb, B + (t0 + kb) + t0 * ldb, ldb, below,
+                           (const int*)fail);
+    }
+    const int64_t below = n - kend;
+    if (below > 0) {
+      const double* X = B + kend + k0 * ldb;  // the panel's rows below it
+      const int64_t T = tiles(below);
+      hipLaunchKernelGGL((k_gemm_sub<false, true, true>), dim3((unsigned)(T * (T + 1) / 2)), dim3(NT), 0, st, below,
+                         below, (int)(kend - k0), X, ldb, X, ldb, B + kend + kend * ldb, ldb, (const int*)fail);
+    }
   }
   prof.end();
   int f = 0;
