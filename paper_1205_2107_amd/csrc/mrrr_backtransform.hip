@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_bt_wsum(int64_t m, const double* __restr
 // W = T X for X = [V0 V1]^T Z is W1 = T1 X1 and W0 = T0 (X0 - C W1).
 // X = the sum of the chunks of the two-block partial products (P_s 128 x m,
 // ld 128); W is 128 x m (ld 128).  32 columns per workgroup, eight threads a
-// column, each 16 rows of a half.
+// column.
 __global__ void __launch_bounds__(NT) k_bt_wsum2(int64_t m, const double* __restrict__ Tws, int b, int nchunk,
                                                  const double* __restrict__ P, const double* __restrict__ Cws,
                                                  double* __restrict__ W) {
@@ -249,34 +249,26 @@ __global__ void __launch_bounds__(NT) k_bt_wsum2(int64_t m, const double* __rest
   const double* T0 = Tws + (int64_t)b * NB * NB;
   const double* T1 = Tws + (int64_t)(b + 1) * NB * NB;
   const double* C = Cws + (int64_t)b * NB * NB;
-  const int oc = t >> 3, part = t & 7;
+  // eight threads a column, each eight rows of every step
+  const int oc = t >> 3, r0 = (t & 7) * 8;
   const int64_t cz = c0 + oc;
-  if (part >= 4) {  // W1 = T1 X1
-    const int r0 = (part - 4) * 16;
-    for (int i = r0; i < r0 + 16; ++i) {
-      double x = 0.0;
-      for (int k = i; k < NB; ++k) x += T1[i * NB + k] * Xs[NB + k][oc];
-      W1s[i][oc] = x;
-      if (cz < m) W[cz * 2 * NB + NB + i] = x;
-    }
+  for (int i = r0; i < r0 + 8; ++i) {  // W1 = T1 X1
+    double x = 0.0;
+    for (int k = i; k < NB; ++k) x += T1[i * NB + k] * Xs[NB + k][oc];
+    W1s[i][oc] = x;
+    if (cz < m) W[cz * 2 * NB + NB + i] = x;
   }
   __syncthreads();
-  if (part < 4) {  // X0 - C W1
-    const int r0 = part * 16;
-    for (int i = r0; i < r0 + 16; ++i) {
-      double x = Xs[i][oc];
-      for (int k = 0; k < NB; ++k) x -= C[i * NB + k] * W1s[k][oc];
-      Xs[i][oc] = x;
-    }
+  for (int i = r0; i < r0 + 8; ++i) {  // X0 - C W1
+    double x = Xs[i][oc];
+    for (int k = 0; k < NB; ++k) x -= C[i * NB + k] * W1s[k][oc];
+    Xs[i][oc] = x;
   }
   __syncthreads();
-  if (part < 4) {  // W0 = T0 (X0 - C W1)
-    const int r0 = part * 16;
-    for (int i = r0; i < r0 + 16; ++i) {
-      double x = 0.0;
-      for (int k = i; k < NB; ++k) x += T0[i * NB + k] * Xs[k][oc];
-      if (cz < m) W[cz * 2 * NB + i] = x;
-    }
+  for (int i = r0; i < r0 + 8; ++i) {  // W0 = T0 (X0 - C W1)
+    double x = 0.0;
+    for (int k = i; k < NB; ++k) x += T0[i * NB + k] * Xs[k][oc];
+    if (cz < m) W[cz * 2 * NB + i] = x;
   }
 }
 
