@@ -192,8 +192,9 @@ def roofline(prof):
     return out
 
 
-def batched_leg(torch, M, count, loop_count):
+def batched_leg(torch, M, count, loop_count, mark=False):
     from paper_1205_2107_amd import workloads as W
+    flag = torch.empty(1, dtype=torch.uint8, device="cuda")
     probs = W.batched_mix(count, W.SEEDS["c4"])
     d, e, ns, off = W.pack(probs)
     dt = torch.tensor(d, device="cuda")
@@ -204,11 +205,17 @@ def batched_leg(torch, M, count, loop_count):
     M.eigh_tridiagonal_batched(dt, et, ns)  # warm-up
     torch.cuda.synchronize()
     reps = 3
+    if mark:
+        flag.fill_(1)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         M.eigh_tridiagonal_batched(dt, et, ns)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    if mark:
+        flag.fill_(2)
+        torch.cuda.synchronize()
     # loop of single-problem calls over the first loop_count problems of the same mix
     singles = [(torch.tensor(p[0], device="cuda"), torch.tensor(p[1], device="cuda")) for p in probs[:loop_count]]
     for a, b in singles[:8]:
@@ -461,6 +468,9 @@ def main():
                     help="only the reduction leg (for a profiler run); prints its JSON")
     ap.add_argument("--only-backtransform", action="store_true",
                     help="only the back-transformation leg (for a profiler run); prints its JSON")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only the batched leg, its timed calls between two one-byte fill kernels "
+                         "that mark them in a kernel trace; prints its JSON")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--looped-count", type=int, default=512)
     ap.add_argument("--profile-once", action="store_true",
@@ -493,6 +503,11 @@ def main():
     if args.only_backtransform:
         log("[bench] back-transformation leg only")
         print(json.dumps({"backtransform": backtransform_leg(torch, M, n)}), flush=True)
+        return
+    if args.only_batched:
+        log("[bench] batched leg only")
+        print(json.dumps({"batched": batched_leg(torch, M, args.batched_count, args.looped_count, mark=True)}),
+              flush=True)
         return
     if args.copy_calib:
         src = torch.ones(args.copy_calib // 8, dtype=torch.float64, device="cuda")
