@@ -1452,7 +1452,12 @@ __device__ __forceinline__ double xstep_bf(double b, double f, double LD, double
   double xn = q - lam;
   if (kMayGuard) {
     const double t0 = f * rc;
-    const double t = fma(rc, fma(-den, t0, f), t0);
+    const double tc = fma(rc, fma(-den, t0, f), t0);
+    // the quotient's correction is NaN where the ratio is infinite (a pivot
+    // of -pivmin under a large f) and where b + x is infinite (rc is NaN):
+    // the uncorrected ratio there, and a vanishing one for an infinite
+    // b + x, so the transform goes on past a zero pivot
+    const double t = (tc == tc) ? tc : (isinf(den) ? 0.0 : t0);
     // one rounding in every inlining context (no contraction left to the compiler)
     const double xs = (t == 0.0) ? f - lam : fma(x, t, -lam);
     xn = guard ? xs : xn;

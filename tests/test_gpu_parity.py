@@ -390,6 +390,23 @@ def test_mid_size_n8000(M, kind):
         assert lo - tol <= wn[j - 1] <= hi + tol
 
 
+@pytest.mark.parametrize("n,seed", [(94, 0), (430, 1), (661, 0), (661, 2), (1354, 1)])
+def test_glued_last_block_of_ten_rows(M, n, seed):
+    # glued W21+ blocks whose last block is the leading 10 x 10 part of W21+:
+    # one eigenvector of the cluster near 0.2538 peaks at the last row, and
+    # the child representation of that cluster has a zero pivot in the middle
+    # row of every block, so the twisted factorizations pass it in the
+    # guarded form; every gamma below it must stay finite for the twist
+    # search to reach the last row (regression: two equal eigenvectors)
+    d, e = W.glued_wilkinson(n, seed)
+    w, Z, info = gpu_solve(M, d, e)
+    assert info["status"] == 0
+    assert np.abs(Z.T @ Z - np.eye(n)).max() / (n * EPS) <= 10
+    assert residual_ratio(d, e, w, Z) <= 10
+    wo, _, _ = oracle.mrrr(d, e, vectors=False)
+    assert np.abs(w - wo).max() <= eig_tol(d, e)
+
+
 def test_full_size_c3_glued_subset(M):
     n = 60000
     d, e = W.glued_wilkinson(n, W.SEEDS["c3"])
@@ -558,18 +575,11 @@ def test_batched_full_benchmark_batch(bench_batch):
             assert lo - tol <= w[j - 1] <= hi + tol, (b, nb, p[2], j)
 
 
-# Known limit: glued Wilkinson W21+ matrices hold, besides the pairs, a
-# cluster of one eigenvalue (about 0.2538) per block that the leading 10 x 10
-# part of every block shares, so every child shift near that cluster has
-# element growth of about 1e13 spdiam (at the blocks' middle rows, where the
-# cluster's eigenvectors vanish); both the oracle and this solver fall back to
-# the candidate of least growth there.  In about one in a hundred of the 840
-# glued members of this batch the computed eigenvectors of such clusters lose
-# orthogonality (above 10 n eps; where a short last block of 10 rows adds a
-# vector peaked at the last row, two vectors can coincide), while the oracle
-# stays below 1 n eps on the same matrices.
-@pytest.mark.xfail(reason="known limit: glued Wilkinson clusters whose child shifts all have large element growth",
-                   strict=False)
+# Known limit: in a few glued Wilkinson members the eigenvectors of the
+# clusters of equal pairs (near 7.0040 in the ones seen) lose orthogonality:
+# 44 and 124 n eps in two of the 840 glued members of this batch, where the
+# oracle stays below 1 n eps.  Every other member is below 10 n eps.
+@pytest.mark.xfail(reason="known limit: a few glued Wilkinson clusters of equal pairs above 10 n eps", strict=False)
 def test_batched_full_benchmark_batch_glued_orthogonality(bench_batch):
     probs, ns, off, wbn, infos, ratios = bench_batch
     bad = [(b, int(ns[b]), ratios[b][1]) for b, p in enumerate(probs)
