@@ -405,6 +405,10 @@ def test_glued_last_block_of_ten_rows(M, n, seed):
     assert residual_ratio(d, e, w, Z) <= 10
     wo, _, _ = oracle.mrrr(d, e, vectors=False)
     assert np.abs(w - wo).max() <= eig_tol(d, e)
+    # one vector of the cluster per block (the block's own or the last one)
+    idx = np.where(np.abs(w - 0.25380581709667) < 1e-9)[0]
+    assert len(idx) == (n + 20) // 21
+    assert len(set((np.abs(Z[:, idx]).argmax(axis=0) // 21).tolist())) == len(idx)
 
 
 def test_full_size_c3_glued_subset(M):

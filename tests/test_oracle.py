@@ -275,3 +275,23 @@ def test_oracle_vs_multiprecision(case):
     assert np.abs(w - we).max() <= eig_tol(d, e)
     worst, checked, _ = compare_vectors(d, e, we, Ve, Z)
     assert checked > 0 and worst <= 1.0
+
+
+@pytest.mark.parametrize("n,seed", [(94, 0), (430, 1), (661, 0)])
+def test_glued_last_block_of_ten_rows(n, seed):
+    # glued W21+ blocks ending in the leading 10 x 10 part of W21+: a cluster
+    # of one eigenvalue per block (near 0.2538) that no child shift separates
+    # without element growth of about 1e13 spdiam; eigenvalues against LAPACK,
+    # orthogonality and residual at the 10 n eps bar (no floor), and every
+    # computed vector of that cluster supported on a different block
+    d, e = W.glued_wilkinson(n, seed)
+    w, Z, st = oracle.mrrr(d, e)
+    assert st == 0
+    T = dense(d, e)
+    assert np.abs(w - np.linalg.eigvalsh(T)).max() <= eig_tol(d, e)
+    assert np.abs(Z.T @ Z - np.eye(n)).max() / (n * EPS) <= 10
+    assert np.linalg.norm(T @ Z - Z * w, axis=0).max() / (n * EPS * norm1(d, e)) <= 10
+    idx = np.where(np.abs(w - 0.25380581709667) < 1e-9)[0]
+    assert len(idx) == (n + 20) // 21
+    blocks = np.abs(Z[:, idx]).argmax(axis=0) // 21
+    assert len(set(blocks.tolist())) == len(idx)
